@@ -1,0 +1,443 @@
+"""DH^2 interpolation, recompression and matvec, step by step in FP64.
+
+Follows the paper's Sections 2 and 3.2 in its notation:
+
+* leaf bases   V_tc[i,nu] = int_{T_i} exp(i kappa <x,c>) L_{t,nu}(x) dx      (Section 2)
+* transfers    E_{t'c}[nu',nu] = exp(i kappa <xi_{t'nu'}, c - c'>) L_{t,nu}(xi_{t'nu'}),
+               c' = sd(c)                                                  (eq. (nested_apx))
+* couplings    S_b[nu,mu] = g_c(xi_{t,nu}, xi_{s,mu})                        (Section 2)
+* near field   Galerkin entries of the inadmissible leaves                 (Definition DH^2)
+* basis weights  W_sc = P_sc R_sc: R of a QR of V (leaf) or of the stacked
+                 [R_{t1c1} E_{t1c}; R_{t2c2} E_{t2c}] (inner)               (eq. (basis_weights_def))
+* block weights  omega_b = |R_tc S_b R_sc^*|_F = |G_int restricted to b|_F: blocks are
+                 scaled by 1/omega_b so the truncation error is block-relative (Section 5)
+* total weights  Z_tc = [S_b R_sc^* / omega_b (s in row(t,c)),  E_{tc+} Zhat_{t+c+}^*
+                 (c+ with sd(c+) = c)], Zhat_tc = R factor of a QR of Z_tc^*   (eq. (recomp_weight_full))
+* truncation   SVD of V_tc Zhat_tc^* (leaf) or Vhat_tc Zhat_tc^* with
+               Vhat_tc = [C_{t1c1} E_{t1c}; C_{t2c2} E_{t2c}] (inner); rank k_tc is the
+               smallest with sum_{i>k} sigma_i^2 <= eps^2; Q_tc / F_{t'c} from the left
+               singular vectors; C_tc = Q_tc^* V_tc resp. Qhat^* Vhat          (eq. (C_tc))
+* column basis the same steps applied to G^* (blocks as columns, S_b^*)   (Section 3.1)
+* projection   Stilde_b = C_tc S_b C_{W,sc}^*                               (Lemma 'Projections')
+* matvec       forward transform, coupling, backward transform, near field: the
+               product Y = Gtilde X implied by eq. (vsw) and the nested bases (eq. (nested)).
+
+Every numerical step is a plain numpy expression; numpy.linalg.qr / svd are
+the library factorisations.  No blocking or reordering beyond the paper's.
+"""
+import math
+
+import numpy as np
+
+from .structure import build_structure
+from .quadrature import triangle_data, kernel_gc
+from .chebyshev import box_points, box_lagrange
+from . import cquad
+
+
+def _H(a):
+    return a.conj().T
+
+
+class OracleDH2:
+    """Holds every intermediate of the construction, keyed by cluster /
+    (cluster, direction index) / block index, for inspection by the tests."""
+
+    def __init__(self, V, T, kappa, order, eta, leaf, tol, eta1=10.0, norm="fro",
+                 recompress=True):
+        V = np.asarray(V, dtype=np.float64)
+        T = np.asarray(T, dtype=np.int64)
+        self.kappa = float(kappa)
+        self.m = int(order)
+        self.k = self.m ** 3
+        self.tol = float(tol)
+        self.norm = norm
+        self.st = build_structure(V, T, kappa, eta, leaf, eta1)
+        self.tri = triangle_data(V, T)
+        self.n = T.shape[0]
+        st = self.st
+        nc = len(st.first)
+        self.points = [box_points(st.lo[t], st.hi[t], self.m) for t in range(nc)]
+        self._activity()
+        self._near_field()
+        self._interpolation()
+        self._basis_weights()
+        self._block_weights()
+        if recompress:
+            self._recompress()
+
+    # ------------------------------------------------------------------ structure
+    def dir(self, t, c):
+        return self.st.dirs[self.st.level[t]][c]
+
+    def sd(self, t, c):
+        """Direction of child clusters of t for direction c of t: sd_{level(t)}(c)."""
+        return int(self.st.sd[self.st.level[t]][c])
+
+    def _activity(self):
+        """row(t,c), col(s,c) lists and the (t,c) pairs that need bases.
+
+        A pair (t,c) needs a row basis if row^+(t,c) (row lists of (t,c) and of
+        its ancestors, Section 3.1) is non empty, i.e. it lies in the downward
+        closure (via children and sd) of the pairs with a non empty row(t,c);
+        likewise for columns.  Pairs outside these sets carry rank zero."""
+        st = self.st
+        self.brow = {}
+        self.bcol = {}
+        for b, (t, s, c) in enumerate(st.adm):
+            self.brow.setdefault((t, c), []).append(b)
+            self.bcol.setdefault((s, c), []).append(b)
+        for key in self.brow:
+            self.brow[key].sort(key=lambda b: st.adm[b][1])
+        for key in self.bcol:
+            self.bcol[key].sort(key=lambda b: st.adm[b][0])
+
+        def closure(seed):
+            per = {}
+            for (t, c) in seed:
+                per.setdefault(t, set()).add(c)
+            order = sorted(range(len(st.first)), key=lambda t: st.level[t])
+            for t in order:
+                for c in sorted(per.get(t, ())):
+                    for t1 in st.children[t]:
+                        per.setdefault(t1, set()).add(self.sd(t, c))
+            return {(t, c) for t, cs in per.items() for c in cs}
+
+        self.row_active = closure(self.brow.keys())
+        self.col_active = closure(self.bcol.keys())
+        self.basis_active = self.row_active | self.col_active
+
+    def _by_level(self, pairs, descending=False):
+        lv = self.st.level
+        return sorted(pairs, key=lambda p: ((-lv[p[0]]) if descending else lv[p[0]], p[0], p[1]))
+
+    # ------------------------------------------------------------------ near field
+    def _near_field(self):
+        st = self.st
+        self.N = []
+        for (t, s) in st.near:
+            self.N.append(cquad.near_block(self.tri, st.idx(t), st.idx(s), self.kappa))
+
+    # ------------------------------------------------------------------ interpolation
+    def leaf_basis(self, t, c):
+        """V_tc for a leaf t: Q7 quadrature of the modulated Lagrange polynomials."""
+        st = self.st
+        idx = st.idx(t)
+        x = self.tri["x7"][idx]               # [#t, 7, 3]
+        w = self.tri["w7"][idx]               # [#t, 7]
+        cvec = self.dir(t, c)
+        flat = x.reshape(-1, 3)
+        L = box_lagrange(flat, st.lo[t], st.hi[t], self.m)          # [#t*7, k]
+        phase = np.exp(1j * self.kappa * (flat @ cvec))             # [#t*7]
+        vals = (L * phase[:, None]).reshape(len(idx), 7, self.k)
+        return np.einsum("iq,iqk->ik", w, vals)
+
+    def transfer(self, t1, c):
+        """E_{t1,c} for child t1 of t and direction c of t (eq. (nested_apx))."""
+        st = self.st
+        t = st.parent[t1]
+        c1 = self.sd(t, c)
+        xi1 = self.points[t1]                                        # [k, 3]
+        dvec = self.dir(t, c) - self.dir(t1, c1)
+        L = box_lagrange(xi1, st.lo[t], st.hi[t], self.m)           # [k (nu'), k (nu)]
+        return np.exp(1j * self.kappa * (xi1 @ dvec))[:, None] * L
+
+    def coupling(self, b):
+        """S_b[nu,mu] = g_c(xi_{t,nu}, xi_{s,mu})."""
+        t, s, c = self.st.adm[b]
+        xt = self.points[t]
+        xs = self.points[s]
+        return kernel_gc(xt[:, None, :], xs[None, :, :], self.dir(t, c), self.kappa)
+
+    def _interpolation(self):
+        st = self.st
+        self.Vleaf = {}
+        self.E = {}
+        for (t, c) in self.basis_active:
+            if st.is_leaf(t):
+                self.Vleaf[(t, c)] = self.leaf_basis(t, c)
+            for t1 in st.children[t]:
+                self.E[(t1, c)] = self.transfer(t1, c)
+
+    def expanded_basis(self, t, c, leafmats, transfers):
+        """Expand a nested basis: leaf matrices, X_tc|_{t'} = X_{t'c'} T_{t'c}."""
+        st = self.st
+        if st.is_leaf(t):
+            return leafmats[(t, c)]
+        c1 = self.sd(t, c)
+        return np.vstack([self.expanded_basis(t1, c1, leafmats, transfers) @ transfers[(t1, c)]
+                          for t1 in st.children[t]])
+
+    # ------------------------------------------------------------------ recompression
+    def _basis_weights(self):
+        """R_tc with V_tc = P_tc R_tc, bottom-up (eq. (basis_weights_def))."""
+        st = self.st
+        self.R = {}
+        for (t, c) in self._by_level(self.basis_active, descending=True):
+            if st.is_leaf(t):
+                A = self.Vleaf[(t, c)]
+            else:
+                c1 = self.sd(t, c)
+                A = np.vstack([self.R[(t1, c1)] @ self.E[(t1, c)] for t1 in st.children[t]])
+            self.R[(t, c)] = np.linalg.qr(A, mode="r")
+
+    def _block_weights(self):
+        self.omega = np.empty(len(self.st.adm))
+        for b, (t, s, c) in enumerate(self.st.adm):
+            M = self.R[(t, c)] @ self.coupling(b) @ _H(self.R[(s, c)])
+            self.omega[b] = np.linalg.norm(M, "fro") if self.norm == "fro" else np.linalg.norm(M, 2)
+
+    def _total_weights(self, lists, active, adjoint):
+        """Zhat for every active pair, top-down (Section 3.2).
+
+        Rows: block contributions S_b R_sc^* / omega_b.  Columns (adjoint
+        matrix G^*): S_b^* R_tc^* / omega_b.  Inherited: E_{tc+} Zhat_{t+c+}^*."""
+        st = self.st
+        Z = {}
+        for (t, c) in self._by_level(active):
+            pieces = []
+            for b in lists.get((t, c), []):
+                if self.omega[b] == 0.0:
+                    continue
+                tb, sb, _ = st.adm[b]
+                S = self.coupling(b) / self.omega[b]
+                if not adjoint:
+                    pieces.append(S @ _H(self.R[(sb, c)]))
+                else:
+                    pieces.append(_H(S) @ _H(self.R[(tb, c)]))
+            tp = st.parent[t]
+            if tp >= 0:
+                lp = st.level[tp]
+                for cp in range(len(st.dirs[lp])):
+                    if int(st.sd[lp][cp]) == c and (tp, cp) in Z:
+                        pieces.append(self.E[(t, cp)] @ _H(Z[(tp, cp)]))
+            if pieces:
+                Zt = np.hstack(pieces)                   # k x M
+                Z[(t, c)] = np.linalg.qr(_H(Zt), mode="r")
+            else:
+                Z[(t, c)] = np.zeros((0, self.k), dtype=np.complex128)
+        return Z
+
+    def rank_rule(self, sig):
+        """Smallest k' with sum_{i>k'} sigma_i^2 <= eps^2 (Frobenius), or
+        sigma_{k'+1} <= eps (spectral)."""
+        eps = self.tol
+        if self.norm == "fro":
+            tail = 0.0
+            kk = len(sig)
+            for i in range(len(sig) - 1, -1, -1):
+                tail += sig[i] * sig[i]
+                if tail <= eps * eps:
+                    kk = i
+                else:
+                    break
+            return kk
+        kk = len(sig)
+        while kk > 0 and sig[kk - 1] <= eps:
+            kk -= 1
+        return kk
+
+    def _truncate(self, Z, active):
+        """New basis Q (leaves) / F (transfers), ranks and C = Q^* V, bottom-up."""
+        st = self.st
+        Q, F, C, rank, sig = {}, {}, {}, {}, {}
+        for (t, c) in self._by_level(active, descending=True):
+            if st.is_leaf(t):
+                Vh = self.Vleaf[(t, c)]
+            else:
+                c1 = self.sd(t, c)
+                Vh = np.vstack([C[(t1, c1)] @ self.E[(t1, c)] for t1 in st.children[t]])
+            A = Vh @ _H(Z[(t, c)])
+            if A.shape[0] == 0 or A.shape[1] == 0:
+                U = np.zeros((A.shape[0], 0), dtype=np.complex128)
+                s = np.zeros(0)
+            else:
+                U, s, _ = np.linalg.svd(A, full_matrices=False)
+            kk = self.rank_rule(s)
+            Qh = U[:, :kk]
+            sig[(t, c)] = s
+            rank[(t, c)] = kk
+            if st.is_leaf(t):
+                Q[(t, c)] = Qh
+            else:
+                c1 = self.sd(t, c)
+                off = 0
+                for t1 in st.children[t]:
+                    k1 = rank[(t1, c1)]
+                    F[(t1, c)] = Qh[off:off + k1, :]
+                    off += k1
+            C[(t, c)] = _H(Qh) @ Vh
+        return Q, F, C, rank, sig
+
+    def _recompress(self):
+        self.Zrow = self._total_weights(self.brow, self.row_active, adjoint=False)
+        self.Zcol = self._total_weights(self.bcol, self.col_active, adjoint=True)
+        (self.Q, self.F, self.C, self.rank, self.sig) = self._truncate(self.Zrow, self.row_active)
+        (self.QW, self.FW, self.CW, self.rankW, self.sigW) = self._truncate(self.Zcol, self.col_active)
+        self.St = []
+        for b, (t, s, c) in enumerate(self.st.adm):
+            self.St.append(self.C[(t, c)] @ self.coupling(b) @ _H(self.CW[(s, c)]))
+
+    # ------------------------------------------------------------------ matvec
+    def matvec(self, X):
+        """Y = Gtilde X with forward / coupling / backward / near-field phases.
+        X is [n, nrhs] (or [n]) in the caller's triangle order."""
+        st = self.st
+        X = np.asarray(X, dtype=np.complex128)
+        vec = X.ndim == 1
+        if vec:
+            X = X[:, None]
+        Y = np.zeros_like(X)
+        xh = {}
+        for (s, c) in self._by_level(self.col_active, descending=True):
+            if st.is_leaf(s):
+                xh[(s, c)] = _H(self.QW[(s, c)]) @ X[st.idx(s)]
+            else:
+                c1 = self.sd(s, c)
+                acc = np.zeros((self.rankW[(s, c)], X.shape[1]), dtype=np.complex128)
+                for s1 in st.children[s]:
+                    acc += _H(self.FW[(s1, c)]) @ xh[(s1, c1)]
+                xh[(s, c)] = acc
+        yh = {p: np.zeros((self.rank[p], X.shape[1]), dtype=np.complex128)
+              for p in self.row_active}
+        for b, (t, s, c) in enumerate(st.adm):
+            yh[(t, c)] += self.St[b] @ xh[(s, c)]
+        for (t, c) in self._by_level(self.row_active):
+            if st.is_leaf(t):
+                Y[st.idx(t)] += self.Q[(t, c)] @ yh[(t, c)]
+            else:
+                c1 = self.sd(t, c)
+                for t1 in st.children[t]:
+                    yh[(t1, c1)] += self.F[(t1, c)] @ yh[(t, c)]
+        self._near_apply(X, Y)
+        return Y[:, 0] if vec else Y
+
+    def _near_apply(self, X, Y):
+        st = self.st
+        for i, (t, s) in enumerate(st.near):
+            Y[st.idx(t)] += self.N[i] @ X[st.idx(s)]
+
+    def matvec_expanded(self, X):
+        """Y = Gtilde X from the plain definition: per admissible block
+        Q_tc Stilde_b Q_{W,sc}^* with the bases expanded through F."""
+        st = self.st
+        X = np.asarray(X, dtype=np.complex128)
+        vec = X.ndim == 1
+        if vec:
+            X = X[:, None]
+        Y = np.zeros_like(X)
+        for b, (t, s, c) in enumerate(st.adm):
+            Qt = self.expanded_basis(t, c, self.Q, self.F)
+            Qs = self.expanded_basis(s, c, self.QW, self.FW)
+            Y[st.idx(t)] += Qt @ (self.St[b] @ (_H(Qs) @ X[st.idx(s)]))
+        self._near_apply(X, Y)
+        return Y[:, 0] if vec else Y
+
+    def matvec_interp(self, X, adjoint=False):
+        """Y = G_int X (or G_int^* X): the uncompressed interpolated DH^2 matrix."""
+        st = self.st
+        X = np.asarray(X, dtype=np.complex128)
+        vec = X.ndim == 1
+        if vec:
+            X = X[:, None]
+        Y = np.zeros_like(X)
+        for b, (t, s, c) in enumerate(st.adm):
+            Vt = self.expanded_basis(t, c, self.Vleaf, self.E)
+            Vs = self.expanded_basis(s, c, self.Vleaf, self.E)
+            S = self.coupling(b)
+            if not adjoint:
+                Y[st.idx(t)] += Vt @ (S @ (_H(Vs) @ X[st.idx(s)]))
+            else:
+                Y[st.idx(s)] += Vs @ (_H(S) @ (_H(Vt) @ X[st.idx(t)]))
+        for i, (t, s) in enumerate(st.near):
+            if not adjoint:
+                Y[st.idx(t)] += self.N[i] @ X[st.idx(s)]
+            else:
+                Y[st.idx(s)] += _H(self.N[i]) @ X[st.idx(t)]
+        return Y[:, 0] if vec else Y
+
+    # ------------------------------------------------------------------ dense forms (tiny n)
+    def dense_compressed(self):
+        st = self.st
+        G = np.zeros((self.n, self.n), dtype=np.complex128)
+        for b, (t, s, c) in enumerate(st.adm):
+            Qt = self.expanded_basis(t, c, self.Q, self.F)
+            Qs = self.expanded_basis(s, c, self.QW, self.FW)
+            G[np.ix_(st.idx(t), st.idx(s))] = Qt @ self.St[b] @ _H(Qs)
+        for i, (t, s) in enumerate(st.near):
+            G[np.ix_(st.idx(t), st.idx(s))] = self.N[i]
+        return G
+
+    def dense_interp(self):
+        st = self.st
+        G = np.zeros((self.n, self.n), dtype=np.complex128)
+        for b, (t, s, c) in enumerate(st.adm):
+            Vt = self.expanded_basis(t, c, self.Vleaf, self.E)
+            Vs = self.expanded_basis(s, c, self.Vleaf, self.E)
+            G[np.ix_(st.idx(t), st.idx(s))] = Vt @ self.coupling(b) @ _H(Vs)
+        for i, (t, s) in enumerate(st.near):
+            G[np.ix_(st.idx(t), st.idx(s))] = self.N[i]
+        return G
+
+    def dense_galerkin(self):
+        """Reference Galerkin matrix: near rule on inadmissible leaves (self term
+        on the diagonal), Q7 x Q7 on admissible leaves."""
+        st = self.st
+        G = np.zeros((self.n, self.n), dtype=np.complex128)
+        for (t, s, c) in st.adm:
+            G[np.ix_(st.idx(t), st.idx(s))] = cquad.far_block(self.tri, st.idx(t), st.idx(s), self.kappa)
+        for i, (t, s) in enumerate(st.near):
+            G[np.ix_(st.idx(t), st.idx(s))] = self.N[i]
+        return G
+
+    def galerkin_rows(self, rows):
+        """Rows of the reference Galerkin matrix (any n): [len(rows), n]."""
+        st = self.st
+        rows = np.asarray(rows, dtype=np.int64)
+        out = np.zeros((len(rows), self.n), dtype=np.complex128)
+        where = {int(i): r for r, i in enumerate(rows)}
+        for (t, s, c) in st.adm:
+            sel = [int(i) for i in st.idx(t) if int(i) in where]
+            if sel:
+                blk = cquad.far_block(self.tri, np.array(sel), st.idx(s), self.kappa)
+                for r, i in enumerate(sel):
+                    out[where[i], st.idx(s)] = blk[r]
+        for (t, s) in st.near:
+            sel = [int(i) for i in st.idx(t) if int(i) in where]
+            if sel:
+                blk = cquad.near_block(self.tri, np.array(sel), st.idx(s), self.kappa)
+                for r, i in enumerate(sel):
+                    out[where[i], st.idx(s)] = blk[r]
+        return out
+
+    # ------------------------------------------------------------------ summaries
+    def storage_kb_per_dof(self):
+        """Original-matrix storage as in the paper's tables: near-field entries
+        plus k^2 per admissible block, 16 bytes each, KB = 1024 bytes."""
+        st = self.st
+        near = sum(int(st.size[t]) * int(st.size[s]) for (t, s) in st.near)
+        return (near + self.k * self.k * len(st.adm)) * 16.0 / 1024.0 / self.n
+
+
+def build_oracle(V, T, kappa, order, eta, leaf, tol, eta1=10.0, norm="fro"):
+    return OracleDH2(V, T, kappa, order, eta, leaf, tol, eta1=eta1, norm=norm)
+
+
+def spectral_norm_power(apply, apply_adj, n, iters=100, seed=1, rtol=1e-6):
+    """|A|_2 by power iteration on A^* A with a seeded complex start vector."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x /= np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = apply_adj(apply(x))
+        nrm = np.linalg.norm(y)
+        if nrm == 0.0:
+            return 0.0
+        new = math.sqrt(nrm)
+        x = y / nrm
+        if lam > 0.0 and abs(new - lam) <= rtol * new:
+            lam = new
+            break
+        lam = new
+    return lam

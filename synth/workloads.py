@@ -1,0 +1,56 @@
+"""Named workloads: mesh recipe plus the method parameters.
+
+kappa  wave number, order m (k = m^3 interpolation points per cluster),
+eta    the admissibility parameter eta_2, eta1 the direction parameter eta_1,
+leaf   the maximal leaf-cluster size, tol the recompression tolerance,
+nrhs   right-hand sides per matvec.
+"""
+from dataclasses import dataclass
+
+from .meshes import sphere_octahedral, cube_surface, ellipsoid_octahedral
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    surface: str          # "sphere" | "cube" | "ellipsoid"
+    q: int                # refinement level (sphere n = 8 q^2, cube n = 12 q^2)
+    kappa: float
+    order: int
+    leaf: int
+    tol: float
+    eta: float = 1.0
+    eta1: float = 10.0
+    nrhs: int = 1
+
+    @property
+    def n(self):
+        return (8 if self.surface in ("sphere", "ellipsoid") else 12) * self.q * self.q
+
+
+def make_mesh(w):
+    if w.surface == "sphere":
+        return sphere_octahedral(w.q)
+    if w.surface == "cube":
+        return cube_surface(w.q)
+    if w.surface == "ellipsoid":
+        return ellipsoid_octahedral(w.q)
+    raise ValueError(w.surface)
+
+
+WORKLOADS = {
+    # plain FP64 case: unit sphere n = 2048, kappa 4, m 4, leaf 32, tol 1e-6
+    "sphere2k": Workload("sphere2k", "sphere", 16, 4.0, 4, 32, 1e-6),
+    # unit sphere n = 32768, kappa 16, m 5, leaf 64, tol 1e-6
+    "sphere32k": Workload("sphere32k", "sphere", 64, 16.0, 5, 64, 1e-6),
+    # unit sphere n = 131072, kappa 32, m 5, leaf 64, tol 1e-4, 16 right-hand sides
+    "sphere131k": Workload("sphere131k", "sphere", 128, 32.0, 5, 64, 1e-4, nrhs=16),
+    # directional stress cases: every admissible block carries a direction c != 0
+    # (small eta1 makes every level directional, larger eta admits blocks early)
+    "dir512": Workload("dir512", "sphere", 8, 6.0, 3, 8, 1e-6, eta=8.0, eta1=1.0),
+    "dir2k": Workload("dir2k", "sphere", 16, 8.0, 3, 16, 1e-6, eta=4.0, eta1=1.0),
+    "dir8k": Workload("dir8k", "sphere", 32, 16.0, 4, 32, 1e-6, eta=4.0, eta1=2.0),
+    # cube [-1,1]^3 (flat cluster boxes on the faces), low frequency and directional
+    "cube768": Workload("cube768", "cube", 8, 4.0, 3, 16, 1e-6, eta=2.0),
+    "cube1200dir": Workload("cube1200dir", "cube", 10, 4.0, 3, 16, 1e-6, eta=4.0, eta1=2.0),
+}
