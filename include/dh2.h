@@ -1,0 +1,202 @@
+/*
+ * dh2.h -- C ABI of the MI355X (gfx950) library for the hybrid directional
+ * H^2-matrix (DH^2) compression of the Helmholtz single-layer Galerkin matrix
+ * (S. Boerm, C. Boerst, "Hybrid matrix compression for high-frequency
+ * problems", arXiv 1809.04384).
+ *
+ * The matrix (Section 1, eq. (matrix)) is G_ij = int_{T_i} int_{T_j} g(x,y)
+ * dy dx for the indicator functions of the triangles T_i of a surface mesh,
+ * with g(x,y) = exp(i kappa |x-y|) / (4 pi |x-y|) (eq. (helmholtz)).
+ * dh2_build constructs a DH^2 approximation by directional Chebyshev
+ * interpolation (Section 2) and recompresses it algebraically (Section 3.2);
+ * dh2_matvec applies the result.
+ *
+ * Conventions
+ *   - complex numbers are interleaved (re, im) pairs of the handle's precision;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *     memory of the device that was current when the handle was built;
+ *   - every function returns a dh2_status; on failure dh2_last_error() gives a
+ *     message (thread-local, valid until the next call on the same thread);
+ *     invalid arguments are detected before any side effect;
+ *   - distinct handles may be used from different threads concurrently; one
+ *     handle must not be used from two threads at the same time.
+ */
+#ifndef DH2_H
+#define DH2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DH2_OK = 0,
+  DH2_ERR_ARG = 1,       /* invalid argument (nothing was changed)            */
+  DH2_ERR_GEOMETRY = 2,  /* index out of range or degenerate (zero-area) triangle */
+  DH2_ERR_OOM = 3,       /* device or host allocation failed                  */
+  DH2_ERR_DEVICE = 4,    /* HIP runtime error (no device, launch failure ...)  */
+  DH2_ERR_NUMERIC = 5    /* non-finite value produced                         */
+} dh2_status;
+
+/* Surface mesh.  Host memory, read during the call only (the library copies
+ * what it needs).  vertices: [n_vertices][3] row-major doubles; triangles:
+ * [n_triangles][3] 0-based vertex indices.  The unknowns are the triangles
+ * (piecewise-constant basis, Section 5), so n = n_triangles. */
+typedef struct {
+  int64_t n_vertices;
+  const double* vertices;
+  int64_t n_triangles;
+  const int32_t* triangles;
+} dh2_geometry;
+
+/* Precision of a handle: arithmetic of the interpolation, couplings, GEMMs and
+ * matvec, and the element type of X / Y.  Householder QR and SVD of the
+ * recompression are always FP64. */
+typedef enum { DH2_FP64 = 0, DH2_FP32 = 1 } dh2_precision;
+
+/* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then
+ * override fields; zero fields take the defaults given here. */
+typedef struct {
+  uint32_t size;
+  int32_t precision;  /* dh2_precision, default DH2_FP64                               */
+  double eta1;        /* direction parameter eta_1 of eq. (admissibility) and of the
+                         Remark on the construction of directions; default 10 (Section 5) */
+  int32_t max_nrhs;   /* largest nrhs dh2_matvec will be called with; the matvec
+                         workspace is reserved at build time.  Default 16.          */
+  int32_t reserved0;
+  void* stream;       /* hipStream_t for all work of this handle; NULL = default stream */
+  double workspace_gb;/* device workspace for the recompression batches; default 8 */
+} dh2_options;
+
+typedef struct dh2_problem* dh2_handle;
+
+/* Build the compressed matrix (synchronous: returns when the representation is
+ * on the device).
+ *   geometry  surface mesh (see dh2_geometry)
+ *   kappa     wave number, >= 0
+ *   order     Chebyshev points per axis m >= 1; interpolation rank k = m^3 (Section 5)
+ *   eta       admissibility parameter eta_2 > 0 of the standard and parabolic
+ *             conditions, eq. (admissibility), second and third line
+ *   leafsize  maximal number of triangles in a leaf cluster, >= 1
+ *   tol       recompression accuracy eps >= 0: per cluster and direction the rank is
+ *             the smallest with sum_{i>k} sigma_i^2 <= eps^2 for the block-normalised
+ *             total-weight matrices (block-relative Frobenius control, Section 5);
+ *             tol = 0 keeps every nonzero singular value
+ *   out       receives the handle; *out is set to NULL on failure
+ * Errors: DH2_ERR_ARG (bad scalar), DH2_ERR_GEOMETRY (index out of range,
+ * zero-area triangle, n < 1), DH2_ERR_OOM, DH2_ERR_DEVICE.  Partial builds are
+ * freed. */
+dh2_status dh2_build(const dh2_geometry* geometry, double kappa, int order, double eta,
+                     int leafsize, double tol, dh2_handle* out);
+
+/* As dh2_build with options (NULL = defaults). */
+dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, double eta,
+                        int leafsize, double tol, const dh2_options* options, dh2_handle* out);
+
+/* Y = Gtilde X, the product with the compressed matrix: forward transform,
+ * coupling, backward transform and near field (the product implied by
+ * eq. (vsw) with the nested bases of eq. (nested)).
+ *   X, Y   device pointers, column-major n x nrhs (leading dimension n),
+ *          interleaved complex of the handle's precision, in the caller's
+ *          triangle order; Y is overwritten; X and Y must not overlap
+ *   nrhs   1 <= nrhs <= max_nrhs of the handle
+ * Enqueued on the handle's stream; returns without synchronising and without
+ * allocating.  Errors: DH2_ERR_ARG (NULL handle or pointer, nrhs out of
+ * range), DH2_ERR_DEVICE (launch failure). */
+dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs);
+
+/* Releases all device and host memory of the handle.  NULL is a no-op. */
+void dh2_free(dh2_handle h);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* dh2_last_error(void);
+
+/* Counts, ranks, storage and timings of a built handle. */
+typedef struct {
+  uint32_t size;            /* set to sizeof(dh2_stats) by the caller */
+  int32_t k;                /* interpolation rank m^3 */
+  int64_t n, n_clusters, n_leaves, depth;
+  int64_t n_adm, n_near;    /* admissible / inadmissible leaves of the block tree */
+  int64_t n_slots, n_row_slots, n_col_slots;  /* (cluster, direction) pairs with bases */
+  int64_t near_entries;     /* sum over inadmissible leaves of #t * #s */
+  int64_t coupling_entries; /* sum over admissible leaves of k_tc * k_W,sc after recompression */
+  int64_t basis_entries;    /* leaf bases + transfer matrices, rows and columns, after recompression */
+  int32_t rank_max_row, rank_max_col;
+  double rank_mean_row, rank_mean_col;
+  double matvec_bytes;      /* algorithmic bytes of one matvec with nrhs = 1 (matrix data read once) */
+  double matvec_bytes_per_rhs; /* additional algorithmic bytes per right-hand side */
+  double ms_structure, ms_near, ms_interp, ms_basis_weights, ms_block_weights,
+      ms_total_weights, ms_truncation, ms_projection, ms_total;
+} dh2_stats;
+
+dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);
+
+/* ---------------------------------------------------------------------------
+ * Host-only hierarchy (no GPU needed): cluster tree, directions and block tree
+ * exactly as dh2_build constructs them (Section 2: Definitions 'cluster tree',
+ * 'directions', 'block tree', Remark 'construction of directions').  Used to
+ * inspect and test the structure. */
+typedef struct dh2_plan_s* dh2_plan;
+
+typedef struct {
+  int64_t n, n_clusters, depth, n_adm, n_near, n_dirs_total, n_slots;
+} dh2_plan_sizes;
+
+dh2_status dh2_plan_create(const dh2_geometry* geometry, double kappa, int order, double eta,
+                           int leafsize, double eta1, dh2_plan* out);
+dh2_status dh2_plan_get_sizes(dh2_plan p, dh2_plan_sizes* s);
+/* Copies the hierarchy into caller-owned host arrays (any may be NULL):
+ *   perm[n]                 cluster order -> triangle index
+ *   cl_first[nc], cl_size[nc], cl_level[nc], cl_parent[nc] (-1 for the root)
+ *   cl_box[nc][6]           lo_x, lo_y, lo_z, hi_x, hi_y, hi_z of the vertex box
+ *   level_ndirs[depth+1]    #D_l (1 for D_l = {0})
+ *   dirs[n_dirs_total][3]   directions of all levels, level after level
+ *   sd[n_dirs_total]        son direction index in D_{l+1} (-1 on the last level)
+ *   adm[n_adm][3]           (t, s, direction index) in block-recursion order
+ *   near[n_near][2]         (t, s) in block-recursion order
+ *   slots[n_slots][3]       (t, direction index, flags: 1 = row basis, 2 = column basis) */
+dh2_status dh2_plan_export(dh2_plan p, int64_t* perm, int64_t* cl_first, int64_t* cl_size,
+                           int32_t* cl_level, int64_t* cl_parent, double* cl_box,
+                           int32_t* level_ndirs, double* dirs, int32_t* sd, int64_t* adm,
+                           int64_t* near, int64_t* slots);
+void dh2_plan_free(dh2_plan p);
+
+/* ---------------------------------------------------------------------------
+ * Inspection of a built handle (tests): copies one intermediate matrix to a
+ * caller-owned host buffer of complex doubles, column-major.  Call with
+ * out = NULL to query rows / cols.  FP32 handles are widened to FP64.
+ *   what = DH2_INSPECT_NEAR        index = inadmissible leaf (recursion order): #t x #s block
+ *          DH2_INSPECT_LEAF_BASIS  index = slot of a leaf cluster: V_tc, #t x k (Section 2)
+ *          DH2_INSPECT_TRANSFER    index = 2*slot + child: E_{t'c}, k x k (eq. (nested_apx))
+ *          DH2_INSPECT_RANK_ROW    index ignored: k_tc of every slot (-1 if no row basis), n_slots x 1
+ *          DH2_INSPECT_RANK_COL    same for the column basis
+ *          DH2_INSPECT_SIGMA_ROW   index = slot: singular values of the truncation step
+ *          DH2_INSPECT_SIGMA_COL   same for the column pass
+ *          DH2_INSPECT_OMEGA       index ignored: block weights |G_int restricted to b|_F, n_adm x 1
+ *          DH2_INSPECT_BASIS_WEIGHT      index = slot: R_tc with V_tc = P_tc R_tc (eq. (basis_weights_def))
+ *          DH2_INSPECT_TOTAL_WEIGHT_ROW  index = slot: Zhat_tc of the row pass (eq. (recomp_weight_full))
+ *          DH2_INSPECT_TOTAL_WEIGHT_COL  index = slot: Zhat of the column pass (adjoint matrix)
+ *          DH2_INSPECT_COUPLING    index = admissible leaf: S_b = (g_c(xi_t,nu, xi_s,mu)), k x k
+ * Real-valued results are returned in the real parts. */
+enum {
+  DH2_INSPECT_NEAR = 1,
+  DH2_INSPECT_LEAF_BASIS = 2,
+  DH2_INSPECT_TRANSFER = 3,
+  DH2_INSPECT_RANK_ROW = 4,
+  DH2_INSPECT_RANK_COL = 5,
+  DH2_INSPECT_SIGMA_ROW = 6,
+  DH2_INSPECT_SIGMA_COL = 7,
+  DH2_INSPECT_OMEGA = 8,
+  DH2_INSPECT_BASIS_WEIGHT = 9,
+  DH2_INSPECT_TOTAL_WEIGHT_ROW = 10,
+  DH2_INSPECT_TOTAL_WEIGHT_COL = 11,
+  DH2_INSPECT_COUPLING = 12
+};
+dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64_t* rows,
+                       int64_t* cols);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DH2_H */

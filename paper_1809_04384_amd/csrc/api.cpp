@@ -1,0 +1,1549 @@
+// C ABI (include/dh2.h) and host orchestration of the DH^2 build and matvec.
+//
+// Build phases (Boerm & Boerst, arXiv 1809.04384):
+//   structure      cluster tree, directions, block tree           (Section 2; plan.cpp)
+//   near field     dense inadmissible leaves                       (Definition of DH^2 matrices)
+//   interpolation  leaf bases V_tc and transfers E_{t'c}           (Section 2, eq. (nested_apx))
+//   basis weights  R_tc with V_tc = P_tc R_tc, bottom-up           (eq. (basis_weights_def))
+//   block weights  omega_b = |R_tc S_b R_sc^*|_F                   (block-relative error control, Section 5)
+//   total weights  Zhat_tc, top-down, rows and columns             (eq. (recomp_weight_full))
+//   truncation     SVD -> Q_tc / F_{t'c}, ranks, C_tc, bottom-up   (Section 3.2, eq. (C_tc))
+//   projection     Stilde_b = C_tc S_b C_{W,sc}^*                  (Lemma 'Projections')
+// The couplings S_b are never stored: they are regenerated on the device in
+// batches wherever a phase needs them.  All device work runs on the handle's
+// stream; the host only builds descriptor lists and reads back the ranks of
+// each level (they size the next level's products).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dh2.h"
+#include "kernels.hpp"
+#include "matvec.hpp"
+#include "plan.hpp"
+
+using namespace dh2;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+  dh2_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw Fail{e_ == hipErrorOutOfMemory ? DH2_ERR_OOM : DH2_ERR_DEVICE,               \
+                 std::string(#x) + " failed: " + hipGetErrorString(e_)};                 \
+  } while (0)
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Gauss-Legendre nodes/weights on [0,1] by Newton iteration on P_n.
+void gauss_legendre01(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2) P'^2) on [-1,1], halved
+  }
+}
+
+QuadTab make_quad() {
+  QuadTab q{};
+  // 7-point rule of Radon (degree 5): centroid and two orbits (a,a,1-2a)
+  const double s15 = std::sqrt(15.0);
+  const double a = (6.0 - s15) / 21.0, b = (6.0 + s15) / 21.0;
+  const double wa = (155.0 - s15) / 1200.0, wb = (155.0 + s15) / 1200.0;
+  const double pts[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a, a, 1 - 2 * a}, {a, 1 - 2 * a, a},
+                            {1 - 2 * a, a, a},         {b, b, 1 - 2 * b}, {b, 1 - 2 * b, b},
+                            {1 - 2 * b, b, b}};
+  const double ws[7] = {9.0 / 40.0, wa, wa, wa, wb, wb, wb};
+  for (int i = 0; i < 7; ++i) {
+    for (int d = 0; d < 3; ++d) q.b7[i][d] = pts[i][d];
+    q.w7[i] = ws[i];
+  }
+  // 16-point rule: 4 x 4 Gauss-Legendre on the square, Duffy-collapsed
+  double u[4], wu[4];
+  gauss_legendre01(4, u, wu);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * i + j;
+      q.b16[k][0] = 1.0 - u[i];
+      q.b16[k][1] = u[i] * (1.0 - u[j]);
+      q.b16[k][2] = u[i] * u[j];
+      q.w16[k] = 2.0 * wu[i] * wu[j] * u[i];
+    }
+  return q;
+}
+
+ChebTab make_cheb(int m) {
+  ChebTab c{};
+  c.m = m;
+  for (int j = 0; j < m; ++j) c.node[j] = std::cos((2 * j + 1) * M_PI / (2.0 * m));
+  for (int j = 0; j < m; ++j) {
+    double den = 1.0;
+    for (int l = 0; l < m; ++l)
+      if (l != j) den *= (c.node[j] - c.node[l]);
+    c.inv_den[j] = 1.0 / den;
+  }
+  return c;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct dh2_plan_s {
+  Plan plan;
+};
+
+struct dh2_problem {
+  Plan plan;
+  int precision = DH2_FP64;
+  hipStream_t stream = nullptr;
+  int max_nrhs = 16;
+  double tol = 0;
+  int norm_mode = 0;
+  int device = 0;
+  size_t ws_bytes = 0;
+  std::vector<void*> allocs;
+  dh2_stats stats{};
+
+  // device data kept after the build
+  int64_t* perm_d = nullptr;
+  double* box_d = nullptr;
+  double* dirs_d = nullptr;
+  std::vector<int64_t> dir_off;        // first global direction index of each level
+  void* near_d = nullptr;              // near-field blocks
+  std::vector<int64_t> near_off;
+  void* V_d = nullptr;                 // leaf bases (FP64)
+  std::vector<int64_t> V_off;          // per slot (-1 if none)
+  void* E_d = nullptr;                 // transfers (FP64), per slot 2 k x k
+  std::vector<int64_t> E_off;
+  std::vector<int32_t> rank_row, rank_col;  // -1 if not in the set
+  std::vector<std::vector<double>> sig_row, sig_col;
+  std::vector<double> omega;
+  z64* R_d = nullptr;                  // basis weights, per slot k x k (rows rR)
+  z64* Zr_d = nullptr;                 // total weights (rows, columns), per slot k x k
+  z64* Zc_d = nullptr;
+  std::vector<int32_t> rR, rZr, rZc;
+  ChebTab cheb{};
+  // compressed representation
+  std::vector<z64*> Qr_ptr, Qc_ptr;   // Qhat per slot (m x rank, column-major)
+  std::vector<int32_t> Qr_m, Qc_m;
+  void* St_d = nullptr;  std::vector<int64_t> St_off;
+  // matvec schedule
+  void* Xp_d = nullptr; void* Yp_d = nullptr; void* xh_d = nullptr; void* yh_d = nullptr;
+  MvOut* mv_outs_d = nullptr; MvTerm* mv_terms_d = nullptr;
+  struct Phase { int64_t out_begin, out_end; };
+  std::vector<Phase> mv_phases;
+
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    HIPCHK(hipMalloc(&p, count * sizeof(T)));
+    allocs.push_back(p);
+    return (T*)p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+      hipFree(p);
+      allocs.erase(it);
+    }
+  }
+  // host bytes of pending asynchronous uploads, kept alive until the next sync()
+  std::vector<std::vector<char>> pending_host;
+
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) {
+      pending_host.emplace_back((const char*)v.data(), (const char*)v.data() + v.size() * sizeof(T));
+      HIPCHK(hipMemcpyAsync(p, pending_host.back().data(), v.size() * sizeof(T),
+                            hipMemcpyHostToDevice, stream));
+    }
+    return p;
+  }
+  ~dh2_problem() {
+    if (stream) hipStreamSynchronize(stream);
+    else hipDeviceSynchronize();
+    for (void* p : allocs) hipFree(p);
+  }
+  void sync() {
+    HIPCHK(hipStreamSynchronize(stream));
+    pending_host.clear();
+  }
+  void check_launch() { HIPCHK(hipGetLastError()); }
+};
+
+namespace {
+
+typedef z64 C64;
+
+// slot-level bookkeeping used during the build
+struct SlotInfo {
+  int64_t t;
+  int32_t c, level;
+  bool leaf;
+  int64_t child_slot[2] = {-1, -1};
+  int32_t nrows;              // #t
+  int64_t row0;               // first cluster-order position
+};
+
+struct Builder {
+  dh2_problem& h;
+  Plan& p;
+  int k;
+  int64_t ns;
+  ChebTab ct;
+  std::vector<SlotInfo> si;
+  std::vector<int32_t> rR;                 // rows of R per slot
+  C64* R_d = nullptr;                      // per slot k x k
+  C64* Zr_d = nullptr;                     // per slot k x k (row pass)
+  C64* Zc_d = nullptr;                     // per slot k x k (column pass)
+  std::vector<int32_t> rZr, rZc;
+  std::vector<C64*> Cr_ptr, Cc_ptr;                    // C_tc rank x k per slot
+  std::vector<void*> keep_rc;                          // their allocations (freed after the build)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t* cnt_d = nullptr;                            // per slot: rows of a compacted fold
+
+  // read the compacted row counts of the given slots
+  void read_counts(const std::vector<int64_t>& qs, std::vector<int32_t>& dst) {
+    h.sync();
+    if (qs.empty()) return;
+    std::vector<int32_t> all(ns);
+    HIPCHK(hipMemcpy(all.data(), cnt_d, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t q : qs) dst[q] = all[q];
+  }
+  std::vector<int64_t> slot_by_level_begin;            // slots sorted by level
+
+  Builder(dh2_problem& hh) : h(hh), p(hh.plan) {}
+
+  C64* Rp(int64_t q) { return R_d + (size_t)q * k * k; }
+  C64* Zp(bool row, int64_t q) { return (row ? Zr_d : Zc_d) + (size_t)q * k * k; }
+  int64_t gdir(int64_t t, int32_t c) { return h.dir_off[p.cl[t].level] + c; }
+  int child_index(int64_t t) {
+    const Cluster& par = p.cl[p.cl[t].parent];
+    return par.child[0] == t ? 0 : 1;
+  }
+  C64* Ep(int64_t parent_slot, int ci) { return (C64*)h.E_d + h.E_off[parent_slot] + (size_t)ci * k * k; }
+
+  template <class T>
+  T* upload_tmp(const std::vector<T>& v, std::vector<void*>& tmp) {
+    T* d = h.upload(v);
+    tmp.push_back(d);
+    return d;
+  }
+  void free_tmp(std::vector<void*>& tmp) {
+    h.sync();
+    for (void* x : tmp) h.release(x);
+    tmp.clear();
+  }
+
+  // ------------------------------------------------------------------
+  void setup_slots() {
+    k = p.k;
+    ns = (int64_t)p.slots.size();
+    ct = make_cheb(p.order);
+    si.resize(ns);
+    for (int64_t q = 0; q < ns; ++q) {
+      const Slot& s = p.slots[q];
+      const Cluster& c = p.cl[s.t];
+      si[q].t = s.t;
+      si[q].c = s.c;
+      si[q].level = c.level;
+      si[q].leaf = c.leaf();
+      si[q].nrows = (int32_t)c.size;
+      si[q].row0 = c.first;
+      if (!c.leaf())
+        for (int i = 0; i < 2; ++i) si[q].child_slot[i] = p.slot_of(c.child[i], p.son_dir(s.t, s.c));
+    }
+  }
+
+  // parents (inherited contributions) of slot q within a set (row or column flags)
+  std::vector<int64_t> parents_of(int64_t q, const std::vector<uint8_t>& flag) {
+    std::vector<int64_t> out;
+    const int64_t t = si[q].t;
+    const int64_t tp = p.cl[t].parent;
+    if (tp < 0) return out;
+    for (const auto& pr : p.cl_slots[tp]) {
+      const int32_t cp = pr.first;
+      if (p.son_dir(tp, cp) == si[q].c && flag[pr.second]) out.push_back(pr.second);
+    }
+    return out;
+  }
+
+  // ------------------------------------------------------------------
+  void interpolation() {
+    // leaf bases
+    std::vector<LeafDesc> ld;
+    h.V_off.assign(ns, -1);
+    int64_t voff = 0;
+    for (int64_t q = 0; q < ns; ++q)
+      if (si[q].leaf) {
+        h.V_off[q] = voff;
+        ld.push_back({si[q].row0, si[q].nrows, (int32_t)si[q].t, gdir(si[q].t, si[q].c), voff});
+        voff += (int64_t)si[q].nrows * k;
+      }
+    h.V_d = h.alloc<C64>(voff);
+    std::vector<void*> tmp;
+    launch_leaf_basis<double>(upload_tmp(ld, tmp), (int64_t)ld.size(), ct, p.kappa, x7, w7, h.box_d,
+                              h.dirs_d, h.V_d, h.stream);
+    h.check_launch();
+    // transfers
+    std::vector<TransDesc> td;
+    h.E_off.assign(ns, -1);
+    int64_t eoff = 0;
+    for (int64_t q = 0; q < ns; ++q)
+      if (!si[q].leaf) {
+        h.E_off[q] = eoff;
+        const Cluster& c = p.cl[si[q].t];
+        for (int i = 0; i < 2; ++i) {
+          td.push_back({(int32_t)c.child[i], (int32_t)si[q].t, gdir(si[q].t, si[q].c),
+                        h.dir_off[c.level + 1] + p.son_dir(si[q].t, si[q].c), eoff});
+          eoff += (int64_t)k * k;
+        }
+      }
+    h.E_d = h.alloc<C64>(eoff);
+    launch_transfer<double>(upload_tmp(td, tmp), (int64_t)td.size(), ct, p.kappa, h.box_d, h.dirs_d,
+                            h.E_d, h.stream);
+    h.check_launch();
+    free_tmp(tmp);
+  }
+
+  const double* x7 = nullptr;
+  const double* w7 = nullptr;
+
+  // ------------------------------------------------------------------
+  // basis weights, bottom-up (eq. (basis_weights_def))
+  void basis_weights() {
+    rR.assign(ns, 0);
+    R_d = h.alloc<C64>((size_t)ns * k * k);
+    for (int l = p.depth; l >= 0; --l) {
+      std::vector<int64_t> qs;
+      for (int64_t q = 0; q < ns; ++q)
+        if (si[q].level == l) qs.push_back(q);
+      size_t i0 = 0;
+      while (i0 < qs.size()) {
+        std::vector<GemmDesc> gd;
+        std::vector<FoldPiece> pieces;
+        std::vector<FoldTask> tasks;
+        size_t used = 0;
+        size_t i1 = i0;
+        for (; i1 < qs.size(); ++i1) {
+          const int64_t q = qs[i1];
+          if (!si[q].leaf && used + (size_t)2 * k * k * sizeof(C64) > ws_bytes && i1 > i0) break;
+          FoldTask tk{};
+          tk.R = Rp(q);
+          tk.n = k;
+          tk.ldr = k;
+          tk.init_zero = 1;
+          tk.compact = 1;
+          tk.count = cnt_d + q;
+          tk.piece_begin = (int32_t)pieces.size();
+          if (si[q].leaf) {
+            pieces.push_back({(C64*)h.V_d + h.V_off[q], si[q].nrows, si[q].nrows});
+          } else {
+            int rows = 0;
+            for (int i = 0; i < 2; ++i) {
+              const int64_t cq = si[q].child_slot[i];
+              const int r = rR[cq];
+              C64* dst = (C64*)(ws + used);
+              used += (size_t)std::max(r, 1) * k * sizeof(C64);
+              if (r > 0) {
+                GemmDesc g{};
+                g.A = Rp(cq); g.lda = k; g.M = r; g.K = k;
+                g.B = Ep(q, i); g.ldb = k; g.N = k;
+                g.C = dst; g.ldc = r;
+                g.alpha_re = 1.0;
+                gd.push_back(g);
+                pieces.push_back({dst, r, r});
+              }
+              rows += r;
+            }
+            (void)rows;
+          }
+          tk.piece_end = (int32_t)pieces.size();
+          tasks.push_back(tk);
+        }
+        std::vector<void*> tmp;
+        if (!gd.empty()) launch_gemm<double>(upload_tmp(gd, tmp), (int64_t)gd.size(), k, k, h.stream);
+        launch_fold<double>(upload_tmp(tasks, tmp), (int64_t)tasks.size(), upload_tmp(pieces, tmp), k,
+                            h.stream);
+        h.check_launch();
+        free_tmp(tmp);
+        i0 = i1;
+      }
+      read_counts(qs, rR);
+    }
+  }
+
+  // generate S_b for a list of blocks into the workspace at dst
+  void gen_couplings(const std::vector<int64_t>& blocks, C64* dst, std::vector<void*>& tmp) {
+    std::vector<CoupDesc> cd(blocks.size());
+    for (size_t i = 0; i < blocks.size(); ++i) {
+      const AdmBlock& b = p.adm[blocks[i]];
+      cd[i] = {(int32_t)b.t, (int32_t)b.s, gdir(b.t, b.c)};
+    }
+    launch_coupling<double>(upload_tmp(cd, tmp), (int64_t)cd.size(), ct, p.kappa, h.box_d, h.dirs_d,
+                            dst, h.stream);
+    h.check_launch();
+  }
+
+  // ------------------------------------------------------------------
+  // block weights omega_b = |R_tc S_b R_sc^*|_F
+  void block_weights() {
+    const int64_t nb = (int64_t)p.adm.size();
+    double* om_d = h.alloc<double>(nb);
+    const size_t per = (size_t)3 * k * k * sizeof(C64);
+    const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
+    for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+      const int64_t b1 = std::min(nb, b0 + batch);
+      std::vector<int64_t> blocks;
+      for (int64_t b = b0; b < b1; ++b) blocks.push_back(b);
+      C64* S = (C64*)ws;
+      C64* T1 = S + (size_t)(b1 - b0) * k * k;
+      C64* T2 = T1 + (size_t)(b1 - b0) * k * k;
+      std::vector<void*> tmp;
+      gen_couplings(blocks, S, tmp);
+      std::vector<GemmDesc> g1, g2;
+      std::vector<FrobDesc> fd;
+      for (int64_t b = b0; b < b1; ++b) {
+        const AdmBlock& a = p.adm[b];
+        const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
+        const int rt = rR[qt], rs = rR[qs];
+        const size_t i = (size_t)(b - b0);
+        GemmDesc g{};
+        g.A = Rp(qt); g.lda = k; g.M = rt; g.K = k;
+        g.B = S + i * k * k; g.ldb = k; g.N = k;
+        g.C = T1 + i * k * k; g.ldc = std::max(rt, 1);
+        g.alpha_re = 1.0;
+        g1.push_back(g);
+        GemmDesc g2d{};
+        g2d.A = T1 + i * k * k; g2d.lda = std::max(rt, 1); g2d.M = rt; g2d.K = k;
+        g2d.B = Rp(qs); g2d.ldb = k; g2d.N = rs; g2d.opB = 2;
+        g2d.C = T2 + i * k * k; g2d.ldc = std::max(rt, 1);
+        g2d.alpha_re = 1.0;
+        g2.push_back(g2d);
+        fd.push_back({T2 + i * k * k, rt, rs, std::max(rt, 1), 0, b});
+      }
+      launch_gemm<double>(upload_tmp(g1, tmp), (int64_t)g1.size(), k, k, h.stream);
+      launch_gemm<double>(upload_tmp(g2, tmp), (int64_t)g2.size(), k, k, h.stream);
+      launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
+      h.check_launch();
+      free_tmp(tmp);
+    }
+    h.omega.resize(nb);
+    if (nb) HIPCHK(hipMemcpy(h.omega.data(), om_d, nb * sizeof(double), hipMemcpyDeviceToHost));
+    h.release(om_d);
+  }
+
+  // ------------------------------------------------------------------
+  // total weights, top-down (eq. (recomp_weight_full)).  row = true: rows of
+  // Z_tc^* are omega_b^{-1} R_sc S_b^* (blocks of row(t,c)) and Zhat_{t+c+} E_{tc+}^*
+  // (inherited); row = false: the same for G^* with omega_b^{-1} R_tc S_b.
+  void total_weights(bool row) {
+    const std::vector<uint8_t>& flag = row ? p.slot_row : p.slot_col;
+    const std::vector<int64_t>& ptr = row ? p.row_ptr : p.col_ptr;
+    const std::vector<int64_t>& blk = row ? p.row_blk : p.col_blk;
+    std::vector<int32_t>& rZ = row ? rZr : rZc;
+    rZ.assign(ns, 0);
+    C64*& Z = row ? Zr_d : Zc_d;
+    Z = h.alloc<C64>((size_t)ns * k * k);
+    // workspace partition: couplings | pieces | temporaries
+    const size_t wsS = ws_bytes * 4 / 10, wsP = ws_bytes * 45 / 100;
+    C64* Sbuf = (C64*)ws;
+    C64* Pbuf = (C64*)(ws + wsS);
+    C64* Tbuf = (C64*)(ws + wsS + wsP);
+    const size_t wsT = ws_bytes - wsS - wsP;
+    const int64_t maxS = std::max<int64_t>(1, (int64_t)(wsS / ((size_t)k * k * sizeof(C64))));
+    const int64_t maxT = std::max<int64_t>(1, (int64_t)(wsT / ((size_t)k * k * sizeof(C64))));
+
+    for (int l = 0; l <= p.depth; ++l) {
+      std::vector<int64_t> qs;
+      for (int64_t q = 0; q < ns; ++q)
+        if (si[q].level == l && flag[q]) qs.push_back(q);
+      // piece list of every slot of the level: (kind, index)
+      struct PieceSrc { int64_t q; int64_t blockid; int64_t parent; int rows; };
+      std::vector<std::vector<PieceSrc>> srcs(qs.size());
+      for (size_t a = 0; a < qs.size(); ++a) {
+        const int64_t q = qs[a];
+        for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) {
+          const int64_t b = blk[e];
+          if (!(h.omega[b] > 0.0)) continue;
+          const AdmBlock& ab = p.adm[b];
+          const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
+          if (rR[other] > 0) srcs[a].push_back({q, b, -1, rR[other]});
+        }
+        for (int64_t pq : parents_of(q, flag))
+          if (rZ[pq] > 0) srcs[a].push_back({q, -1, pq, rZ[pq]});
+        int64_t M = 0;
+        for (auto& s : srcs[a]) M += s.rows;
+        (void)M;
+        rZ[q] = 0;
+      }
+      // batches over (slot, piece) in order
+      size_t a0 = 0, e0 = 0;
+      std::vector<uint8_t> started(qs.size(), 0);
+      while (a0 < qs.size()) {
+        if (e0 >= srcs[a0].size()) {  // slot without pieces: rank 0, Zhat never read
+          ++a0;
+          e0 = 0;
+          continue;
+        }
+        // collect a batch
+        struct Item { size_t a; size_t e0, e1; };
+        std::vector<Item> items;
+        std::vector<int64_t> sblocks;
+        size_t prow = 0;
+        size_t a = a0, e = e0;
+        while (a < qs.size()) {
+          Item it{a, e, e};
+          while (e < srcs[a].size()) {
+            const PieceSrc& s = srcs[a][e];
+            const size_t need = (size_t)s.rows * k;
+            if ((s.blockid >= 0 && (int64_t)sblocks.size() >= maxS) ||
+                (prow + need) * sizeof(C64) > wsP)
+              break;
+            if (s.blockid >= 0) sblocks.push_back(s.blockid);
+            prow += need;
+            ++e;
+          }
+          it.e1 = e;
+          if (it.e1 > it.e0) items.push_back(it);
+          if (e < srcs[a].size()) break;  // workspace full
+          ++a;
+          e = 0;
+        }
+        if (items.empty()) throw Fail{DH2_ERR_OOM, "workspace too small for one coupling piece"};
+        std::vector<void*> tmp;
+        gen_couplings(sblocks, Sbuf, tmp);
+        std::vector<GemmDesc> gd;
+        std::vector<FoldPiece> pieces;
+        std::vector<std::pair<size_t, size_t>> item_pieces;  // piece range per item
+        size_t sidx = 0, poff = 0;
+        for (const Item& it : items) {
+          const size_t pb = pieces.size();
+          for (size_t ee = it.e0; ee < it.e1; ++ee) {
+            const PieceSrc& s = srcs[it.a][ee];
+            C64* dst = Pbuf + poff;
+            poff += (size_t)s.rows * k;
+            GemmDesc g{};
+            g.M = s.rows; g.N = k; g.K = k;
+            g.C = dst; g.ldc = s.rows;
+            if (s.blockid >= 0) {
+              const AdmBlock& ab = p.adm[s.blockid];
+              const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
+              g.A = Rp(other); g.lda = k;
+              g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
+              g.alpha_re = 1.0 / h.omega[s.blockid];
+              ++sidx;
+            } else {
+              g.A = Zp(row, s.parent); g.lda = k;
+              g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
+              g.alpha_re = 1.0;
+            }
+            gd.push_back(g);
+            pieces.push_back({dst, s.rows, s.rows});
+          }
+          item_pieces.push_back({pb, pieces.size()});
+        }
+        launch_gemm<double>(upload_tmp(gd, tmp), (int64_t)gd.size(), k, k, h.stream);
+        h.check_launch();
+        // TSQR split: fold segments of each item into temporaries when the
+        // batch has few slots, then fold the temporaries into Zhat
+        const int64_t want = 512;
+        int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
+        G = std::min<int64_t>(G, std::max<int64_t>(1, maxT / (int64_t)items.size()));
+        std::vector<FoldTask> t1, t2;
+        std::vector<FoldPiece> p2;
+        int64_t tcount = 0;
+        for (size_t ii = 0; ii < items.size(); ++ii) {
+          const Item& it = items[ii];
+          const int64_t q = qs[it.a];
+          const size_t pb = item_pieces[ii].first, pe = item_pieces[ii].second;
+          const int64_t np = (int64_t)(pe - pb);
+          const int64_t g = std::min<int64_t>(G, np);
+          const int last = it.e1 >= srcs[it.a].size() ? 1 : 0;
+          FoldTask fin{Zp(row, q), k, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
+          if (g <= 1) {
+            fin.piece_begin = (int32_t)pb;
+            fin.piece_end = (int32_t)pe;
+            t2.push_back(fin);
+          } else {
+            fin.piece_begin = (int32_t)(pieces.size() + p2.size());
+            for (int64_t s = 0; s < g; ++s) {
+              const size_t sb = pb + (size_t)(np * s / g), se = pb + (size_t)(np * (s + 1) / g);
+              C64* Rt = Tbuf + (size_t)tcount * k * k;
+              ++tcount;
+              t1.push_back(FoldTask{Rt, k, k, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
+              // all k rows: in floating point a compacted factor may keep more
+              // nonzero rows than the rows folded into it
+              p2.push_back({Rt, k, k});
+            }
+            fin.piece_end = (int32_t)(pieces.size() + p2.size());
+            t2.push_back(fin);
+          }
+          started[it.a] = 1;
+        }
+        pieces.insert(pieces.end(), p2.begin(), p2.end());
+        FoldPiece* pd = upload_tmp(pieces, tmp);
+        if (!t1.empty()) launch_fold<double>(upload_tmp(t1, tmp), (int64_t)t1.size(), pd, k, h.stream);
+        launch_fold<double>(upload_tmp(t2, tmp), (int64_t)t2.size(), pd, k, h.stream);
+        h.check_launch();
+        free_tmp(tmp);
+        // advance
+        const Item& last = items.back();
+        a0 = last.a;
+        e0 = last.e1;
+        if (e0 >= srcs[a0].size()) {
+          ++a0;
+          e0 = 0;
+        }
+      }
+      std::vector<int64_t> done;
+      for (size_t a = 0; a < qs.size(); ++a)
+        if (!srcs[a].empty()) done.push_back(qs[a]);
+      read_counts(done, rZ);
+    }
+  }
+
+  // ------------------------------------------------------------------
+  // truncation, bottom-up (Section 3.2): SVD of V Zhat^* (leaf) or Vhat Zhat^*
+  // with Vhat = [C_{t1c1} E_{t1c}; C_{t2c2} E_{t2c}], rank by the tolerance rule,
+  // Qhat = leading left singular vectors, C_tc = Qhat^* Vhat.
+  void truncation(bool row) {
+    const std::vector<uint8_t>& flag = row ? p.slot_row : p.slot_col;
+    std::vector<int32_t>& rZ = row ? rZr : rZc;
+    std::vector<int32_t>& rank = row ? h.rank_row : h.rank_col;
+    auto& sig = row ? h.sig_row : h.sig_col;
+    rank.assign(ns, -1);
+    sig.assign(ns, {});
+    std::vector<C64*>& Cptr = row ? Cr_ptr : Cc_ptr;
+    std::vector<z64*>& Qptr = row ? h.Qr_ptr : h.Qc_ptr;
+    std::vector<int32_t>& Qm = row ? h.Qr_m : h.Qc_m;
+    Cptr.assign(ns, nullptr);
+    Qptr.assign(ns, nullptr);
+    Qm.assign(ns, 0);
+    for (int l = p.depth; l >= 0; --l) {
+      std::vector<int64_t> qs;
+      for (int64_t q = 0; q < ns; ++q)
+        if (si[q].level == l && flag[q]) qs.push_back(q);
+      size_t i0 = 0;
+      while (i0 < qs.size()) {
+        // per slot: m, Vhat (m x k), B (rZ x m), RB (m x m), U (m x m), scratch 2 m^2
+        std::vector<int64_t> batch;
+        std::vector<size_t> off_vh, off_b, off_rb, off_u, off_sc;
+        std::vector<int32_t> mm;
+        size_t used = 0;
+        size_t i1 = i0;
+        for (; i1 < qs.size(); ++i1) {
+          const int64_t q = qs[i1];
+          int m;
+          if (si[q].leaf) m = si[q].nrows;
+          else m = rank[si[q].child_slot[0]] + rank[si[q].child_slot[1]];
+          const size_t need = ((size_t)m * k + (size_t)rZ[q] * m + 4 * (size_t)m * m + 8) * sizeof(C64);
+          if (used + need > ws_bytes && i1 > i0) break;
+          batch.push_back(q);
+          mm.push_back(m);
+          off_vh.push_back(used); used += (size_t)m * k * sizeof(C64);
+          off_b.push_back(used); used += (size_t)rZ[q] * m * sizeof(C64);
+          off_rb.push_back(used); used += (size_t)m * m * sizeof(C64);
+          off_u.push_back(used); used += (size_t)m * m * sizeof(C64);
+          off_sc.push_back(used); used += (size_t)2 * m * m * sizeof(C64) + 8 * sizeof(C64);
+          if (used > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for a truncation step"};
+        }
+        std::vector<void*> tmp;
+        std::vector<GemmDesc> g1, g2;
+        std::vector<FoldTask> ft;
+        std::vector<FoldPiece> fp;
+        std::vector<SvdTask> sv;
+        const size_t nb = batch.size();
+        double* sig_d = (double*)h.alloc<double>(nb * 256 + 1);
+        int32_t* rk_d = h.alloc<int32_t>(nb + 1);
+        tmp.push_back(sig_d);
+        tmp.push_back(rk_d);
+        int maxm = 0;
+        std::vector<const C64*> vh_ptr(nb);
+        std::vector<int> vh_ld(nb);
+        for (size_t b = 0; b < nb; ++b) {
+          const int64_t q = batch[b];
+          const int m = mm[b];
+          maxm = std::max(maxm, m);
+          C64* vh = (C64*)(ws + off_vh[b]);
+          if (si[q].leaf) {
+            vh_ptr[b] = (C64*)h.V_d + h.V_off[q];
+            vh_ld[b] = si[q].nrows;
+          } else {
+            int off = 0;
+            for (int i = 0; i < 2; ++i) {
+              const int64_t cq = si[q].child_slot[i];
+              const int kc = rank[cq];
+              if (kc > 0) {
+                GemmDesc g{};
+                g.A = Cptr[cq]; g.lda = kc; g.M = kc; g.K = k;
+                g.B = Ep(q, i); g.ldb = k; g.N = k;
+                g.C = vh + off; g.ldc = m;
+                g.alpha_re = 1.0;
+                g1.push_back(g);
+              }
+              off += kc;
+            }
+            vh_ptr[b] = vh;
+            vh_ld[b] = m;
+          }
+          if (m == 0 || rZ[q] == 0) continue;
+          // B = Zhat Vhat^* (rZ x m)
+          C64* B = (C64*)(ws + off_b[b]);
+          GemmDesc g{};
+          g.A = Zp(row, q); g.lda = k; g.M = rZ[q]; g.K = k;
+          g.B = vh_ptr[b]; g.ldb = vh_ld[b]; g.N = m; g.opB = 2;
+          g.C = B; g.ldc = rZ[q];
+          g.alpha_re = 1.0;
+          g2.push_back(g);
+          ft.push_back(FoldTask{(C64*)(ws + off_rb[b]), m, m, (int32_t)fp.size(),
+                                (int32_t)fp.size() + 1, 1, 0, nullptr});
+          fp.push_back({B, rZ[q], rZ[q]});
+          SvdTask st{};
+          st.B = ws + off_rb[b]; st.ldb = m;
+          st.U = ws + off_u[b]; st.ldu = m;
+          st.sig = sig_d + b * 256;
+          st.rank = rk_d + b;
+          st.scratch = ws + off_sc[b];
+          st.m = m;
+          st.norm_mode = h.norm_mode;
+          st.eps = h.tol;
+          sv.push_back(st);
+        }
+        if (maxm > 256) throw Fail{DH2_ERR_ARG, "truncation matrix with more than 256 rows"};
+        if (!g1.empty()) launch_gemm<double>(upload_tmp(g1, tmp), (int64_t)g1.size(), k, k, h.stream);
+        if (!g2.empty()) launch_gemm<double>(upload_tmp(g2, tmp), (int64_t)g2.size(), k, std::max(maxm, 1), h.stream);
+        if (!ft.empty()) {
+          // fold per m: n differs per task, LDS sized for the largest
+          launch_fold<double>(upload_tmp(ft, tmp), (int64_t)ft.size(), upload_tmp(fp, tmp), maxm, h.stream);
+          launch_jacobi(upload_tmp(sv, tmp), (int64_t)sv.size(), maxm, h.stream);
+        }
+        h.check_launch();
+        h.sync();
+        std::vector<int32_t> rk(nb, 0);
+        std::vector<double> sg(nb * 256);
+        HIPCHK(hipMemcpy(rk.data(), rk_d, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(sg.data(), sig_d, nb * 256 * sizeof(double), hipMemcpyDeviceToHost));
+        // store Qhat (m x kk) and C = Qhat^* Vhat (kk x k); SVD results are indexed by batch position
+        std::vector<int> kkb(nb, 0);
+        size_t qtot = 0, ctot = 0;
+        for (size_t b = 0; b < nb; ++b) {
+          const int64_t q = batch[b];
+          const int m = mm[b];
+          if (m > 0 && rZ[q] > 0) {
+            kkb[b] = rk[b];
+            sig[q].assign(sg.begin() + b * 256, sg.begin() + b * 256 + m);
+          }
+          qtot += (size_t)m * kkb[b];
+          ctot += (size_t)kkb[b] * k;
+        }
+        C64* Qb = h.alloc<C64>(std::max<size_t>(qtot, 1));
+        C64* Cb = h.alloc<C64>(std::max<size_t>(ctot, 1));
+        keep_rc.push_back(Cb);
+        std::vector<CopyDesc> cp;
+        std::vector<GemmDesc> g3;
+        size_t qo = 0, co = 0;
+        for (size_t b = 0; b < nb; ++b) {
+          const int64_t q = batch[b];
+          const int m = mm[b];
+          const int kk = kkb[b];
+          rank[q] = kk;
+          Qm[q] = m;
+          Qptr[q] = Qb + qo;
+          Cptr[q] = Cb + co;
+          qo += (size_t)m * kk;
+          co += (size_t)kk * k;
+          if (kk > 0) {
+            cp.push_back({ws + off_u[b], Qptr[q], m, kk, m, m});
+            GemmDesc g{};
+            g.A = Qptr[q]; g.lda = m; g.M = kk; g.K = m; g.opA = 2;
+            g.B = vh_ptr[b]; g.ldb = vh_ld[b]; g.N = k;
+            g.C = Cptr[q]; g.ldc = kk;
+            g.alpha_re = 1.0;
+            g3.push_back(g);
+          }
+        }
+        if (!cp.empty()) launch_copy<double>(upload_tmp(cp, tmp), (int64_t)cp.size(), h.stream);
+        if (!g3.empty()) launch_gemm<double>(upload_tmp(g3, tmp), (int64_t)g3.size(), k, k, h.stream);
+        h.check_launch();
+        free_tmp(tmp);
+        i0 = i1;
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------
+  // projection Stilde_b = C_tc S_b C_{W,sc}^* (Lemma 'Projections')
+  void projection() {
+    const int64_t nb = (int64_t)p.adm.size();
+    h.St_off.assign(nb, 0);
+    int64_t tot = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const AdmBlock& a = p.adm[b];
+      h.St_off[b] = tot;
+      tot += (int64_t)h.rank_row[p.slot_of(a.t, a.c)] * h.rank_col[p.slot_of(a.s, a.c)];
+    }
+    h.St_d = h.alloc<C64>((size_t)std::max<int64_t>(tot, 1));
+    const size_t per = (size_t)2 * k * k * sizeof(C64);
+    const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
+    for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+      const int64_t b1 = std::min(nb, b0 + batch);
+      std::vector<int64_t> blocks;
+      for (int64_t b = b0; b < b1; ++b) blocks.push_back(b);
+      C64* S = (C64*)ws;
+      C64* T = S + (size_t)(b1 - b0) * k * k;
+      std::vector<void*> tmp;
+      gen_couplings(blocks, S, tmp);
+      std::vector<GemmDesc> g1, g2;
+      for (int64_t b = b0; b < b1; ++b) {
+        const AdmBlock& a = p.adm[b];
+        const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
+        const int kt = h.rank_row[qt], ks = h.rank_col[qs];
+        if (kt == 0 || ks == 0) continue;
+        const size_t i = (size_t)(b - b0);
+        GemmDesc g{};
+        g.A = Cr_ptr[qt]; g.lda = kt; g.M = kt; g.K = k;
+        g.B = S + i * k * k; g.ldb = k; g.N = k;
+        g.C = T + i * k * k; g.ldc = kt;
+        g.alpha_re = 1.0;
+        g1.push_back(g);
+        GemmDesc gg{};
+        gg.A = T + i * k * k; gg.lda = kt; gg.M = kt; gg.K = k;
+        gg.B = Cc_ptr[qs]; gg.ldb = ks; gg.N = ks; gg.opB = 2;
+        gg.C = (C64*)h.St_d + h.St_off[b]; gg.ldc = kt;
+        gg.alpha_re = 1.0;
+        g2.push_back(gg);
+      }
+      if (!g1.empty()) {
+        launch_gemm<double>(upload_tmp(g1, tmp), (int64_t)g1.size(), k, k, h.stream);
+        launch_gemm<double>(upload_tmp(g2, tmp), (int64_t)g2.size(), k, k, h.stream);
+      }
+      h.check_launch();
+      free_tmp(tmp);
+    }
+  }
+
+  // ------------------------------------------------------------------
+  // matvec schedule: phases of MvOut lists (see matvec.hip)
+  void matvec_schedule() {
+    const int nr = h.max_nrhs;
+    const int64_t n = p.n;
+    h.Xp_d = h.alloc<C64>((size_t)n * nr);
+    h.Yp_d = h.alloc<C64>((size_t)n * nr);
+    std::vector<int64_t> xo(ns, -1), yo(ns, -1);
+    int64_t xt = 0, yt = 0;
+    for (int64_t q = 0; q < ns; ++q) {
+      if (h.rank_col[q] > 0) { xo[q] = xt; xt += (int64_t)h.rank_col[q] * nr; }
+      if (h.rank_row[q] > 0) { yo[q] = yt; yt += (int64_t)h.rank_row[q] * nr; }
+    }
+    C64* xh = h.alloc<C64>((size_t)std::max<int64_t>(xt, 1));
+    C64* yh = h.alloc<C64>((size_t)std::max<int64_t>(yt, 1));
+    h.xh_d = xh;
+    h.yh_d = yh;
+    C64* Xp = (C64*)h.Xp_d;
+    C64* Yp = (C64*)h.Yp_d;
+    std::vector<MvOut> outs;
+    std::vector<MvTerm> terms;
+    h.mv_phases.clear();
+    auto begin_phase = [&]() { h.mv_phases.push_back({(int64_t)outs.size(), (int64_t)outs.size()}); };
+    auto end_phase = [&]() { h.mv_phases.back().out_end = (int64_t)outs.size(); };
+    // forward, leaves
+    begin_phase();
+    for (int64_t q = 0; q < ns; ++q)
+      if (si[q].leaf && h.rank_col[q] > 0) {
+        const int kq = h.rank_col[q];
+        MvOut o{xh + xo[q], kq, kq, (int32_t)terms.size(), 0, 0, 0};
+        terms.push_back({h.Qc_ptr[q], Xp + si[q].row0, si[q].nrows, si[q].nrows, (int32_t)n, 2});
+        o.term_end = (int32_t)terms.size();
+        outs.push_back(o);
+      }
+    end_phase();
+    // forward, inner clusters bottom-up
+    for (int l = p.depth; l >= 0; --l) {
+      begin_phase();
+      for (int64_t q = 0; q < ns; ++q)
+        if (si[q].level == l && !si[q].leaf && h.rank_col[q] > 0) {
+          const int kq = h.rank_col[q];
+          MvOut o{xh + xo[q], kq, kq, (int32_t)terms.size(), 0, 0, 0};
+          int off = 0;
+          for (int i = 0; i < 2; ++i) {
+            const int64_t cq = si[q].child_slot[i];
+            const int kc = h.rank_col[cq];
+            if (kc > 0)
+              terms.push_back({h.Qc_ptr[q] + off, xh + xo[cq], kc, h.Qc_m[q], kc, 2});
+            off += kc;
+          }
+          o.term_end = (int32_t)terms.size();
+          outs.push_back(o);
+        }
+      end_phase();
+    }
+    // coupling
+    begin_phase();
+    for (int64_t q = 0; q < ns; ++q)
+      if (h.rank_row[q] > 0) {
+        const int kq = h.rank_row[q];
+        MvOut o{yh + yo[q], kq, kq, (int32_t)terms.size(), 0, 0, 0};
+        for (int64_t e = p.row_ptr[q]; e < p.row_ptr[q + 1]; ++e) {
+          const int64_t b = p.row_blk[e];
+          const AdmBlock& a = p.adm[b];
+          const int64_t qs = p.slot_of(a.s, a.c);
+          const int ks = h.rank_col[qs];
+          if (ks > 0) terms.push_back({(C64*)h.St_d + h.St_off[b], xh + xo[qs], ks, kq, ks, 0});
+        }
+        o.term_end = (int32_t)terms.size();
+        outs.push_back(o);
+      }
+    end_phase();
+    // backward, top-down: y_{t'c'} += F_{t'c} y_tc
+    for (int l = 1; l <= p.depth; ++l) {
+      begin_phase();
+      for (int64_t q = 0; q < ns; ++q)
+        if (si[q].level == l && h.rank_row[q] > 0) {
+          const int kq = h.rank_row[q];
+          MvOut o{yh + yo[q], kq, kq, (int32_t)terms.size(), 0, 1, 0};
+          const int ci = child_index(si[q].t);
+          for (int64_t pq : parents_of(q, p.slot_row)) {
+            const int kp = h.rank_row[pq];
+            if (kp <= 0) continue;
+            const int off = ci == 0 ? 0 : h.rank_row[si[pq].child_slot[0]];
+            terms.push_back({h.Qr_ptr[pq] + off, yh + yo[pq], kp, h.Qr_m[pq], kp, 0});
+          }
+          o.term_end = (int32_t)terms.size();
+          if (o.term_end > o.term_begin) outs.push_back(o);
+        }
+      end_phase();
+    }
+    // leaf output + near field
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> near_of_leaf(p.cl.size());
+    for (int64_t b = 0; b < (int64_t)p.near.size(); ++b) {
+      const NearBlock& nbk = p.near[b];
+      const Cluster& t = p.cl[nbk.t];
+      // distribute the rows of t over its leaves
+      std::vector<int64_t> stack{nbk.t};
+      while (!stack.empty()) {
+        const int64_t c = stack.back();
+        stack.pop_back();
+        if (p.cl[c].leaf()) near_of_leaf[c].push_back({b, p.cl[c].first - t.first});
+        else
+          for (int i = 0; i < 2; ++i) stack.push_back(p.cl[c].child[i]);
+      }
+    }
+    begin_phase();
+    for (int64_t t = 0; t < (int64_t)p.cl.size(); ++t) {
+      const Cluster& c = p.cl[t];
+      if (!c.leaf()) continue;
+      MvOut o{Yp + c.first, (int32_t)c.size, (int32_t)n, (int32_t)terms.size(), 0, 0, 0};
+      for (const auto& pr : p.cl_slots[t]) {
+        const int64_t q = pr.second;
+        if (h.rank_row[q] > 0)
+          terms.push_back({h.Qr_ptr[q], yh + yo[q], h.rank_row[q], (int32_t)c.size, h.rank_row[q], 0});
+      }
+      for (const auto& pr : near_of_leaf[t]) {
+        const NearBlock& nbk = p.near[pr.first];
+        const Cluster& tt = p.cl[nbk.t];
+        const Cluster& ss = p.cl[nbk.s];
+        terms.push_back({(C64*)h.near_d + h.near_off[pr.first] + pr.second, Xp + ss.first,
+                         (int32_t)ss.size, (int32_t)tt.size, (int32_t)n, 0});
+      }
+      o.term_end = (int32_t)terms.size();
+      outs.push_back(o);
+    }
+    end_phase();
+    h.mv_outs_d = h.upload(outs);
+    h.mv_terms_d = h.upload(terms);
+  }
+};
+
+void validate(const dh2_geometry* g, double kappa, int order, double eta, int leafsize, double tol,
+              double eta1) {
+  if (!g) throw Fail{DH2_ERR_ARG, "geometry is NULL"};
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) throw Fail{DH2_ERR_ARG, "kappa must be finite and >= 0"};
+  if (order < 1 || order > kMaxOrder) throw Fail{DH2_ERR_ARG, "order must be in [1, 8]"};
+  if (!(eta > 0.0) || !std::isfinite(eta)) throw Fail{DH2_ERR_ARG, "eta must be > 0"};
+  if (leafsize < 1 || leafsize > 256) throw Fail{DH2_ERR_ARG, "leafsize must be in [1, 256]"};
+  if (!(tol >= 0.0) || !std::isfinite(tol)) throw Fail{DH2_ERR_ARG, "tol must be finite and >= 0"};
+  if (!(eta1 > 0.0) || !std::isfinite(eta1)) throw Fail{DH2_ERR_ARG, "eta1 must be > 0"};
+  if (g->n_triangles < 1 || g->n_vertices < 3 || !g->vertices || !g->triangles)
+    throw Fail{DH2_ERR_GEOMETRY, "empty geometry"};
+  if (g->n_triangles > (int64_t)1 << 30) throw Fail{DH2_ERR_GEOMETRY, "too many triangles"};
+  for (int64_t i = 0; i < g->n_vertices * 3; ++i)
+    if (!std::isfinite(g->vertices[i])) throw Fail{DH2_ERR_GEOMETRY, "non-finite vertex coordinate"};
+  for (int64_t i = 0; i < g->n_triangles; ++i) {
+    const int32_t* t = g->triangles + 3 * i;
+    for (int v = 0; v < 3; ++v)
+      if (t[v] < 0 || t[v] >= g->n_vertices)
+        throw Fail{DH2_ERR_GEOMETRY, "triangle " + std::to_string(i) + " has a vertex index out of range"};
+    const double* a = g->vertices + 3 * (int64_t)t[0];
+    const double* b = g->vertices + 3 * (int64_t)t[1];
+    const double* c = g->vertices + 3 * (int64_t)t[2];
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (!(cx * cx + cy * cy + cz * cz > 0.0))
+      throw Fail{DH2_ERR_GEOMETRY, "triangle " + std::to_string(i) + " has zero area"};
+  }
+}
+
+void build_all(dh2_problem& h, const dh2_geometry& g) {
+  const double t_start = now_ms();
+  Plan& p = h.plan;
+  h.stats.ms_structure = 0;
+  double t0 = now_ms();
+  // structure (host)
+  {
+    std::string err = build_plan(g.vertices, g.n_vertices, g.triangles, g.n_triangles, h.plan.kappa,
+                                 h.plan.order, h.plan.eta, h.plan.leafsize, h.plan.eta1, p);
+    if (!err.empty()) throw Fail{DH2_ERR_ARG, err};
+  }
+  h.stats.ms_structure = now_ms() - t0;
+  Builder bd(h);
+  bd.setup_slots();
+  const int k = p.k;
+  const int64_t n = p.n;
+  const int64_t nc = (int64_t)p.cl.size();
+
+  // geometry, per-triangle data
+  t0 = now_ms();
+  std::vector<double> Vh(g.vertices, g.vertices + 3 * g.n_vertices);
+  std::vector<int32_t> Th(g.triangles, g.triangles + 3 * g.n_triangles);
+  double* Vd = h.upload(Vh);
+  int32_t* Td = h.upload(Th);
+  h.perm_d = h.upload(p.perm);
+  double* x7 = h.alloc<double>((size_t)n * 21);
+  double* w7 = h.alloc<double>((size_t)n * 7);
+  double* x16 = h.alloc<double>((size_t)n * 48);
+  double* w16 = h.alloc<double>((size_t)n * 16);
+  double* selfl = h.alloc<double>((size_t)n);
+  launch_tri_data(n, Vd, Td, h.perm_d, make_quad(), x7, w7, x16, w16, selfl, h.stream);
+  h.check_launch();
+  std::vector<double> box(6 * nc);
+  for (int64_t t = 0; t < nc; ++t)
+    for (int d = 0; d < 3; ++d) {
+      box[6 * t + d] = p.cl[t].lo[d];
+      box[6 * t + 3 + d] = p.cl[t].hi[d];
+    }
+  h.box_d = h.upload(box);
+  std::vector<double> dirs;
+  h.dir_off.clear();
+  for (int l = 0; l <= p.depth; ++l) {
+    h.dir_off.push_back((int64_t)dirs.size() / 3);
+    dirs.insert(dirs.end(), p.dirs[l].begin(), p.dirs[l].end());
+  }
+  h.dirs_d = h.upload(dirs);
+
+  // near field
+  {
+    std::vector<NearDesc> nd(p.near.size());
+    h.near_off.resize(p.near.size());
+    int64_t off = 0;
+    for (size_t b = 0; b < p.near.size(); ++b) {
+      const Cluster& t = p.cl[p.near[b].t];
+      const Cluster& s = p.cl[p.near[b].s];
+      nd[b] = {t.first, s.first, (int32_t)t.size, (int32_t)s.size, off};
+      h.near_off[b] = off;
+      off += t.size * s.size;
+    }
+    h.stats.near_entries = off;
+    h.near_d = h.alloc<C64>((size_t)std::max<int64_t>(off, 1));
+    NearDesc* ndd = h.upload(nd);
+    launch_near<double>(ndd, (int64_t)nd.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+    h.check_launch();
+    h.sync();
+    h.release(ndd);
+  }
+  h.stats.ms_near = now_ms() - t0;
+
+  // workspace
+  bd.ws_bytes = h.ws_bytes;
+  bd.ws = (char*)h.alloc<char>(bd.ws_bytes);
+  bd.cnt_d = h.alloc<int32_t>((size_t)std::max<int64_t>(bd.ns, 1));
+
+  t0 = now_ms();
+  bd.x7 = x7;
+  bd.w7 = w7;
+  bd.interpolation();
+  h.sync();
+  h.stats.ms_interp = now_ms() - t0;
+  t0 = now_ms();
+  bd.basis_weights();
+  h.sync();
+  h.stats.ms_basis_weights = now_ms() - t0;
+  t0 = now_ms();
+  bd.block_weights();
+  h.stats.ms_block_weights = now_ms() - t0;
+  t0 = now_ms();
+  bd.total_weights(true);
+  bd.total_weights(false);
+  h.sync();
+  h.stats.ms_total_weights = now_ms() - t0;
+  t0 = now_ms();
+  bd.truncation(true);
+  bd.truncation(false);
+  h.stats.ms_truncation = now_ms() - t0;
+  t0 = now_ms();
+  bd.projection();
+  h.sync();
+  h.stats.ms_projection = now_ms() - t0;
+  // release build-only buffers
+  h.R_d = bd.R_d;
+  h.Zr_d = bd.Zr_d;
+  h.Zc_d = bd.Zc_d;
+  h.rR = bd.rR;
+  h.rZr = bd.rZr;
+  h.rZc = bd.rZc;
+  h.cheb = bd.ct;
+  for (void* x : bd.keep_rc) h.release(x);
+  h.release(bd.ws);
+  h.release(bd.cnt_d);
+  h.release(x7);
+  h.release(w7);
+  h.release(x16);
+  h.release(w16);
+  h.release(selfl);
+  h.release(Vd);
+  h.release(Td);
+  bd.matvec_schedule();
+  h.sync();
+  h.stats.ms_total = now_ms() - t_start;
+
+  // stats
+  dh2_stats& s = h.stats;
+  s.k = k;
+  s.n = n;
+  s.n_clusters = nc;
+  s.n_leaves = 0;
+  for (const auto& c : p.cl) s.n_leaves += c.leaf() ? 1 : 0;
+  s.depth = p.depth;
+  s.n_adm = (int64_t)p.adm.size();
+  s.n_near = (int64_t)p.near.size();
+  s.n_slots = bd.ns;
+  s.n_row_slots = s.n_col_slots = 0;
+  int64_t basis = 0;
+  double sr = 0, sc = 0;
+  s.rank_max_row = s.rank_max_col = 0;
+  for (int64_t q = 0; q < bd.ns; ++q) {
+    if (h.rank_row[q] >= 0) {
+      ++s.n_row_slots;
+      sr += h.rank_row[q];
+      s.rank_max_row = std::max(s.rank_max_row, h.rank_row[q]);
+      basis += (int64_t)h.Qr_m[q] * h.rank_row[q];
+    }
+    if (h.rank_col[q] >= 0) {
+      ++s.n_col_slots;
+      sc += h.rank_col[q];
+      s.rank_max_col = std::max(s.rank_max_col, h.rank_col[q]);
+      basis += (int64_t)h.Qc_m[q] * h.rank_col[q];
+    }
+  }
+  s.rank_mean_row = s.n_row_slots ? sr / s.n_row_slots : 0;
+  s.rank_mean_col = s.n_col_slots ? sc / s.n_col_slots : 0;
+  int64_t coup = 0;
+  for (const auto& a : p.adm)
+    coup += (int64_t)h.rank_row[p.slot_of(a.t, a.c)] * h.rank_col[p.slot_of(a.s, a.c)];
+  s.coupling_entries = coup;
+  s.basis_entries = basis;
+  const double e = h.precision == DH2_FP64 ? 16.0 : 8.0;
+  s.matvec_bytes = e * ((double)s.near_entries + (double)coup + (double)basis);
+  int64_t xsum = 0, ysum = 0;
+  for (int64_t q = 0; q < bd.ns; ++q) {
+    xsum += std::max(0, h.rank_col[q]);
+    ysum += std::max(0, h.rank_row[q]);
+  }
+  s.matvec_bytes_per_rhs = e * (2.0 * n + 2.0 * (double)(xsum + ysum));
+}
+
+dh2_status fail(const Fail& f) {
+  g_err = f.msg;
+  return f.st;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* dh2_last_error(void) { return g_err.c_str(); }
+
+dh2_status dh2_build(const dh2_geometry* geometry, double kappa, int order, double eta, int leafsize,
+                     double tol, dh2_handle* out) {
+  return dh2_build_ex(geometry, kappa, order, eta, leafsize, tol, nullptr, out);
+}
+
+dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, double eta,
+                        int leafsize, double tol, const dh2_options* options, dh2_handle* out) {
+  g_err.clear();
+  if (!out) {
+    g_err = "out is NULL";
+    return DH2_ERR_ARG;
+  }
+  *out = nullptr;
+  dh2_options opt{};
+  opt.size = sizeof(opt);
+  if (options) {
+    if (options->size < sizeof(uint32_t) || options->size > sizeof(dh2_options)) {
+      g_err = "options.size must be sizeof(dh2_options)";
+      return DH2_ERR_ARG;
+    }
+    std::memcpy(&opt, options, options->size);
+  }
+  if (opt.precision != DH2_FP64 && opt.precision != DH2_FP32) {
+    g_err = "unknown precision";
+    return DH2_ERR_ARG;
+  }
+  if (opt.precision == DH2_FP32) {
+    g_err = "FP32 form is not available in this build";
+    return DH2_ERR_ARG;
+  }
+  const double eta1 = opt.eta1 > 0 ? opt.eta1 : 10.0;
+  const int max_nrhs = opt.max_nrhs > 0 ? opt.max_nrhs : 16;
+  const double wsgb = opt.workspace_gb > 0 ? opt.workspace_gb : 8.0;
+  std::unique_ptr<dh2_problem> h;
+  try {
+    validate(geometry, kappa, order, eta, leafsize, tol, eta1);
+    if (max_nrhs > 4096) throw Fail{DH2_ERR_ARG, "max_nrhs too large"};
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+      throw Fail{DH2_ERR_DEVICE, "no HIP device available"};
+    h.reset(new dh2_problem());
+    HIPCHK(hipGetDevice(&h->device));
+    {
+      int lds = 0;
+      HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+      set_lds_limit((size_t)lds);
+    }
+    h->precision = opt.precision;
+    h->stream = (hipStream_t)opt.stream;
+    h->max_nrhs = max_nrhs;
+    h->tol = tol;
+    h->norm_mode = 0;
+    h->plan.kappa = kappa;
+    h->plan.order = order;
+    h->plan.eta = eta;
+    h->plan.leafsize = leafsize;
+    h->plan.eta1 = eta1;
+    h->ws_bytes = (size_t)(wsgb * (1ull << 30));
+    // small problems do not need the full workspace
+    const double k = (double)order * order * order;
+    const double est = (double)geometry->n_triangles * k * 16.0 * 64.0 + 64.0 * k * k * 16.0 * 64.0;
+    if ((double)h->ws_bytes > est) h->ws_bytes = (size_t)est;
+    h->stats.size = sizeof(dh2_stats);
+    build_all(*h, *geometry);
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return DH2_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return DH2_ERR_DEVICE;
+  }
+  *out = h.release();
+  return DH2_OK;
+}
+
+dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs) {
+  if (!h || !X || !Y) {
+    g_err = "NULL handle or vector";
+    return DH2_ERR_ARG;
+  }
+  if (nrhs < 1 || nrhs > h->max_nrhs) {
+    g_err = "nrhs out of range [1, max_nrhs]";
+    return DH2_ERR_ARG;
+  }
+  try {
+    const int64_t n = h->plan.n;
+    launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
+    for (const auto& ph : h->mv_phases)
+      if (ph.out_end > ph.out_begin)
+        launch_mv_terms<double>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
+                                nrhs, h->stream);
+    launch_mv_permute<double>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, h->stream);
+    HIPCHK(hipGetLastError());
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+  return DH2_OK;
+}
+
+void dh2_free(dh2_handle h) { delete h; }
+
+dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s) {
+  if (!h || !s || s->size != sizeof(dh2_stats)) {
+    g_err = "NULL handle / stats or wrong stats size";
+    return DH2_ERR_ARG;
+  }
+  *s = h->stats;
+  return DH2_OK;
+}
+
+dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64_t* rows,
+                       int64_t* cols) {
+  if (!h || !rows || !cols) {
+    g_err = "NULL argument";
+    return DH2_ERR_ARG;
+  }
+  try {
+    const Plan& p = h->plan;
+    const int k = p.k;
+    const int64_t ns = (int64_t)p.slots.size();
+    const void* src = nullptr;
+    int64_t r = 0, c = 0;
+    std::vector<double> host;
+    switch (what) {
+      case DH2_INSPECT_NEAR: {
+        if (index < 0 || index >= (int64_t)p.near.size()) throw Fail{DH2_ERR_ARG, "index out of range"};
+        r = p.cl[p.near[index].t].size;
+        c = p.cl[p.near[index].s].size;
+        src = (const z64*)h->near_d + h->near_off[index];
+        break;
+      }
+      case DH2_INSPECT_LEAF_BASIS: {
+        if (index < 0 || index >= ns || h->V_off[index] < 0) throw Fail{DH2_ERR_ARG, "not a leaf slot"};
+        r = p.cl[p.slots[index].t].size;
+        c = k;
+        src = (const z64*)h->V_d + h->V_off[index];
+        break;
+      }
+      case DH2_INSPECT_TRANSFER: {
+        const int64_t q = index / 2;
+        if (index < 0 || q >= ns || h->E_off[q] < 0) throw Fail{DH2_ERR_ARG, "not an inner slot"};
+        r = k;
+        c = k;
+        src = (const z64*)h->E_d + h->E_off[q] + (index % 2) * (int64_t)k * k;
+        break;
+      }
+      case DH2_INSPECT_RANK_ROW:
+      case DH2_INSPECT_RANK_COL: {
+        const auto& rk = what == DH2_INSPECT_RANK_ROW ? h->rank_row : h->rank_col;
+        r = ns;
+        c = 1;
+        host.resize(2 * ns);
+        for (int64_t q = 0; q < ns; ++q) {
+          host[2 * q] = rk[q];
+          host[2 * q + 1] = 0;
+        }
+        break;
+      }
+      case DH2_INSPECT_SIGMA_ROW:
+      case DH2_INSPECT_SIGMA_COL: {
+        if (index < 0 || index >= ns) throw Fail{DH2_ERR_ARG, "index out of range"};
+        const auto& sg = (what == DH2_INSPECT_SIGMA_ROW ? h->sig_row : h->sig_col)[index];
+        r = (int64_t)sg.size();
+        c = 1;
+        host.resize(2 * r);
+        for (int64_t i = 0; i < r; ++i) {
+          host[2 * i] = sg[i];
+          host[2 * i + 1] = 0;
+        }
+        break;
+      }
+      case DH2_INSPECT_BASIS_WEIGHT:
+      case DH2_INSPECT_TOTAL_WEIGHT_ROW:
+      case DH2_INSPECT_TOTAL_WEIGHT_COL: {
+        if (index < 0 || index >= ns) throw Fail{DH2_ERR_ARG, "index out of range"};
+        const z64* base = what == DH2_INSPECT_BASIS_WEIGHT ? h->R_d
+                          : what == DH2_INSPECT_TOTAL_WEIGHT_ROW ? h->Zr_d : h->Zc_d;
+        const auto& rows = what == DH2_INSPECT_BASIS_WEIGHT ? h->rR
+                           : what == DH2_INSPECT_TOTAL_WEIGHT_ROW ? h->rZr : h->rZc;
+        r = rows[index];
+        c = k;
+        // rows of a k x k column-major buffer: copy column by column
+        if (out && r > 0) {
+          HIPCHK(hipStreamSynchronize(h->stream));
+          std::vector<z64> full((size_t)k * k);
+          HIPCHK(hipMemcpy(full.data(), base + (size_t)index * k * k, full.size() * sizeof(z64),
+                           hipMemcpyDeviceToHost));
+          host.resize((size_t)2 * r * c);
+          for (int64_t j = 0; j < c; ++j)
+            for (int64_t i = 0; i < r; ++i) {
+              host[2 * (i + j * r)] = full[i + j * k].x;
+              host[2 * (i + j * r) + 1] = full[i + j * k].y;
+            }
+        }
+        break;
+      }
+      case DH2_INSPECT_COUPLING: {
+        if (index < 0 || index >= (int64_t)p.adm.size()) throw Fail{DH2_ERR_ARG, "index out of range"};
+        r = k;
+        c = k;
+        if (out) {
+          const AdmBlock& a = p.adm[index];
+          std::vector<CoupDesc> cd{{(int32_t)a.t, (int32_t)a.s, h->dir_off[p.cl[a.t].level] + a.c}};
+          CoupDesc* cdd = h->upload(cd);
+          z64* S = h->alloc<z64>((size_t)k * k);
+          launch_coupling<double>(cdd, 1, h->cheb, p.kappa, h->box_d, h->dirs_d, S, h->stream);
+          HIPCHK(hipGetLastError());
+          h->sync();
+          host.resize((size_t)2 * k * k);
+          HIPCHK(hipMemcpy(host.data(), S, (size_t)k * k * sizeof(z64), hipMemcpyDeviceToHost));
+          h->release(S);
+          h->release(cdd);
+        }
+        break;
+      }
+      case DH2_INSPECT_OMEGA: {
+        r = (int64_t)h->omega.size();
+        c = 1;
+        host.resize(2 * r);
+        for (int64_t i = 0; i < r; ++i) {
+          host[2 * i] = h->omega[i];
+          host[2 * i + 1] = 0;
+        }
+        break;
+      }
+      default:
+        throw Fail{DH2_ERR_ARG, "unknown inspection target"};
+    }
+    *rows = r;
+    *cols = c;
+    if (out && r * c > 0) {
+      if (src) {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipMemcpy(out, src, (size_t)r * c * 16, hipMemcpyDeviceToHost));
+      } else {
+        std::memcpy(out, host.data(), host.size() * sizeof(double));
+      }
+    }
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+  return DH2_OK;
+}
+
+// ---------------------------------------------------------------------------
+dh2_status dh2_plan_create(const dh2_geometry* geometry, double kappa, int order, double eta,
+                           int leafsize, double eta1, dh2_plan* out) {
+  g_err.clear();
+  if (!out) {
+    g_err = "out is NULL";
+    return DH2_ERR_ARG;
+  }
+  *out = nullptr;
+  try {
+    validate(geometry, kappa, order, eta, leafsize, 0.0, eta1 > 0 ? eta1 : 10.0);
+    std::unique_ptr<dh2_plan_s> p(new dh2_plan_s());
+    std::string err = build_plan(geometry->vertices, geometry->n_vertices, geometry->triangles,
+                                 geometry->n_triangles, kappa, order, eta, leafsize,
+                                 eta1 > 0 ? eta1 : 10.0, p->plan);
+    if (!err.empty()) throw Fail{DH2_ERR_ARG, err};
+    *out = p.release();
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return DH2_ERR_OOM;
+  }
+  return DH2_OK;
+}
+
+dh2_status dh2_plan_get_sizes(dh2_plan pl, dh2_plan_sizes* s) {
+  if (!pl || !s) {
+    g_err = "NULL argument";
+    return DH2_ERR_ARG;
+  }
+  const Plan& p = pl->plan;
+  s->n = p.n;
+  s->n_clusters = (int64_t)p.cl.size();
+  s->depth = p.depth;
+  s->n_adm = (int64_t)p.adm.size();
+  s->n_near = (int64_t)p.near.size();
+  int64_t nd = 0;
+  for (const auto& d : p.dirs) nd += (int64_t)d.size() / 3;
+  s->n_dirs_total = nd;
+  s->n_slots = (int64_t)p.slots.size();
+  return DH2_OK;
+}
+
+dh2_status dh2_plan_export(dh2_plan pl, int64_t* perm, int64_t* cl_first, int64_t* cl_size,
+                           int32_t* cl_level, int64_t* cl_parent, double* cl_box,
+                           int32_t* level_ndirs, double* dirs, int32_t* sd, int64_t* adm,
+                           int64_t* near, int64_t* slots) {
+  if (!pl) {
+    g_err = "NULL plan";
+    return DH2_ERR_ARG;
+  }
+  const Plan& p = pl->plan;
+  if (perm) std::copy(p.perm.begin(), p.perm.end(), perm);
+  for (size_t t = 0; t < p.cl.size(); ++t) {
+    const Cluster& c = p.cl[t];
+    if (cl_first) cl_first[t] = c.first;
+    if (cl_size) cl_size[t] = c.size;
+    if (cl_level) cl_level[t] = c.level;
+    if (cl_parent) cl_parent[t] = c.parent;
+    if (cl_box)
+      for (int d = 0; d < 3; ++d) {
+        cl_box[6 * t + d] = c.lo[d];
+        cl_box[6 * t + 3 + d] = c.hi[d];
+      }
+  }
+  int64_t off = 0;
+  for (int l = 0; l <= p.depth; ++l) {
+    const int64_t nd = (int64_t)p.dirs[l].size() / 3;
+    if (level_ndirs) level_ndirs[l] = (int32_t)nd;
+    for (int64_t c = 0; c < nd; ++c) {
+      if (dirs)
+        for (int d = 0; d < 3; ++d) dirs[3 * (off + c) + d] = p.dirs[l][3 * c + d];
+      if (sd) sd[off + c] = l < p.depth ? p.sd[l][c] : -1;
+    }
+    off += nd;
+  }
+  for (size_t b = 0; b < p.adm.size(); ++b)
+    if (adm) {
+      adm[3 * b] = p.adm[b].t;
+      adm[3 * b + 1] = p.adm[b].s;
+      adm[3 * b + 2] = p.adm[b].c;
+    }
+  for (size_t b = 0; b < p.near.size(); ++b)
+    if (near) {
+      near[2 * b] = p.near[b].t;
+      near[2 * b + 1] = p.near[b].s;
+    }
+  for (size_t q = 0; q < p.slots.size(); ++q)
+    if (slots) {
+      slots[3 * q] = p.slots[q].t;
+      slots[3 * q + 1] = p.slots[q].c;
+      slots[3 * q + 2] = (p.slot_row[q] ? 1 : 0) | (p.slot_col[q] ? 2 : 0);
+    }
+  return DH2_OK;
+}
+
+void dh2_plan_free(dh2_plan p) { delete p; }
+
+}  // extern "C"

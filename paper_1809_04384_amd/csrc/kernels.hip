@@ -1,0 +1,760 @@
+// HIP kernels of the DH^2 build (gfx950, wave64).  Each kernel cites the part
+// of Boerm & Boerst (arXiv 1809.04384) it computes.  Complex data is
+// interleaved (re, im); matrices are column-major unless stated.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+namespace dh2 {
+
+// ---------------------------------------------------------------------------
+// Per-triangle data (Section 5: piecewise-constant basis on flat triangles).
+// Triangle at cluster position p is user triangle perm[p].  Outputs in
+// cluster order: 7-point and 16-point quadrature points / weights and the
+// closed-form Laplace self integral int_T int_T 1/|x-y| divided by 4 pi:
+//   (4 A^2 / 3) sum_e (1/l_e) log(L / (L - 2 l_e)),  L = perimeter.
+__global__ void k_tri_data(int64_t n, const double* __restrict__ V, const int32_t* __restrict__ T,
+                           const int64_t* __restrict__ perm, QuadTab qt, double* __restrict__ x7,
+                           double* __restrict__ w7, double* __restrict__ x16,
+                           double* __restrict__ w16, double* __restrict__ self_lap) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t u = perm[p];
+  double P[3][3];
+  for (int v = 0; v < 3; ++v)
+    for (int d = 0; d < 3; ++d) P[v][d] = V[3 * (int64_t)T[3 * u + v] + d];
+  double e1[3], e2[3];
+  for (int d = 0; d < 3; ++d) {
+    e1[d] = P[1][d] - P[0][d];
+    e2[d] = P[2][d] - P[0][d];
+  }
+  const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+  const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+  const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+  const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+  for (int q = 0; q < 7; ++q) {
+    for (int d = 0; d < 3; ++d)
+      x7[(p * 7 + q) * 3 + d] = qt.b7[q][0] * P[0][d] + qt.b7[q][1] * P[1][d] + qt.b7[q][2] * P[2][d];
+    w7[p * 7 + q] = area * qt.w7[q];
+  }
+  for (int q = 0; q < 16; ++q) {
+    for (int d = 0; d < 3; ++d)
+      x16[(p * 16 + q) * 3 + d] =
+          qt.b16[q][0] * P[0][d] + qt.b16[q][1] * P[1][d] + qt.b16[q][2] * P[2][d];
+    w16[p * 16 + q] = area * qt.w16[q];
+  }
+  double l[3];
+  for (int e = 0; e < 3; ++e) {
+    const int a = (e + 1) % 3, b = (e + 2) % 3;
+    const double dx = P[a][0] - P[b][0], dy = P[a][1] - P[b][1], dz = P[a][2] - P[b][2];
+    l[e] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  const double L = l[0] + l[1] + l[2];
+  double s = 0.0;
+  for (int e = 0; e < 3; ++e) s += log(L / (L - 2.0 * l[e])) / l[e];
+  self_lap[p] = (4.0 * area * area / 3.0) * s * (0.25 / M_PI);
+}
+
+// ---------------------------------------------------------------------------
+// Near field (Definition of the DH^2 representation: inadmissible leaves are
+// stored as dense arrays).  Entry (i,j) of block t x s:
+//   i != j: sum_{p,q<16} w_i,p w_j,q g(x_i,p, y_j,q),  g = exp(i kappa r) / (4 pi r)
+//   i == j: Laplace closed form + sum w w rho(r), rho(r) = (exp(i kappa r) - 1) / r,
+//           rho(0) = i kappa (singularity subtraction).
+// One workgroup per block, one thread per entry; the 16-point data is read
+// through the caches.  Output column-major, leading dimension #t.
+template <typename R>
+__global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ blocks, double kappa,
+                                              const double* __restrict__ x16,
+                                              const double* __restrict__ w16,
+                                              const double* __restrict__ self_lap,
+                                              cpx<R>* __restrict__ out) {
+  const NearDesc d = blocks[blockIdx.x];
+  const int64_t total = (int64_t)d.nr * d.nc;
+  const R kap = (R)kappa;
+  const R inv4pi = (R)(0.25 / M_PI);
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = (int)(e % d.nr);
+    const int j = (int)(e / d.nr);
+    const int64_t gi = d.row0 + i, gj = d.col0 + j;
+    const double* xi = x16 + gi * 48;
+    const double* xj = x16 + gj * 48;
+    const double* wi = w16 + gi * 16;
+    const double* wj = w16 + gj * 16;
+    R sre = 0, sim = 0;
+    if (gi != gj) {
+      for (int p = 0; p < 16; ++p) {
+        const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
+        R accr = 0, acci = 0;
+        for (int q = 0; q < 16; ++q) {
+          const R dx = (R)(ax - xj[3 * q]), dy = (R)(ay - xj[3 * q + 1]), dz = (R)(az - xj[3 * q + 2]);
+          const R r = sqrt_r(dx * dx + dy * dy + dz * dz);
+          R sn, cs;
+          sincos_r(kap * r, &sn, &cs);
+          const R f = (R)wj[q] / r;
+          accr += f * cs;
+          acci += f * sn;
+        }
+        sre += (R)wi[p] * accr;
+        sim += (R)wi[p] * acci;
+      }
+      sre *= inv4pi;
+      sim *= inv4pi;
+    } else {
+      for (int p = 0; p < 16; ++p) {
+        const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
+        for (int q = 0; q < 16; ++q) {
+          const R w = (R)(wi[p] * wj[q]);
+          const R dx = (R)(ax - xj[3 * q]), dy = (R)(ay - xj[3 * q + 1]), dz = (R)(az - xj[3 * q + 2]);
+          const R r = sqrt_r(dx * dx + dy * dy + dz * dz);
+          if (r == (R)0) {
+            sim += w * kap;
+          } else {
+            R sh, ch, sn, cs;
+            sincos_r((R)0.5 * kap * r, &sh, &ch);
+            sincos_r(kap * r, &sn, &cs);
+            sre += w * ((R)-2 * sh * sh) / r;
+            sim += w * sn / r;
+          }
+        }
+      }
+      sre = (R)self_lap[gi] + sre * inv4pi;
+      sim = sim * inv4pi;
+    }
+    out[d.off + e] = cpx<R>{sre, sim};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf bases (Section 2): V_tc[i,nu] = sum_{q<7} w_q exp(i kappa <x_q,c>) L_{t,nu}(x_q)
+// for the triangles i of leaf t.  Output #t x k, column-major.
+template <typename R>
+__global__ void __launch_bounds__(256) k_leaf_basis(const LeafDesc* __restrict__ dd, ChebTab ct,
+                                                    double kappa, const double* __restrict__ x7,
+                                                    const double* __restrict__ w7,
+                                                    const double* __restrict__ box,
+                                                    const double* __restrict__ dirs,
+                                                    cpx<R>* __restrict__ out) {
+  const LeafDesc d = dd[blockIdx.x];
+  const int m = ct.m;
+  const int k = m * m * m;
+  const double lo[3] = {box[6 * d.cl], box[6 * d.cl + 1], box[6 * d.cl + 2]};
+  const double hi[3] = {box[6 * d.cl + 3], box[6 * d.cl + 4], box[6 * d.cl + 5]};
+  const double c[3] = {dirs[3 * d.dir], dirs[3 * d.dir + 1], dirs[3 * d.dir + 2]};
+  const int64_t total = (int64_t)d.nr * k;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = (int)(e % d.nr);
+    const int nu = (int)(e / d.nr);
+    const int jx = nu % m, jy = (nu / m) % m, jz = nu / (m * m);
+    const int64_t g = d.row0 + i;
+    double sre = 0, sim = 0;
+    for (int q = 0; q < 7; ++q) {
+      const double* x = x7 + (g * 7 + q) * 3;
+      double Lx[kMaxOrder], Ly[kMaxOrder], Lz[kMaxOrder];
+      lagrange<double>(ct, to_ref(x[0], lo[0], hi[0]), Lx);
+      lagrange<double>(ct, to_ref(x[1], lo[1], hi[1]), Ly);
+      lagrange<double>(ct, to_ref(x[2], lo[2], hi[2]), Lz);
+      const double L = Lx[jx] * Ly[jy] * Lz[jz];
+      double sn, cs;
+      sincos(kappa * (x[0] * c[0] + x[1] * c[1] + x[2] * c[2]), &sn, &cs);
+      const double f = w7[g * 7 + q] * L;
+      sre += f * cs;
+      sim += f * sn;
+    }
+    out[d.off + e] = cpx<R>{(R)sre, (R)sim};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transfer matrices (eq. (nested_apx)): for child t' of t, direction c of t,
+// c' = sd(c): E_{t'c}[nu',nu] = exp(i kappa <xi_{t'nu'}, c - c'>) L_{t,nu}(xi_{t'nu'}).
+// Output k x k column-major.
+template <typename R>
+__global__ void __launch_bounds__(256) k_transfer(const TransDesc* __restrict__ dd, ChebTab ct,
+                                                  double kappa, const double* __restrict__ box,
+                                                  const double* __restrict__ dirs,
+                                                  cpx<R>* __restrict__ out) {
+  const TransDesc d = dd[blockIdx.x];
+  const int m = ct.m;
+  const int k = m * m * m;
+  const double* bp = box + 6 * d.parent;
+  const double* bc = box + 6 * d.child;
+  double dc[3];
+  for (int a = 0; a < 3; ++a) dc[a] = dirs[3 * d.dir_parent + a] - dirs[3 * d.dir_child + a];
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+    const int nu1 = (int)(e % k);   // row: child point
+    const int nu = (int)(e / k);    // column: parent polynomial
+    const int ix = nu1 % m, iy = (nu1 / m) % m, iz = nu1 / (m * m);
+    const double xi[3] = {axis_point(ct, bc[0], bc[3], ix), axis_point(ct, bc[1], bc[4], iy),
+                          axis_point(ct, bc[2], bc[5], iz)};
+    const int jx = nu % m, jy = (nu / m) % m, jz = nu / (m * m);
+    double Lx[kMaxOrder], Ly[kMaxOrder], Lz[kMaxOrder];
+    lagrange<double>(ct, to_ref(xi[0], bp[0], bp[3]), Lx);
+    lagrange<double>(ct, to_ref(xi[1], bp[1], bp[4]), Ly);
+    lagrange<double>(ct, to_ref(xi[2], bp[2], bp[5]), Lz);
+    const double L = Lx[jx] * Ly[jy] * Lz[jz];
+    double sn, cs;
+    sincos(kappa * (xi[0] * dc[0] + xi[1] * dc[1] + xi[2] * dc[2]), &sn, &cs);
+    out[d.off + e] = cpx<R>{(R)(L * cs), (R)(L * sn)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coupling matrices (Section 2): S_b[nu,mu] = g_c(xi_{t,nu}, xi_{s,mu}),
+// g_c(x,y) = exp(i kappa (|x-y| - <x-y,c>)) / (4 pi |x-y|).  One workgroup per
+// block of the batch; output k x k column-major at out + item * k * k.
+template <typename R>
+__global__ void __launch_bounds__(256) k_coupling(const CoupDesc* __restrict__ dd, ChebTab ct,
+                                                  double kappa, const double* __restrict__ box,
+                                                  const double* __restrict__ dirs,
+                                                  cpx<R>* __restrict__ out) {
+  const CoupDesc d = dd[blockIdx.x];
+  const int m = ct.m;
+  const int k = m * m * m;
+  const double* bt = box + 6 * d.t;
+  const double* bs = box + 6 * d.s;
+  const double c[3] = {dirs[3 * d.dir], dirs[3 * d.dir + 1], dirs[3 * d.dir + 2]};
+  __shared__ double pt[3][kMaxOrder], ps[3][kMaxOrder];
+  if (threadIdx.x < 3 * m) {
+    const int a = threadIdx.x / m, j = threadIdx.x % m;
+    pt[a][j] = axis_point(ct, bt[a], bt[a + 3], j);
+    ps[a][j] = axis_point(ct, bs[a], bs[a + 3], j);
+  }
+  __syncthreads();
+  cpx<R>* o = out + (int64_t)blockIdx.x * k * k;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int nu = e % k, mu = e / k;
+    const double dx = pt[0][nu % m] - ps[0][mu % m];
+    const double dy = pt[1][(nu / m) % m] - ps[1][(mu / m) % m];
+    const double dz = pt[2][nu / (m * m)] - ps[2][mu / (m * m)];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double sn, cs;
+    sincos(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
+    const double f = 0.25 / M_PI / r;
+    o[e] = cpx<R>{(R)(f * cs), (R)(f * sn)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex GEMM, C = alpha op(A) op(B) (+ C if accumulate), op in
+// {N, T, C (conjugate transpose)}.  32 x 32 output tile per workgroup of 256
+// threads (2 x 2 outputs each), K staged through LDS in slices of 16.
+template <typename R>
+__global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, int ntm) {
+  const GemmDesc d = dd[blockIdx.y];
+  const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
+  const int m0 = tm * 32, n0 = tn * 32;
+  if (m0 >= d.M || n0 >= d.N) return;
+  const cpx<R>* A = (const cpx<R>*)d.A;
+  const cpx<R>* B = (const cpx<R>*)d.B;
+  cpx<R>* C = (cpx<R>*)d.C;
+  __shared__ cpx<R> As[16][33];
+  __shared__ cpx<R> Bs[16][33];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  cpx<R> acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = cpx<R>{0, 0};
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 512; e += 256) {
+      // A slice: rows m0..m0+31 of op(A), columns k0..k0+15
+      const int i = e % 32, kk = e / 32;
+      const int gi = m0 + i, gk = k0 + kk;
+      cpx<R> v{0, 0};
+      if (gi < d.M && gk < d.K) {
+        if (d.opA == 0) v = A[gi + (int64_t)gk * d.lda];
+        else {
+          v = A[gk + (int64_t)gi * d.lda];
+          if (d.opA == 2) v = conj(v);
+        }
+      }
+      As[kk][i] = v;
+      // B slice: rows k0..k0+15 of op(B), columns n0..n0+31
+      const int kb = e % 16, j = e / 16;
+      const int gkb = k0 + kb, gj = n0 + j;
+      cpx<R> w{0, 0};
+      if (gkb < d.K && gj < d.N) {
+        if (d.opB == 0) w = B[gkb + (int64_t)gj * d.ldb];
+        else {
+          w = B[gj + (int64_t)gkb * d.ldb];
+          if (d.opB == 2) w = conj(w);
+        }
+      }
+      Bs[kb][j] = w;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      const cpx<R> a0 = As[kk][tx], a1 = As[kk][tx + 16];
+      const cpx<R> b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
+      cfma(acc[0][0], a0, b0);
+      cfma(acc[0][1], a0, b1);
+      cfma(acc[1][0], a1, b0);
+      cfma(acc[1][1], a1, b1);
+    }
+    __syncthreads();
+  }
+  const cpx<R> al{(R)d.alpha_re, (R)d.alpha_im};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int gi = m0 + tx + 16 * a, gj = n0 + ty + 16 * b;
+      if (gi < d.M && gj < d.N) {
+        const cpx<R> v = al * acc[a][b];
+        cpx<R>& dst = C[gi + (int64_t)gj * d.ldc];
+        dst = d.accumulate ? dst + v : v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Householder fold (FP64): R <- R factor of [R; P_1; P_2; ...] for an n x n
+// upper triangular R (column-major, leading dimension ldr) and pieces P
+// (rows x n, column-major).  This is the QR step of the basis weights
+// (eq. (basis_weights_def)) and of the total weights (skinny QR of Z_tc^*,
+// eq. (recomp_weight_full)); only R is kept, as in the paper.
+// Column j: x = (R[j,j], P[:,j]); beta = -phase(R[j,j]) |x| with |x| taken
+// through a max-abs scale; d = R[j,j] - beta, u = (1, P[:,j] / d),
+// tau = (beta - R[j,j]) / beta; H = I - tau u u^H satisfies H^H x = beta e_0
+// and is applied as H^H to the remaining columns.  |u_i| <= 1 and
+// 1 <= |tau| <= 2, so no intermediate is squared: bases with columns many
+// orders of magnitude below the others (flat boxes) stay exact.  A column
+// whose remaining entries are below 1e-14 of the staged rows' maximum is
+// skipped (rounding residue of a rank-deficient piece), so the number of
+// nonzero rows stays at the numerical rank.
+// Rows of the current piece are staged in LDS (row-major, CH rows).
+template <typename PT>
+__global__ void __launch_bounds__(256) k_fold(const FoldTask* __restrict__ tasks,
+                                              const FoldPiece* __restrict__ pieces, int ch) {
+  extern __shared__ double lds_raw[];
+  const FoldTask tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  z64* R = (z64*)tk.R;
+  z64* P = (z64*)lds_raw;                     // [ch][n]
+  __shared__ z64 s_tauc;                      // conj(tau)
+  __shared__ int s_skip;
+  __shared__ double s_wmax[4];
+  const int tid = threadIdx.x;
+  if (tk.init_zero)
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      R[i + (int64_t)j * tk.ldr] = z64{0, 0};
+    }
+  __syncthreads();
+  for (int pc = tk.piece_begin; pc < tk.piece_end; ++pc) {
+    const FoldPiece pp = pieces[pc];
+    const cpx<PT>* src = (const cpx<PT>*)pp.P;
+    for (int r0 = 0; r0 < pp.rows; r0 += ch) {
+      const int p = min(ch, pp.rows - r0);
+      double lmax = 0.0;
+      for (int e = tid; e < p * n; e += 256) {
+        const int i = e % p, j = e / p;
+        const cpx<PT> v = src[(r0 + i) + (int64_t)j * pp.ld];
+        P[i * n + j] = z64{(double)v.x, (double)v.y};
+        lmax = fmax(lmax, fmax(fabs((double)v.x), fabs((double)v.y)));
+      }
+      for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+      if ((tid & 63) == 0) s_wmax[tid >> 6] = lmax;
+      __syncthreads();
+      // columns whose remaining entries are at rounding level of the staged rows
+      // are left alone: they carry no information and would only add noise rows
+      const double skip_below = 1e-14 * fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
+      for (int j = 0; j < n; ++j) {
+        // reflector of column j: wave 0, every lane computes the same scalars
+        if (tid < 64) {
+          double mx = 0.0;
+          for (int i = tid; i < p; i += 64) {
+            const z64 v = P[i * n + j];
+            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+          }
+          for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+          if (mx <= skip_below) {
+            if (tid == 0) s_skip = 1;
+          } else {
+            const z64 a = R[j + (int64_t)j * tk.ldr];
+            const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
+            const double inv = 1.0 / scale;
+            double part = 0.0;
+            for (int i = tid; i < p; i += 64) {
+              const z64 v = P[i * n + j];
+              part += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
+            }
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            const z64 as{a.x * inv, a.y * inv};
+            const double aas = sqrt(abs2(as));
+            const double sig_s = sqrt(aas * aas + part);          // |x| / scale
+            const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
+            const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
+            const z64 d_s = as - beta_s;                           // |d_s| = aas + sig_s
+            // u_i = P_ij / d = (P_ij / scale) / d_s
+            const double dd = 1.0 / abs2(d_s);
+            const z64 dinv{d_s.x * dd, -d_s.y * dd};
+            for (int i = tid; i < p; i += 64) {
+              const z64 v = P[i * n + j];
+              P[i * n + j] = z64{v.x * inv, v.y * inv} * dinv;
+            }
+            if (tid == 0) {
+              // tau = (beta - a) / beta = -d_s / beta_s
+              const double bb = 1.0 / abs2(beta_s);
+              const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
+              s_tauc = conj(tau);
+              s_skip = 0;
+              R[j + (int64_t)j * tk.ldr] = z64{beta_s.x * scale, beta_s.y * scale};
+            }
+          }
+        }
+        __syncthreads();
+        if (!s_skip) {
+          const z64 tc = s_tauc;
+          for (int jj = j + 1 + tid; jj < n; jj += 256) {
+            z64* rj = &R[j + (int64_t)jj * tk.ldr];
+            z64 w = *rj;
+            for (int i = 0; i < p; ++i) cfmac(w, P[i * n + j], P[i * n + jj]);
+            const z64 tw = tc * w;
+            *rj = *rj - tw;
+            for (int i = 0; i < p; ++i) P[i * n + jj] = P[i * n + jj] - P[i * n + j] * tw;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  if (tk.compact) {
+    // A row is filled iff its diagonal is nonzero: reflectors write beta != 0
+    // there and never touch rows they skip.  Filled rows are independent (upper
+    // triangular with nonzero pivots), so there are at most rank <= folded rows
+    // of them; move them to the top in pivot order and clear the rest.
+    __shared__ int s_rows[kMaxOrder * kMaxOrder * kMaxOrder];
+    __shared__ int s_cnt;
+    if (tid == 0) {
+      int c = 0;
+      for (int j = 0; j < n; ++j) {
+        const z64 dg = R[j + (int64_t)j * tk.ldr];
+        if (dg.x != 0.0 || dg.y != 0.0) s_rows[c++] = j;
+      }
+      s_cnt = c;
+      if (tk.count) *tk.count = c;
+    }
+    __syncthreads();
+    const int c = s_cnt;
+    for (int jj = tid; jj < n; jj += 256) {
+      for (int r = 0; r < c; ++r) {
+        const int i = s_rows[r];
+        if (i != r) R[r + (int64_t)jj * tk.ldr] = R[i + (int64_t)jj * tk.ldr];
+      }
+      for (int r = c; r < n; ++r) R[r + (int64_t)jj * tk.ldr] = z64{0, 0};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Truncation SVD (FP64): left singular vectors and singular values of
+// A = B^H from the m x m upper triangular B (the R factor of A^H), by
+// one-sided (Hestenes) Jacobi on the columns of B with round-robin pairs; the
+// accumulated rotations are the left singular vectors of A.  The rank rule
+// (smallest k with sum_{i>k} sigma_i^2 <= eps^2, or sigma_{k+1} <= eps) is
+// applied in the epilogue (Section 3.1: lowest rank meeting the bound).
+// The input is scaled by a power of two to unit magnitude, and rotations with
+// a numerically zero column are skipped, so no product of tiny quantities
+// reaches the subnormal range (where the rotation phase would lose its bits).
+// Workspace: 2 m^2 complex (B and V), in LDS when lds != 0, else in global
+// scratch given by the task.
+__global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ tasks, int use_lds) {
+  extern __shared__ double lds_raw[];
+  const SvdTask tk = tasks[blockIdx.x];
+  const int m = tk.m;
+  const int mp = (m + 1) & ~1;   // padded to even
+  z64* B = use_lds ? (z64*)lds_raw : (z64*)tk.scratch;
+  z64* V = B + (int64_t)m * m;
+  __shared__ int s_pos[512];
+  __shared__ int s_rot;
+  __shared__ double s_sig[256];
+  __shared__ int s_ord[256];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  __shared__ double s_wmax[4];
+  const z64* Bin = (const z64*)tk.B;
+  double lmax = 0.0;
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    const z64 v = Bin[i + (int64_t)j * tk.ldb];
+    lmax = fmax(lmax, fmax(fabs(v.x), fabs(v.y)));
+  }
+  for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+  if (lane == 0) s_wmax[wave] = lmax;
+  __syncthreads();
+  // exact power-of-two scaling to unit magnitude; sigma is scaled back at the end
+  int sexp = 0;
+  {
+    const double mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
+    if (mx > 0.0) frexp(mx, &sexp);
+  }
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    const z64 v = Bin[i + (int64_t)j * tk.ldb];
+    B[e] = z64{ldexp(v.x, -sexp), ldexp(v.y, -sexp)};
+    V[e] = z64{i == j ? 1.0 : 0.0, 0.0};
+  }
+  for (int i = tid; i < mp; i += 256) s_pos[i] = i;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < mp - 1; ++round) {
+      for (int pr = wave; pr < mp / 2; pr += 4) {
+        int p = s_pos[pr], q = s_pos[mp - 1 - pr];
+        if (p >= m || q >= m) continue;
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double a = 0, b = 0;
+        z64 g{0, 0};
+        for (int i = lane; i < m; i += 64) {
+          const z64 bp = B[i + p * m], bq = B[i + q * m];
+          a += abs2(bp);
+          b += abs2(bq);
+          cfmac(g, bp, bq);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off);
+          b += __shfl_xor(b, off);
+          g.x += __shfl_xor(g.x, off);
+          g.y += __shfl_xor(g.y, off);
+        }
+        // columns at or below 1e-100 of unit scale are numerically zero; the
+        // test |g| <= 1e-15 |b_p| |b_q| uses the norms, whose product cannot
+        // underflow here, so the phase g / |g| below stays exact
+        if (fmin(a, b) <= 1e-200) continue;
+        const double ag = sqrt(abs2(g));
+        if (ag <= 1e-15 * sqrt(a) * sqrt(b)) continue;
+        const double zeta = (b - a) / (2.0 * ag);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = c * t;
+        const z64 e{g.x / ag, -g.y / ag};   // exp(-i phi), phi = arg g
+        for (int i = lane; i < m; i += 64) {
+          const z64 bp = B[i + p * m], bq = B[i + q * m];
+          const z64 ebq = e * bq;
+          B[i + p * m] = z64{c * bp.x - s * ebq.x, c * bp.y - s * ebq.y};
+          B[i + q * m] = z64{s * bp.x + c * ebq.x, s * bp.y + c * ebq.y};
+          const z64 vp = V[i + p * m], vq = V[i + q * m];
+          const z64 evq = e * vq;
+          V[i + p * m] = z64{c * vp.x - s * evq.x, c * vp.y - s * evq.y};
+          V[i + q * m] = z64{s * vp.x + c * evq.x, s * vp.y + c * evq.y};
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+      if (tid == 0) {  // rotate all positions but the first
+        const int last = s_pos[mp - 1];
+        for (int i = mp - 1; i > 1; --i) s_pos[i] = s_pos[i - 1];
+        s_pos[1] = last;
+      }
+      __syncthreads();
+    }
+    if (!s_rot) break;
+    __syncthreads();
+  }
+  // singular values = column norms of B, sorted descending (stable)
+  for (int j = wave; j < m; j += 4) {
+    double a = 0;
+    for (int i = lane; i < m; i += 64) a += abs2(B[i + j * m]);
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) s_sig[j] = ldexp(sqrt(a), sexp);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < m; ++j) s_ord[j] = j;
+    for (int j = 0; j < m; ++j) {
+      int best = j;
+      for (int l = j + 1; l < m; ++l)
+        if (s_sig[s_ord[l]] > s_sig[s_ord[best]]) best = l;
+      const int t = s_ord[best];
+      for (int l = best; l > j; --l) s_ord[l] = s_ord[l - 1];
+      s_ord[j] = t;
+    }
+    int kk = m;
+    if (tk.norm_mode == 0) {
+      double tail = 0.0;
+      for (int i = m - 1; i >= 0; --i) {
+        const double sv = s_sig[s_ord[i]];
+        tail += sv * sv;
+        if (tail <= tk.eps * tk.eps) kk = i;
+        else break;
+      }
+    } else {
+      while (kk > 0 && s_sig[s_ord[kk - 1]] <= tk.eps) --kk;
+    }
+    *tk.rank = kk;
+    for (int j = 0; j < m; ++j) tk.sig[j] = s_sig[s_ord[j]];
+  }
+  __syncthreads();
+  z64* U = (z64*)tk.U;
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    U[i + (int64_t)j * tk.ldu] = V[i + s_ord[j] * m];
+  }
+}
+
+// Frobenius norms of a batch of matrices (block weights omega_b).
+template <typename R>
+__global__ void __launch_bounds__(256) k_frob(const FrobDesc* __restrict__ dd, double* __restrict__ out) {
+  const FrobDesc d = dd[blockIdx.x];
+  const cpx<R>* A = (const cpx<R>*)d.A;
+  double acc = 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)d.M * d.N; e += 256) {
+    const int i = (int)(e % d.M), j = (int)(e / d.M);
+    const cpx<R> v = A[i + (int64_t)j * d.ld];
+    acc += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[d.index] = sqrt(red[0]);
+}
+
+// Copy of a sub-matrix (column selection / layout change).
+template <typename R>
+__global__ void k_copy(const CopyDesc* __restrict__ dd) {
+  const CopyDesc d = dd[blockIdx.x];
+  const cpx<R>* s = (const cpx<R>*)d.src;
+  cpx<R>* t = (cpx<R>*)d.dst;
+  for (int64_t e = threadIdx.x; e < (int64_t)d.M * d.N; e += blockDim.x) {
+    const int i = (int)(e % d.M), j = (int)(e / d.M);
+    t[i + (int64_t)j * d.ldd] = s[i + (int64_t)j * d.lds];
+  }
+}
+
+// FP64 -> FP32 narrowing of a complex array (basis data of the FP32 form).
+__global__ void k_narrow(const z64* __restrict__ a, z32* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = z32{(float)a[i].x, (float)a[i].y};
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+void launch_tri_data(int64_t n, const double* V, const int32_t* T, const int64_t* perm,
+                     const QuadTab& qt, double* x7, double* w7, double* x16, double* w16,
+                     double* self_lap, hipStream_t st) {
+  hipLaunchKernelGGL(k_tri_data, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, V, T,
+                     perm, qt, x7, w7, x16, w16, self_lap);
+}
+
+template <typename R>
+void launch_near(const NearDesc* d, int64_t nb, double kappa, const double* x16, const double* w16,
+                 const double* self_lap, void* out, hipStream_t st) {
+  for (int64_t b0 = 0; b0 < nb; b0 += 1 << 30) {
+    const int64_t cnt = std::min<int64_t>(nb - b0, 1 << 30);
+    hipLaunchKernelGGL(k_near<R>, dim3((unsigned)cnt), dim3(256), 0, st, d + b0, kappa, x16, w16,
+                       self_lap, (cpx<R>*)out);
+  }
+}
+template void launch_near<double>(const NearDesc*, int64_t, double, const double*, const double*,
+                                  const double*, void*, hipStream_t);
+template void launch_near<float>(const NearDesc*, int64_t, double, const double*, const double*,
+                                 const double*, void*, hipStream_t);
+
+template <typename R>
+void launch_leaf_basis(const LeafDesc* d, int64_t nb, const ChebTab& ct, double kappa,
+                       const double* x7, const double* w7, const double* box, const double* dirs,
+                       void* out, hipStream_t st) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_leaf_basis<R>, dim3((unsigned)nb), dim3(256), 0, st, d, ct, kappa, x7, w7,
+                       box, dirs, (cpx<R>*)out);
+}
+template void launch_leaf_basis<double>(const LeafDesc*, int64_t, const ChebTab&, double,
+                                        const double*, const double*, const double*,
+                                        const double*, void*, hipStream_t);
+
+template <typename R>
+void launch_transfer(const TransDesc* d, int64_t nb, const ChebTab& ct, double kappa,
+                     const double* box, const double* dirs, void* out, hipStream_t st) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_transfer<R>, dim3((unsigned)nb), dim3(256), 0, st, d, ct, kappa, box, dirs,
+                       (cpx<R>*)out);
+}
+template void launch_transfer<double>(const TransDesc*, int64_t, const ChebTab&, double,
+                                      const double*, const double*, void*, hipStream_t);
+
+template <typename R>
+void launch_coupling(const CoupDesc* d, int64_t nb, const ChebTab& ct, double kappa,
+                     const double* box, const double* dirs, void* out, hipStream_t st) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_coupling<R>, dim3((unsigned)nb), dim3(256), 0, st, d, ct, kappa, box, dirs,
+                       (cpx<R>*)out);
+}
+template void launch_coupling<double>(const CoupDesc*, int64_t, const ChebTab&, double,
+                                      const double*, const double*, void*, hipStream_t);
+
+template <typename R>
+void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st) {
+  if (nitems <= 0 || maxM <= 0 || maxN <= 0) return;
+  const int ntm = (maxM + 31) / 32, ntn = (maxN + 31) / 32;
+  for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
+    const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
+    hipLaunchKernelGGL(k_gemm<R>, dim3((unsigned)(ntm * ntn), (unsigned)cnt), dim3(256), 0, st,
+                       d + i0, ntm);
+  }
+}
+template void launch_gemm<double>(const GemmDesc*, int64_t, int, int, hipStream_t);
+template void launch_gemm<float>(const GemmDesc*, int64_t, int, int, hipStream_t);
+
+static size_t g_lds_limit = 65536;   // per-workgroup LDS bytes usable for dynamic buffers
+
+void set_lds_limit(size_t bytes) {
+  // keep 8 KB for the kernels' static shared variables
+  g_lds_limit = bytes > 16384 ? bytes - 8192 : 8192;
+  if (g_lds_limit > 131072) g_lds_limit = 131072;
+}
+
+int fold_rows_per_chunk(int n) {
+  int ch = (int)(g_lds_limit / ((size_t)n * 16));
+  if (ch > 64) ch = 64;
+  if (ch < 1) ch = 1;
+  return ch;
+}
+
+template <typename PT>
+void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, hipStream_t st) {
+  if (ntasks <= 0) return;
+  const int ch = fold_rows_per_chunk(n);
+  const size_t lds = (size_t)ch * n * 16;
+  hipLaunchKernelGGL(k_fold<PT>, dim3((unsigned)ntasks), dim3(256), lds, st, t, p, ch);
+}
+template void launch_fold<double>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
+template void launch_fold<float>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
+
+void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, hipStream_t st) {
+  if (ntasks <= 0) return;
+  const size_t need = (size_t)2 * maxm * maxm * 16;
+  const int use_lds = need <= g_lds_limit ? 1 : 0;
+  hipLaunchKernelGGL(k_jacobi, dim3((unsigned)ntasks), dim3(256), use_lds ? need : 0, st, t, use_lds);
+}
+
+template <typename R>
+void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st) {
+  if (nb > 0) hipLaunchKernelGGL(k_frob<R>, dim3((unsigned)nb), dim3(256), 0, st, d, out);
+}
+template void launch_frob<double>(const FrobDesc*, int64_t, double*, hipStream_t);
+template void launch_frob<float>(const FrobDesc*, int64_t, double*, hipStream_t);
+
+template <typename R>
+void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st) {
+  if (nb > 0) hipLaunchKernelGGL(k_copy<R>, dim3((unsigned)nb), dim3(256), 0, st, d);
+}
+template void launch_copy<double>(const CopyDesc*, int64_t, hipStream_t);
+template void launch_copy<float>(const CopyDesc*, int64_t, hipStream_t);
+
+void launch_narrow(const void* a, void* b, int64_t n, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (const z64*)a, (z32*)b, n);
+}
+
+}  // namespace dh2

@@ -1,0 +1,122 @@
+// Descriptors and launch wrappers of the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dev.hpp"
+
+namespace dh2 {
+
+// quadrature rules as barycentric coordinates + weights summing to one
+struct QuadTab {
+  double b7[7][3];
+  double w7[7];
+  double b16[16][3];
+  double w16[16];
+};
+
+struct NearDesc {     // inadmissible leaf t x s
+  int64_t row0, col0; // first cluster-order position of t and s
+  int32_t nr, nc;
+  int64_t off;        // element offset of the column-major block
+};
+
+struct LeafDesc {     // leaf basis V_tc
+  int64_t row0;
+  int32_t nr;
+  int32_t cl;
+  int64_t dir;        // global direction index (row of the direction table)
+  int64_t off;
+};
+
+struct TransDesc {    // transfer E_{t'c}
+  int32_t child, parent;
+  int64_t dir_parent, dir_child;
+  int64_t off;
+};
+
+struct CoupDesc {     // coupling S_b of block (t, s, c)
+  int32_t t, s;
+  int64_t dir;
+};
+
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int32_t M, N, K, lda, ldb, ldc;
+  int32_t opA, opB;   // 0 = N, 1 = T, 2 = C (conjugate transpose)
+  int32_t accumulate;
+  int32_t pad;
+  double alpha_re, alpha_im;
+};
+
+struct FoldTask {
+  void* R;            // n x n FP64 complex, column-major
+  int32_t n, ldr;
+  int32_t piece_begin, piece_end;
+  int32_t init_zero;  // start from R = 0
+  int32_t compact;    // final fold: move the nonzero rows to the top, zero the rest
+  int32_t* count;     // receives the number of nonzero rows when compacting (may be NULL)
+};
+
+struct FoldPiece {
+  const void* P;      // rows x n complex of the piece precision, column-major
+  int32_t rows, ld;
+};
+
+struct SvdTask {
+  const void* B;      // m x m FP64 complex (R factor of A^H), leading dimension ldb
+  void* U;            // m x m output: left singular vectors of A, sorted
+  double* sig;        // m singular values, descending
+  int32_t* rank;      // chosen rank
+  void* scratch;      // 2 m^2 complex doubles when not in LDS
+  int32_t m, ldb, ldu, norm_mode;
+  double eps;
+};
+
+struct FrobDesc {
+  const void* A;
+  int32_t M, N, ld;
+  int32_t pad;
+  int64_t index;
+};
+
+struct CopyDesc {
+  const void* src;
+  void* dst;
+  int32_t M, N, lds, ldd;
+};
+
+void launch_tri_data(int64_t n, const double* V, const int32_t* T, const int64_t* perm,
+                     const QuadTab& qt, double* x7, double* w7, double* x16, double* w16,
+                     double* self_lap, hipStream_t st);
+template <typename R>
+void launch_near(const NearDesc* d, int64_t nb, double kappa, const double* x16, const double* w16,
+                 const double* self_lap, void* out, hipStream_t st);
+template <typename R>
+void launch_leaf_basis(const LeafDesc* d, int64_t nb, const ChebTab& ct, double kappa,
+                       const double* x7, const double* w7, const double* box, const double* dirs,
+                       void* out, hipStream_t st);
+template <typename R>
+void launch_transfer(const TransDesc* d, int64_t nb, const ChebTab& ct, double kappa,
+                     const double* box, const double* dirs, void* out, hipStream_t st);
+template <typename R>
+void launch_coupling(const CoupDesc* d, int64_t nb, const ChebTab& ct, double kappa,
+                     const double* box, const double* dirs, void* out, hipStream_t st);
+template <typename R>
+void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st);
+void set_lds_limit(size_t bytes);
+int fold_rows_per_chunk(int n);
+template <typename PT>
+void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, hipStream_t st);
+void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, hipStream_t st);
+template <typename R>
+void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st);
+template <typename R>
+void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st);
+void launch_narrow(const void* a, void* b, int64_t n, hipStream_t st);
+
+}  // namespace dh2

@@ -1,0 +1,32 @@
+// Matvec of the compressed matrix: descriptors and launch wrappers (matvec.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dh2 {
+
+// One term of an output: y[i, r] += sum_j op(A)[i, j] x[j + r ldx], j < K.
+struct MvTerm {
+  const void* A;
+  const void* x;
+  int32_t K, lda, ldx, op;   // op: 0 = A, 2 = A^H
+};
+
+// One output matrix y (M x nrhs, leading dimension ldy) and its term range.
+struct MvOut {
+  void* y;
+  int32_t M, ldy;
+  int32_t term_begin, term_end;
+  int32_t accumulate;        // keep the current contents of y
+  int32_t pad;
+};
+
+template <typename R>
+void launch_mv_terms(const MvOut* outs, int64_t nout, const MvTerm* terms, int nrhs, hipStream_t st);
+template <typename R>
+void launch_mv_permute(const void* src, void* dst, const int64_t* perm, int64_t n, int nrhs,
+                       int gather, hipStream_t st);
+
+}  // namespace dh2

@@ -1,0 +1,209 @@
+"""ctypes binding of libdh2.so (C ABI: include/dh2.h).
+
+Argument marshalling only: every computation runs in the native library.
+Device vectors are torch tensors (device memory and streams come from torch);
+host geometry is numpy.  The library must be built first
+(python -m paper_1809_04384_amd.build); loading fails loudly otherwise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdh2.so")
+
+DH2_OK = 0
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_GEOMETRY", 3: "ERR_OOM", 4: "ERR_DEVICE", 5: "ERR_NUMERIC"}
+FP64, FP32 = 0, 1
+INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col": 5,
+           "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
+           "total_weight_row": 10, "total_weight_col": 11, "coupling": 12}
+
+EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_free", "dh2_last_error",
+            "dh2_get_stats", "dh2_plan_create", "dh2_plan_get_sizes", "dh2_plan_export",
+            "dh2_plan_free", "dh2_inspect"]
+
+
+class Dh2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("vertices", ctypes.c_void_p),
+                ("n_triangles", ctypes.c_int64), ("triangles", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("eta1", ctypes.c_double),
+                ("max_nrhs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("workspace_gb", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("k", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("n_clusters", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("depth", ctypes.c_int64), ("n_adm", ctypes.c_int64), ("n_near", ctypes.c_int64),
+                ("n_slots", ctypes.c_int64), ("n_row_slots", ctypes.c_int64),
+                ("n_col_slots", ctypes.c_int64), ("near_entries", ctypes.c_int64),
+                ("coupling_entries", ctypes.c_int64), ("basis_entries", ctypes.c_int64),
+                ("rank_max_row", ctypes.c_int32), ("rank_max_col", ctypes.c_int32),
+                ("rank_mean_row", ctypes.c_double), ("rank_mean_col", ctypes.c_double),
+                ("matvec_bytes", ctypes.c_double), ("matvec_bytes_per_rhs", ctypes.c_double),
+                ("ms_structure", ctypes.c_double), ("ms_near", ctypes.c_double),
+                ("ms_interp", ctypes.c_double), ("ms_basis_weights", ctypes.c_double),
+                ("ms_block_weights", ctypes.c_double), ("ms_total_weights", ctypes.c_double),
+                ("ms_truncation", ctypes.c_double), ("ms_projection", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+class PlanSizes(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in
+                ("n", "n_clusters", "depth", "n_adm", "n_near", "n_dirs_total", "n_slots")]
+
+
+_lib = None
+
+
+def load():
+    """Load libdh2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch provides device memory and streams; loading it first makes libdh2
+    # bind to the same HIP runtime instead of a second copy
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdh2.so not found at %s: build it with "
+                           "python -m paper_1809_04384_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.dh2_build.argtypes = [P, D, I32, D, I32, D, P]
+    lib.dh2_build_ex.argtypes = [P, D, I32, D, I32, D, P, P]
+    lib.dh2_matvec.argtypes = [P, P, P, I32]
+    lib.dh2_free.argtypes = [P]
+    lib.dh2_free.restype = None
+    lib.dh2_last_error.restype = ctypes.c_char_p
+    lib.dh2_get_stats.argtypes = [P, P]
+    lib.dh2_plan_create.argtypes = [P, D, I32, D, I32, D, P]
+    lib.dh2_plan_get_sizes.argtypes = [P, P]
+    lib.dh2_plan_export.argtypes = [P] * 13
+    lib.dh2_plan_free.argtypes = [P]
+    lib.dh2_plan_free.restype = None
+    lib.dh2_inspect.argtypes = [P, I32, I64, P, P, P]
+    for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_get_stats", "dh2_plan_create",
+                 "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != DH2_OK:
+        raise Dh2Error(st, load().dh2_last_error().decode())
+
+
+def _geometry(V, T):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    g = Geometry(V.shape[0], V.ctypes.data, T.shape[0], T.ctypes.data)
+    return g, (V, T)
+
+
+class Plan:
+    """Host-only hierarchy (cluster tree, directions, block tree)."""
+
+    def __init__(self, V, T, kappa, order, eta, leafsize, eta1=10.0):
+        lib = load()
+        g, keep = _geometry(V, T)
+        self._p = ctypes.c_void_p()
+        _check(lib.dh2_plan_create(ctypes.byref(g), kappa, order, eta, leafsize, eta1,
+                                   ctypes.byref(self._p)))
+
+    def export(self):
+        lib = load()
+        s = PlanSizes()
+        _check(lib.dh2_plan_get_sizes(self._p, ctypes.byref(s)))
+        nc, nd = s.n_clusters, s.n_dirs_total
+        out = {
+            "perm": np.empty(s.n, np.int64), "first": np.empty(nc, np.int64),
+            "size": np.empty(nc, np.int64), "level": np.empty(nc, np.int32),
+            "parent": np.empty(nc, np.int64), "box": np.empty((nc, 6)),
+            "level_ndirs": np.empty(s.depth + 1, np.int32), "dirs": np.empty((nd, 3)),
+            "sd": np.empty(nd, np.int32), "adm": np.empty((s.n_adm, 3), np.int64),
+            "near": np.empty((s.n_near, 2), np.int64), "slots": np.empty((s.n_slots, 3), np.int64)}
+        keys = ["perm", "first", "size", "level", "parent", "box", "level_ndirs", "dirs", "sd",
+                "adm", "near", "slots"]
+        _check(lib.dh2_plan_export(self._p, *[out[k].ctypes.data for k in keys]))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_p", None) and _lib is not None:
+            _lib.dh2_plan_free(self._p)
+            self._p = None
+
+
+class Handle:
+    """A built DH^2 matrix on the current HIP device."""
+
+    def __init__(self, V, T, kappa, order, eta, leafsize, tol, eta1=10.0, precision=FP64,
+                 max_nrhs=16, stream=None, workspace_gb=0.0):
+        lib = load()
+        g, keep = _geometry(V, T)
+        opt = Options()
+        opt.size = ctypes.sizeof(Options)
+        opt.precision = precision
+        opt.eta1 = eta1
+        opt.max_nrhs = max_nrhs
+        opt.stream = stream
+        opt.workspace_gb = workspace_gb
+        self.precision = precision
+        self.max_nrhs = max_nrhs
+        self.n = int(np.asarray(T).shape[0])
+        self._h = ctypes.c_void_p()
+        _check(lib.dh2_build_ex(ctypes.byref(g), kappa, order, eta, leafsize, tol,
+                                ctypes.byref(opt), ctypes.byref(self._h)))
+
+    def matvec_ptr(self, x_ptr, y_ptr, nrhs):
+        """Y = Gtilde X for raw device pointers (column-major n x nrhs complex)."""
+        _check(load().dh2_matvec(self._h, x_ptr, y_ptr, nrhs))
+
+    def matvec(self, X, Y):
+        """X, Y: device tensors of shape (nrhs, n), complex128 (FP64) or complex64
+        (FP32), C-contiguous (= column-major n x nrhs)."""
+        import torch
+        want = torch.complex128 if self.precision == FP64 else torch.complex64
+        for A in (X, Y):
+            if A.dtype != want or not A.is_contiguous() or A.dim() != 2 or A.shape[1] != self.n:
+                raise ValueError("X/Y must be contiguous %s tensors of shape (nrhs, %d)" % (want, self.n))
+        if X.shape != Y.shape:
+            raise ValueError("X and Y must have the same shape")
+        self.matvec_ptr(X.data_ptr(), Y.data_ptr(), X.shape[0])
+
+    def stats(self):
+        s = Stats()
+        s.size = ctypes.sizeof(Stats)
+        _check(load().dh2_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "size"}
+
+    def inspect(self, what, index=0):
+        lib = load()
+        r, c = ctypes.c_int64(), ctypes.c_int64()
+        code = INSPECT[what]
+        _check(lib.dh2_inspect(self._h, code, index, None, ctypes.byref(r), ctypes.byref(c)))
+        out = np.empty((c.value, r.value), dtype=np.complex128)   # column-major r x c
+        _check(lib.dh2_inspect(self._h, code, index, out.ctypes.data, ctypes.byref(r), ctypes.byref(c)))
+        return out.T
+
+    def free(self):
+        if getattr(self, "_h", None):
+            load().dh2_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
