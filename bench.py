@@ -1,0 +1,223 @@
+"""Benchmark: DH^2 build + compressed matvec on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere131k]
+
+One step = the whole hot path over one problem: dh2_build (structure, near
+field, interpolation, recompression) followed by the matvec on the workload's
+right-hand sides.  The printed JSON line reports:
+  value        matvec throughput in GB/s (algorithmic bytes: every stored matrix
+               entry read once plus the vectors) with X, Y resident in HBM
+  build_s      wall time of dh2_build (median over the timed steps)
+  roofline     the near-field matvec kernel (the dominant HBM stream) against
+               the MI355X HBM peak, timed with HIP events on its stream
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+               (near-field rows of a few leaf clusters), on the host cores
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "DH² build s + matvec GB/s, n=131k κ=32 at rel.err 1e-4, FP32 vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sphere131k")
+    ap.add_argument("--matvec-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-leaves", type=int, default=3)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, V, T, X, nleaves):
+    """Oracle near-field matvec on the rows of a few leaf clusters (seeded
+    choice), timed on the host.  Returns the baseline object."""
+    from oracle.structure import build_structure
+    from oracle.quadrature import triangle_data
+    from oracle import cquad
+    t0 = time.time()
+    st = build_structure(V, T, w.kappa, w.eta, w.leaf, w.eta1)
+    tri = triangle_data(V, T)
+    t_struct = time.time() - t0
+    leaves = [t for t in range(len(st.first)) if st.is_leaf(t)]
+    rng = np.random.default_rng(2)
+    pick = sorted(rng.choice(len(leaves), size=min(nleaves, len(leaves)), replace=False).tolist())
+    chosen = [leaves[i] for i in pick]
+    # near blocks covering the chosen rows: blocks (t', s) with t' an ancestor-or-self of t
+    anc = {}
+    for t in chosen:
+        a = t
+        while a >= 0:
+            anc.setdefault(a, []).append(t)
+            a = int(st.parent[a])
+    t0 = time.time()
+    blocks = []
+    for (tb, sb) in st.near:
+        for t in anc.get(tb, []):
+            blocks.append((t, sb, cquad.near_block(tri, st.idx(t), st.idx(sb), w.kappa)))
+    t_assemble = time.time() - t0
+    Xc = X.T                                           # n x nrhs
+    Y = {t: np.zeros((int(st.size[t]), Xc.shape[1]), dtype=np.complex128) for t in chosen}
+    nbytes = sum(N.size for _, _, N in blocks) * 16 + 2 * 16 * Xc.shape[1] * sum(Y[t].shape[0] for t in chosen)
+    reps = 0
+    t0 = time.time()
+    while True:
+        for t, sb, N in blocks:
+            Y[t] += N @ Xc[st.idx(sb)]
+        reps += 1
+        if time.time() - t0 > 3.0:
+            break
+    t_mv = (time.time() - t0) / reps
+    threads = os.environ.get("OMP_NUM_THREADS")
+    cores = int(threads) if threads else os.cpu_count()
+    return {
+        "value": nbytes / t_mv / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+        "sample": ("near-field matvec of %d leaf row clusters (%d rows, %d blocks, %.2f GB of entries) "
+                   "of the same mesh and parameters, %d right-hand sides; oracle structure %.1f s, "
+                   "assembly of the sampled near-field rows %.1f s (C, OpenMP)"
+                   % (len(chosen), sum(Y[t].shape[0] for t in chosen), len(blocks),
+                      sum(N.size for _, _, N in blocks) * 16 / 1e9, Xc.shape[1], t_struct, t_assemble)),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; --gpus %d is not supported (the path runs on one "
+              "MI355X; see the design notes for how it would shard)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1809_04384_amd import dh2
+
+    w = synth.WORKLOADS[args.workload]
+    V, T = synth.make_mesh(w)
+    n = len(T)
+    nrhs = w.nrhs
+    X = synth.complex_gaussian(n, nrhs, seed=0)                 # (nrhs, n) complex128
+    torch.cuda.set_device(0)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    Yd = torch.empty_like(Xd)
+    log("workload %s n=%d kappa=%g m=%d leaf=%d tol=%g nrhs=%d" % (w.name, n, w.kappa, w.order, w.leaf, w.tol, nrhs))
+
+    def step():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1))
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        h.matvec(Xd, Yd)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t1
+        return h, tb, tm
+
+    for i in range(args.warmup):
+        h, tb, tm = step()
+        log("warmup %d: build %.2f s" % (i, tb))
+        h.free()
+    builds, steps_ms, h = [], [], None
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        if h is not None:
+            h.free()
+        h, tb, tm = step()
+        builds.append(tb)
+        steps_ms.append((tb + tm) * 1e3)
+        log("step %d: build %.2f s, matvec %.2f ms" % (i, tb, tm * 1e3))
+    t_all = time.perf_counter() - t_all
+    st = h.stats()
+    log("stats " + json.dumps({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}))
+
+    # matvec throughput: median of event-timed calls on the current stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(args.matvec_reps):
+        ev0.record()
+        h.matvec(Xd, Yd)
+        ev1.record()
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    mv_ms = statistics.median(times)
+    mv_bytes = st["matvec_bytes"] + nrhs * st["matvec_bytes_per_rhs"]
+    mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+    # dominant kernel: near field, timed with events around its launch
+    phases = {}
+    near_ms = []
+    near_bytes = 0.0
+    for _ in range(args.matvec_reps):
+        ph, near_bytes = h.matvec_profile(Xd, Yd)
+        near_ms.append(ph["near"])
+        for k, v in ph.items():
+            phases.setdefault(k, []).append(v)
+    near_avg = sum(near_ms) / len(near_ms)
+    e = 16.0
+    near_alg = near_bytes + 2.0 * e * n * nrhs
+    near_gbs = near_alg / (near_avg * 1e-3) / 1e9
+    log("matvec %.3f ms (%.1f GB/s); near field %.3f ms, %.2f GB -> %.1f GB/s"
+        % (mv_ms, mv_gbs, near_avg, near_alg / 1e9, near_gbs))
+    h.free()
+
+    base = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        base = cpu_baseline(w, V, T, X, args.cpu_sample_leaves)
+        log("cpu baseline %.3f GB/s" % base["value"])
+
+    out = {
+        "metric": METRIC,
+        "value": round(mv_gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_all * 1e3 / max(args.steps, 1), 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: unit sphere n=%d, kappa=%g, m=%d (k=%d), leaf %d, eta=%g, eta1=%g, "
+                               "tol=%g, %d complex128 right-hand sides, FP64 form"
+                               % (w.name, n, w.kappa, w.order, w.order ** 3, w.leaf, w.eta, w.eta1,
+                                  w.tol, nrhs),
+                   "n": n, "kappa": w.kappa, "order": w.order, "leafsize": w.leaf, "tol": w.tol,
+                   "nrhs": nrhs, "precision": "fp64"},
+        "build_s": round(statistics.median(builds), 3),
+        "matvec_ms": round(mv_ms, 3),
+        "build_phases_ms": {k[3:]: round(v, 1) for k, v in st.items() if k.startswith("ms_")},
+        "matvec_phases_ms": {k: round(sum(v) / len(v), 4) for k, v in phases.items()},
+        "ranks": {"row_max": st["rank_max_row"], "row_mean": round(st["rank_mean_row"], 2),
+                  "col_max": st["rank_max_col"], "col_mean": round(st["rank_mean_col"], 2)},
+        "storage_kb_per_dof": {
+            "near": round(st["near_entries"] * 16 / 1024 / n, 1),
+            "coupling": round(st["coupling_entries"] * 16 / 1024 / n, 1),
+            "basis": round(st["basis_entries"] * 16 / 1024 / n, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(near_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(near_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_mv_near (near-field matvec)",
+                     "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

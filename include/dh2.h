@@ -106,6 +106,16 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
  * range), DH2_ERR_DEVICE (launch failure). */
 dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs);
 
+/* dh2_matvec with per-phase timing, for benchmarks: runs the same kernels,
+ * records HIP events on the handle's stream between the phases and waits for
+ * them (this call synchronises).  phase_ms[7] receives milliseconds of:
+ * 0 gather of X into cluster order, 1 forward transform, 2 coupling,
+ * 3 backward transform, 4 near field, 5 leaf output, 6 scatter of Y.
+ * near_bytes (may be NULL) receives the near-field matrix bytes streamed by
+ * phase 4.  Errors as dh2_matvec. */
+dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, double* phase_ms,
+                              double* near_bytes);
+
 /* Releases all device and host memory of the handle.  NULL is a no-op. */
 void dh2_free(dh2_handle h);
 

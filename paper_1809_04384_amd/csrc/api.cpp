@@ -161,8 +161,12 @@ struct dh2_problem {
   // matvec schedule
   void* Xp_d = nullptr; void* Yp_d = nullptr; void* xh_d = nullptr; void* yh_d = nullptr;
   MvOut* mv_outs_d = nullptr; MvTerm* mv_terms_d = nullptr;
-  struct Phase { int64_t out_begin, out_end; };
-  std::vector<Phase> mv_phases;
+  struct Phase { int64_t out_begin, out_end; int group; };
+  std::vector<Phase> mv_phases;     // groups: 1 forward, 2 coupling, 3 backward, 5 leaf output
+  NearRow* near_rows_d = nullptr;
+  NearSeg* near_segs_d = nullptr;
+  int64_t n_near_rows = 0;
+  int64_t near_matvec_bytes = 0;    // matrix bytes streamed by the near-field kernel
 
   template <class T>
   T* alloc(size_t count) {
@@ -880,7 +884,8 @@ struct Builder {
     std::vector<MvOut> outs;
     std::vector<MvTerm> terms;
     h.mv_phases.clear();
-    auto begin_phase = [&]() { h.mv_phases.push_back({(int64_t)outs.size(), (int64_t)outs.size()}); };
+    int group = 1;
+    auto begin_phase = [&]() { h.mv_phases.push_back({(int64_t)outs.size(), (int64_t)outs.size(), group}); };
     auto end_phase = [&]() { h.mv_phases.back().out_end = (int64_t)outs.size(); };
     // forward, leaves
     begin_phase();
@@ -914,6 +919,7 @@ struct Builder {
       end_phase();
     }
     // coupling
+    group = 2;
     begin_phase();
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_row[q] > 0) {
@@ -931,6 +937,7 @@ struct Builder {
       }
     end_phase();
     // backward, top-down: y_{t'c'} += F_{t'c} y_tc
+    group = 3;
     for (int l = 1; l <= p.depth; ++l) {
       begin_phase();
       for (int64_t q = 0; q < ns; ++q)
@@ -964,25 +971,43 @@ struct Builder {
           for (int i = 0; i < 2; ++i) stack.push_back(p.cl[c].child[i]);
       }
     }
+    // near field: its own kernel, one entry per leaf, writes Yp
+    std::vector<NearRow> nrows;
+    std::vector<NearSeg> nsegs;
+    int64_t nbytes = 0;
+    for (int64_t t = 0; t < (int64_t)p.cl.size(); ++t) {
+      const Cluster& c = p.cl[t];
+      if (!c.leaf()) continue;
+      NearRow r{c.first, (int32_t)c.size, (int32_t)nsegs.size(), 0, 0};
+      for (const auto& pr : near_of_leaf[t]) {
+        const NearBlock& nbk = p.near[pr.first];
+        const Cluster& tt = p.cl[nbk.t];
+        const Cluster& ss = p.cl[nbk.s];
+        nsegs.push_back({(C64*)h.near_d + h.near_off[pr.first] + pr.second, ss.first, (int32_t)tt.size,
+                         (int32_t)ss.size});
+        nbytes += c.size * ss.size;
+      }
+      r.seg_end = (int32_t)nsegs.size();
+      nrows.push_back(r);
+    }
+    h.near_rows_d = h.upload(nrows);
+    h.near_segs_d = h.upload(nsegs);
+    h.n_near_rows = (int64_t)nrows.size();
+    h.near_matvec_bytes = nbytes * (int64_t)sizeof(C64);
+    // leaf output: Y_t += Q_tc y_tc (after the near field)
+    group = 5;
     begin_phase();
     for (int64_t t = 0; t < (int64_t)p.cl.size(); ++t) {
       const Cluster& c = p.cl[t];
       if (!c.leaf()) continue;
-      MvOut o{Yp + c.first, (int32_t)c.size, (int32_t)n, (int32_t)terms.size(), 0, 0, 0};
+      MvOut o{Yp + c.first, (int32_t)c.size, (int32_t)n, (int32_t)terms.size(), 0, 1, 0};
       for (const auto& pr : p.cl_slots[t]) {
         const int64_t q = pr.second;
         if (h.rank_row[q] > 0)
           terms.push_back({h.Qr_ptr[q], yh + yo[q], h.rank_row[q], (int32_t)c.size, h.rank_row[q], 0});
       }
-      for (const auto& pr : near_of_leaf[t]) {
-        const NearBlock& nbk = p.near[pr.first];
-        const Cluster& tt = p.cl[nbk.t];
-        const Cluster& ss = p.cl[nbk.s];
-        terms.push_back({(C64*)h.near_d + h.near_off[pr.first] + pr.second, Xp + ss.first,
-                         (int32_t)ss.size, (int32_t)tt.size, (int32_t)n, 0});
-      }
       o.term_end = (int32_t)terms.size();
-      outs.push_back(o);
+      if (o.term_end > o.term_begin) outs.push_back(o);
     }
     end_phase();
     h.mv_outs_d = h.upload(outs);
@@ -1278,6 +1303,41 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
   return DH2_OK;
 }
 
+namespace {
+// Runs the matvec phases on the handle's stream; with ev != NULL records
+// ev[g] before group g (0 gather, 1 forward, 2 coupling, 3 backward, 4 near,
+// 5 leaf output, 6 scatter) and ev[7] at the end.
+void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
+  const int64_t n = h->plan.n;
+  auto mark = [&](int g) {
+    if (ev) HIPCHK(hipEventRecord(ev[g], h->stream));
+  };
+  auto terms = [&](int g) {
+    for (const auto& ph : h->mv_phases)
+      if (ph.group == g && ph.out_end > ph.out_begin)
+        launch_mv_terms<double>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
+                                nrhs, h->stream);
+  };
+  mark(0);
+  launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
+  mark(1);
+  terms(1);
+  mark(2);
+  terms(2);
+  mark(3);
+  terms(3);
+  mark(4);
+  launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
+                         h->stream);
+  mark(5);
+  terms(5);
+  mark(6);
+  launch_mv_permute<double>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, h->stream);
+  mark(7);
+  HIPCHK(hipGetLastError());
+}
+}  // namespace
+
 dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs) {
   if (!h || !X || !Y) {
     g_err = "NULL handle or vector";
@@ -1288,17 +1348,40 @@ dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs) {
     return DH2_ERR_ARG;
   }
   try {
-    const int64_t n = h->plan.n;
-    launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
-    for (const auto& ph : h->mv_phases)
-      if (ph.out_end > ph.out_begin)
-        launch_mv_terms<double>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
-                                nrhs, h->stream);
-    launch_mv_permute<double>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, h->stream);
-    HIPCHK(hipGetLastError());
+    run_matvec(h, X, Y, nrhs, nullptr);
   } catch (const Fail& f) {
     return fail(f);
   }
+  return DH2_OK;
+}
+
+dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, double* phase_ms,
+                              double* near_bytes) {
+  if (!h || !X || !Y || !phase_ms) {
+    g_err = "NULL argument";
+    return DH2_ERR_ARG;
+  }
+  if (nrhs < 1 || nrhs > h->max_nrhs) {
+    g_err = "nrhs out of range [1, max_nrhs]";
+    return DH2_ERR_ARG;
+  }
+  hipEvent_t ev[8] = {};
+  try {
+    for (int i = 0; i < 8; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    run_matvec(h, X, Y, nrhs, ev);
+    HIPCHK(hipEventSynchronize(ev[7]));
+    for (int i = 0; i < 7; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      phase_ms[i] = ms;
+    }
+    if (near_bytes) *near_bytes = (double)h->near_matvec_bytes;
+  } catch (const Fail& f) {
+    for (int i = 0; i < 8; ++i)
+      if (ev[i]) hipEventDestroy(ev[i]);
+    return fail(f);
+  }
+  for (int i = 0; i < 8; ++i) hipEventDestroy(ev[i]);
   return DH2_OK;
 }
 

@@ -36,6 +36,88 @@ __global__ void __launch_bounds__(256) k_mv_terms(const MvOut* __restrict__ outs
   }
 }
 
+// Near-field product (the dense inadmissible leaves, Definition of DH^2
+// matrices): a workgroup per leaf row cluster, lane = row, the four waves take
+// interleaved columns; every matrix entry is read once, coalesced along the
+// column, and applied to all right-hand sides held in registers.  The wave
+// partial sums are combined through LDS; Y rows are written (not accumulated).
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_mv_near(const NearRow* __restrict__ rows,
+                                                 const NearSeg* __restrict__ segs,
+                                                 const cpx<R>* __restrict__ X, cpx<R>* __restrict__ Y,
+                                                 int64_t n, int nrhs) {
+  const NearRow rw = rows[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ cpx<R> red[3][64][NR];
+  for (int r0 = 0; r0 < rw.nr; r0 += 64) {
+    const int i = r0 + lane;
+    const bool act = i < rw.nr;
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+      const int nc = min(NR, nrhs - c0);
+      cpx<R> acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = cpx<R>{0, 0};
+      for (int sg = rw.seg_begin; sg < rw.seg_end; ++sg) {
+        const NearSeg s = segs[sg];
+        const cpx<R>* A = (const cpx<R>*)s.A + i;
+        const cpx<R>* x = X + s.x0 + (int64_t)c0 * n;
+        int j = wave;
+        for (; j + 12 < s.ncols; j += 16) {
+          cpx<R> a[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            a[u] = act ? A[(int64_t)(j + 4 * u) * s.lda] : cpx<R>{0, 0};
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+              if (r < nc) cfma(acc[r], a[u], x[j + 4 * u + (int64_t)r * n]);
+        }
+        for (; j < s.ncols; j += 4) {
+          const cpx<R> a = act ? A[(int64_t)j * s.lda] : cpx<R>{0, 0};
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            if (r < nc) cfma(acc[r], a, x[j + (int64_t)r * n]);
+        }
+      }
+      if (wave > 0)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) red[wave - 1][lane][r] = acc[r];
+      __syncthreads();
+      if (wave == 0 && act) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r >= nc) break;
+          const cpx<R> v = acc[r] + red[0][lane][r] + red[1][lane][r] + red[2][lane][r];
+          Y[rw.row0 + i + (int64_t)(c0 + r) * n] = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename R>
+void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
+                    int64_t n, int nrhs, hipStream_t st) {
+  if (nrows <= 0) return;
+  const dim3 g((unsigned)nrows), b(256);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_mv_near<R, 1>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs == 2)
+    hipLaunchKernelGGL((k_mv_near<R, 2>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL((k_mv_near<R, 4>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL((k_mv_near<R, 8>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+  else
+    hipLaunchKernelGGL((k_mv_near<R, 16>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+}
+template void launch_mv_near<double>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
+                                     int64_t, int, hipStream_t);
+template void launch_mv_near<float>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
+                                    int64_t, int, hipStream_t);
+
 // gather: dst[p + r n] = src[perm[p] + r n];  scatter: dst[perm[p] + r n] = src[p + r n]
 template <typename R>
 __global__ void k_mv_permute(const cpx<R>* __restrict__ src, cpx<R>* __restrict__ dst,

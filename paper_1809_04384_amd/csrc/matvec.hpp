@@ -23,6 +23,26 @@ struct MvOut {
   int32_t pad;
 };
 
+// Near field, one entry per leaf row cluster: rows [row0, row0 + nr) of Y get
+// sum over segments of A (nr x ncols, leading dimension lda) times X rows
+// [x0, x0 + ncols).  A segment is an inadmissible block restricted to the rows
+// of this leaf.
+struct NearRow {
+  int64_t row0;
+  int32_t nr;
+  int32_t seg_begin, seg_end;
+  int32_t pad;
+};
+struct NearSeg {
+  const void* A;
+  int64_t x0;
+  int32_t lda, ncols;
+};
+
+template <typename R>
+void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
+                    int64_t n, int nrhs, hipStream_t st);
+
 template <typename R>
 void launch_mv_terms(const MvOut* outs, int64_t nout, const MvTerm* terms, int nrhs, hipStream_t st);
 template <typename R>

@@ -20,7 +20,7 @@ INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col":
            "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
            "total_weight_row": 10, "total_weight_col": 11, "coupling": 12}
 
-EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_free", "dh2_last_error",
+EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_free", "dh2_last_error",
             "dh2_get_stats", "dh2_plan_create", "dh2_plan_get_sizes", "dh2_plan_export",
             "dh2_plan_free", "dh2_inspect"]
 
@@ -83,6 +83,7 @@ def load():
     lib.dh2_build.argtypes = [P, D, I32, D, I32, D, P]
     lib.dh2_build_ex.argtypes = [P, D, I32, D, I32, D, P, P]
     lib.dh2_matvec.argtypes = [P, P, P, I32]
+    lib.dh2_matvec_profile.argtypes = [P, P, P, I32, P, P]
     lib.dh2_free.argtypes = [P]
     lib.dh2_free.restype = None
     lib.dh2_last_error.restype = ctypes.c_char_p
@@ -93,7 +94,7 @@ def load():
     lib.dh2_plan_free.argtypes = [P]
     lib.dh2_plan_free.restype = None
     lib.dh2_inspect.argtypes = [P, I32, I64, P, P, P]
-    for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_get_stats", "dh2_plan_create",
+    for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_get_stats", "dh2_plan_create",
                  "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -181,6 +182,17 @@ class Handle:
         if X.shape != Y.shape:
             raise ValueError("X and Y must have the same shape")
         self.matvec_ptr(X.data_ptr(), Y.data_ptr(), X.shape[0])
+
+    PHASES = ("gather", "forward", "coupling", "backward", "near", "leaf_output", "scatter")
+
+    def matvec_profile(self, X, Y):
+        """Y = Gtilde X with per-phase event timing (synchronising).  Returns
+        ({phase: ms}, near-field bytes streamed)."""
+        ms = (ctypes.c_double * 7)()
+        nb = ctypes.c_double()
+        _check(load().dh2_matvec_profile(self._h, X.data_ptr(), Y.data_ptr(), X.shape[0], ms,
+                                         ctypes.byref(nb)))
+        return dict(zip(self.PHASES, list(ms))), nb.value
 
     def stats(self):
         s = Stats()
