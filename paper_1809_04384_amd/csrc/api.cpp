@@ -160,9 +160,13 @@ struct dh2_problem {
   void* St_d = nullptr;  std::vector<int64_t> St_off;
   // matvec schedule
   void* Xp_d = nullptr; void* Yp_d = nullptr; void* xh_d = nullptr; void* yh_d = nullptr;
+  void* XT_d = nullptr;   // row-major copy of the gathered X (multi right-hand-side near field)
   MvOut* mv_outs_d = nullptr; MvTerm* mv_terms_d = nullptr;
   struct Phase { int64_t out_begin, out_end; int group; };
   std::vector<Phase> mv_phases;     // groups: 1 forward, 2 coupling, 3 backward, 5 leaf output
+  CoupRow* coup_rows_d = nullptr;
+  CoupBlk* coup_blks_d = nullptr;
+  int64_t n_coup_rows = 0;
   NearRow* near_rows_d = nullptr;
   NearSeg* near_segs_d = nullptr;
   int64_t n_near_rows = 0;
@@ -868,6 +872,7 @@ struct Builder {
     const int nr = h.max_nrhs;
     const int64_t n = p.n;
     h.Xp_d = h.alloc<C64>((size_t)n * nr);
+    h.XT_d = h.alloc<C64>((size_t)n * nr);
     h.Yp_d = h.alloc<C64>((size_t)n * nr);
     std::vector<int64_t> xo(ns, -1), yo(ns, -1);
     int64_t xt = 0, yt = 0;
@@ -918,24 +923,26 @@ struct Builder {
         }
       end_phase();
     }
-    // coupling
-    group = 2;
-    begin_phase();
+    // coupling: its own kernel, one entry per row slot
+    std::vector<CoupRow> crows;
+    std::vector<CoupBlk> cblks;
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_row[q] > 0) {
         const int kq = h.rank_row[q];
-        MvOut o{yh + yo[q], kq, kq, (int32_t)terms.size(), 0, 0, 0};
+        CoupRow r{yh + yo[q], kq, (int32_t)cblks.size(), 0, 0};
         for (int64_t e = p.row_ptr[q]; e < p.row_ptr[q + 1]; ++e) {
           const int64_t b = p.row_blk[e];
           const AdmBlock& a = p.adm[b];
           const int64_t qs = p.slot_of(a.s, a.c);
           const int ks = h.rank_col[qs];
-          if (ks > 0) terms.push_back({(C64*)h.St_d + h.St_off[b], xh + xo[qs], ks, kq, ks, 0});
+          if (ks > 0) cblks.push_back({(C64*)h.St_d + h.St_off[b], xh + xo[qs], ks, 0});
         }
-        o.term_end = (int32_t)terms.size();
-        outs.push_back(o);
+        r.blk_end = (int32_t)cblks.size();
+        crows.push_back(r);
       }
-    end_phase();
+    h.coup_rows_d = h.upload(crows);
+    h.coup_blks_d = h.upload(cblks);
+    h.n_coup_rows = (int64_t)crows.size();
     // backward, top-down: y_{t'c'} += F_{t'c} y_tc
     group = 3;
     for (int l = 1; l <= p.depth; ++l) {
@@ -1323,12 +1330,12 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
   mark(1);
   terms(1);
   mark(2);
-  terms(2);
+  launch_mv_coupling<double>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
   mark(3);
   terms(3);
   mark(4);
   launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
-                         h->stream);
+                         h->stream, h->XT_d);
   mark(5);
   terms(5);
   mark(6);

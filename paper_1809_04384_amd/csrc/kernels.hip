@@ -315,28 +315,41 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
 // eq. (recomp_weight_full)); only R is kept, as in the paper.
 // Column j: x = (R[j,j], P[:,j]); beta = -phase(R[j,j]) |x| with |x| taken
 // through a max-abs scale; d = R[j,j] - beta, u = (1, P[:,j] / d),
-// tau = (beta - R[j,j]) / beta; H = I - tau u u^H satisfies H^H x = beta e_0
-// and is applied as H^H to the remaining columns.  |u_i| <= 1 and
-// 1 <= |tau| <= 2, so no intermediate is squared: bases with columns many
-// orders of magnitude below the others (flat boxes) stay exact.  A column
-// whose remaining entries are below 1e-14 of the staged rows' maximum is
-// skipped (rounding residue of a rank-deficient piece), so the number of
-// nonzero rows stays at the numerical rank.
-// Rows of the current piece are staged in LDS (row-major, CH rows).
+// tau = (beta - R[j,j]) / beta; H = I - tau u u^H satisfies H^H x = beta e_0.
+// |u_i| <= 1 and 1 <= |tau| <= 2, so no intermediate is squared: bases with
+// columns many orders of magnitude below the others (flat boxes) stay exact.
+// A column whose remaining entries are below 1e-14 of the staged rows'
+// maximum is skipped (rounding residue of a rank-deficient piece).
+// Blocked form: panels of NB columns are reduced column by column, the
+// panel's reflectors are accumulated as I - V T V^H (V = [I; Y], Y the u
+// vectors, T upper triangular) and the trailing columns get
+// C <- C - V T^H (V^H C) with all threads.  Rows of the current piece are
+// staged in LDS (row-major, CH rows), followed by the NB rows of R of the
+// current panel, so the serial column steps never wait on global memory.
+constexpr int kFoldNB = 8;
+constexpr int kFoldThreads = 512;
+
 template <typename PT>
-__global__ void __launch_bounds__(256) k_fold(const FoldTask* __restrict__ tasks,
-                                              const FoldPiece* __restrict__ pieces, int ch) {
+__global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restrict__ tasks,
+                                                       const FoldPiece* __restrict__ pieces, int ch) {
   extern __shared__ double lds_raw[];
   const FoldTask tk = tasks[blockIdx.x];
   const int n = tk.n;
   z64* R = (z64*)tk.R;
-  z64* P = (z64*)lds_raw;                     // [ch][n]
-  __shared__ z64 s_tauc;                      // conj(tau)
-  __shared__ int s_skip;
-  __shared__ double s_wmax[4];
+  z64* P = (z64*)lds_raw;                       // [ch][n]
+  z64* Rp = P + (size_t)ch * n;                 // [NB][n]: rows j0.. of R during a panel
+  __shared__ z64 s_tauc[kFoldNB];               // conj(tau) per panel column (0 if skipped)
+  __shared__ z64 s_T[kFoldNB][kFoldNB];         // block reflector factor
+  __shared__ z64 s_G[kFoldNB][kFoldNB];         // Y^H Y
+  __shared__ double s_wmax[kFoldThreads / 64];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  constexpr int nwaves = kFoldThreads / 64;
+  // trailing-update layout: lane = 4 * column + row group
+  const int q = lane & 3;                       // row group
+  const int cw = wave * 16 + (lane >> 2);       // column slot within a block of 128
   if (tk.init_zero)
-    for (int e = tid; e < n * n; e += 256) {
+    for (int e = tid; e < n * n; e += kFoldThreads) {
       const int i = e % n, j = e / n;
       R[i + (int64_t)j * tk.ldr] = z64{0, 0};
     }
@@ -347,73 +360,170 @@ __global__ void __launch_bounds__(256) k_fold(const FoldTask* __restrict__ tasks
     for (int r0 = 0; r0 < pp.rows; r0 += ch) {
       const int p = min(ch, pp.rows - r0);
       double lmax = 0.0;
-      for (int e = tid; e < p * n; e += 256) {
+      for (int e = tid; e < p * n; e += kFoldThreads) {
         const int i = e % p, j = e / p;
         const cpx<PT> v = src[(r0 + i) + (int64_t)j * pp.ld];
         P[i * n + j] = z64{(double)v.x, (double)v.y};
         lmax = fmax(lmax, fmax(fabs((double)v.x), fabs((double)v.y)));
       }
       for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
-      if ((tid & 63) == 0) s_wmax[tid >> 6] = lmax;
+      if (lane == 0) s_wmax[wave] = lmax;
       __syncthreads();
-      // columns whose remaining entries are at rounding level of the staged rows
-      // are left alone: they carry no information and would only add noise rows
-      const double skip_below = 1e-14 * fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
-      for (int j = 0; j < n; ++j) {
-        // reflector of column j: wave 0, every lane computes the same scalars
-        if (tid < 64) {
-          double mx = 0.0;
-          for (int i = tid; i < p; i += 64) {
-            const z64 v = P[i * n + j];
-            mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+      double cmax = 0.0;
+      for (int w = 0; w < nwaves; ++w) cmax = fmax(cmax, s_wmax[w]);
+      const double skip_below = 1e-14 * cmax;
+      for (int j0 = 0; j0 < n; j0 += kFoldNB) {
+        const int nb = min(kFoldNB, n - j0);
+        const int pe = j0 + nb;                 // end of the panel
+        for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
+          const int a = e % nb, jj = j0 + e / nb;
+          Rp[a * n + jj] = R[j0 + a + (int64_t)jj * tk.ldr];
+        }
+        __syncthreads();
+        // ---- panel: reflectors column by column, updates inside the panel
+        for (int jl = 0; jl < nb; ++jl) {
+          const int j = j0 + jl;
+          if (wave == 0) {
+            double mx = 0.0;
+            for (int i = lane; i < p; i += 64) {
+              const z64 v = P[i * n + j];
+              mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+            }
+            for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+            if (mx <= skip_below) {
+              for (int i = lane; i < p; i += 64) P[i * n + j] = z64{0, 0};
+              if (lane == 0) s_tauc[jl] = z64{0, 0};
+            } else {
+              const z64 a = Rp[jl * n + j];
+              const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
+              const double inv = 1.0 / scale;
+              double part = 0.0;
+              for (int i = lane; i < p; i += 64) {
+                const z64 v = P[i * n + j];
+                part += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
+              }
+              for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+              const z64 as{a.x * inv, a.y * inv};
+              const double aas = sqrt(abs2(as));
+              const double sig_s = sqrt(aas * aas + part);
+              const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
+              const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
+              const z64 d_s = as - beta_s;
+              const double dd = 1.0 / abs2(d_s);
+              const z64 dinv{d_s.x * dd, -d_s.y * dd};
+              for (int i = lane; i < p; i += 64) {
+                const z64 v = P[i * n + j];
+                P[i * n + j] = z64{v.x * inv, v.y * inv} * dinv;
+              }
+              if (lane == 0) {
+                const double bb = 1.0 / abs2(beta_s);
+                const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
+                s_tauc[jl] = conj(tau);
+                Rp[jl * n + j] = z64{beta_s.x * scale, beta_s.y * scale};
+              }
+            }
           }
-          for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-          if (mx <= skip_below) {
-            if (tid == 0) s_skip = 1;
-          } else {
-            const z64 a = R[j + (int64_t)j * tk.ldr];
-            const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
-            const double inv = 1.0 / scale;
-            double part = 0.0;
-            for (int i = tid; i < p; i += 64) {
-              const z64 v = P[i * n + j];
-              part += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
+          __syncthreads();
+          // remaining panel columns: one wave per column, lanes over rows
+          const z64 tc = s_tauc[jl];
+          if (tc.x != 0.0 || tc.y != 0.0) {
+            for (int jj = j + 1 + wave; jj < pe; jj += nwaves) {
+              z64 w{0, 0};
+              for (int i = lane; i < p; i += 64) cfmac(w, P[i * n + j], P[i * n + jj]);
+              for (int off = 32; off > 0; off >>= 1) {
+                w.x += __shfl_xor(w.x, off);
+                w.y += __shfl_xor(w.y, off);
+              }
+              z64* rj = &Rp[jl * n + jj];
+              const z64 tw = tc * (*rj + w);
+              for (int i = lane; i < p; i += 64) P[i * n + jj] = P[i * n + jj] - P[i * n + j] * tw;
+              __builtin_amdgcn_wave_barrier();
+              if (lane == 0) *rj = *rj - tw;
             }
-            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-            const z64 as{a.x * inv, a.y * inv};
-            const double aas = sqrt(abs2(as));
-            const double sig_s = sqrt(aas * aas + part);          // |x| / scale
-            const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
-            const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
-            const z64 d_s = as - beta_s;                           // |d_s| = aas + sig_s
-            // u_i = P_ij / d = (P_ij / scale) / d_s
-            const double dd = 1.0 / abs2(d_s);
-            const z64 dinv{d_s.x * dd, -d_s.y * dd};
-            for (int i = tid; i < p; i += 64) {
-              const z64 v = P[i * n + j];
-              P[i * n + j] = z64{v.x * inv, v.y * inv} * dinv;
+          }
+          __syncthreads();
+        }
+        if (pe < n) {
+        // ---- T: T[a][a] = tau_a, T[0:a][a] = -tau_a T[0:a][0:a] (Y[:,0:a]^H Y[:,a])
+        for (int e = tid; e < nb * nb; e += kFoldThreads) {
+          const int a = e % nb, b = e / nb;
+          z64 g{0, 0};
+          if (a < b)
+            for (int i = 0; i < p; ++i) cfmac(g, P[i * n + j0 + a], P[i * n + j0 + b]);
+          s_G[a][b] = g;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          for (int b = 0; b < nb; ++b) {
+            const z64 tau = conj(s_tauc[b]);
+            for (int a = 0; a < b; ++a) {
+              z64 acc{0, 0};
+              for (int c = a; c < b; ++c) cfma(acc, s_T[a][c], s_G[c][b]);
+              s_T[a][b] = z64{0, 0} - tau * acc;
             }
-            if (tid == 0) {
-              // tau = (beta - a) / beta = -d_s / beta_s
-              const double bb = 1.0 / abs2(beta_s);
-              const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
-              s_tauc = conj(tau);
-              s_skip = 0;
-              R[j + (int64_t)j * tk.ldr] = z64{beta_s.x * scale, beta_s.y * scale};
-            }
+            s_T[b][b] = tau;
+            for (int a = b + 1; a < nb; ++a) s_T[a][b] = z64{0, 0};
           }
         }
         __syncthreads();
-        if (!s_skip) {
-          const z64 tc = s_tauc;
-          for (int jj = j + 1 + tid; jj < n; jj += 256) {
-            z64* rj = &R[j + (int64_t)jj * tk.ldr];
-            z64 w = *rj;
-            for (int i = 0; i < p; ++i) cfmac(w, P[i * n + j], P[i * n + jj]);
-            const z64 tw = tc * w;
-            *rj = *rj - tw;
-            for (int i = 0; i < p; ++i) P[i * n + jj] = P[i * n + jj] - P[i * n + j] * tw;
+        // ---- trailing columns, 128 at a time: lane = 4 * column + row group.
+        // Every value of a column lives in its four lanes, so no barrier is needed:
+        // W = R[panel rows, jj] + Y^H P[:, jj], W <- T^H W,
+        // R[panel rows, jj] -= W, P[:, jj] -= Y W.
+        for (int jb = pe; jb < n; jb += 128) {
+          const int jj = jb + cw;
+          const bool colok = jj < n;
+          z64 w[kFoldNB];
+#pragma unroll
+          for (int a = 0; a < kFoldNB; ++a) w[a] = z64{0, 0};
+          if (colok)
+            for (int i = q; i < p; i += 4) {
+              const z64 pv = P[i * n + jj];
+#pragma unroll
+              for (int a = 0; a < kFoldNB; ++a)
+                if (a < nb) cfmac(w[a], P[i * n + j0 + a], pv);
+            }
+#pragma unroll
+          for (int a = 0; a < kFoldNB; ++a) {
+            w[a].x += __shfl_xor(w[a].x, 1);
+            w[a].y += __shfl_xor(w[a].y, 1);
+            w[a].x += __shfl_xor(w[a].x, 2);
+            w[a].y += __shfl_xor(w[a].y, 2);
           }
+          if (!colok) continue;
+#pragma unroll
+          for (int a = 0; a < kFoldNB; ++a)
+            if (a < nb) w[a] = w[a] + Rp[a * n + jj];
+          z64 w2[kFoldNB];
+#pragma unroll
+          for (int a = 0; a < kFoldNB; ++a) {
+            z64 acc{0, 0};
+#pragma unroll
+            for (int b = 0; b <= a; ++b) cfmac(acc, s_T[b][a], w[b]);
+            w2[a] = a < nb ? acc : z64{0, 0};
+          }
+          if (q == 0) {
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a)
+              if (a < nb) {
+                z64* r = &Rp[a * n + jj];
+                *r = *r - w2[a];
+              }
+          }
+          for (int i = q; i < p; i += 4) {
+            z64 acc = P[i * n + jj];
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a)
+              if (a < nb) acc = acc - P[i * n + j0 + a] * w2[a];
+            P[i * n + jj] = acc;
+          }
+        }
+        __syncthreads();
+        }
+        // panel rows of R back to global memory
+        for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
+          const int a = e % nb, jj = j0 + e / nb;
+          R[j0 + a + (int64_t)jj * tk.ldr] = Rp[a * n + jj];
         }
         __syncthreads();
       }
@@ -437,7 +547,7 @@ __global__ void __launch_bounds__(256) k_fold(const FoldTask* __restrict__ tasks
     }
     __syncthreads();
     const int c = s_cnt;
-    for (int jj = tid; jj < n; jj += 256) {
+    for (int jj = tid; jj < n; jj += kFoldThreads) {
       for (int r = 0; r < c; ++r) {
         const int i = s_rows[r];
         if (i != r) R[r + (int64_t)jj * tk.ldr] = R[i + (int64_t)jj * tk.ldr];
@@ -708,13 +818,12 @@ template void launch_gemm<float>(const GemmDesc*, int64_t, int, int, hipStream_t
 static size_t g_lds_limit = 65536;   // per-workgroup LDS bytes usable for dynamic buffers
 
 void set_lds_limit(size_t bytes) {
-  // keep 8 KB for the kernels' static shared variables
-  g_lds_limit = bytes > 16384 ? bytes - 8192 : 8192;
-  if (g_lds_limit > 131072) g_lds_limit = 131072;
+  // keep 12 KB for the kernels' static shared variables
+  g_lds_limit = bytes > 24576 ? bytes - 12288 : 12288;
 }
 
 int fold_rows_per_chunk(int n) {
-  int ch = (int)(g_lds_limit / ((size_t)n * 16));
+  int ch = (int)(g_lds_limit / ((size_t)n * 16)) - kFoldNB;
   if (ch > 64) ch = 64;
   if (ch < 1) ch = 1;
   return ch;
@@ -724,8 +833,8 @@ template <typename PT>
 void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, hipStream_t st) {
   if (ntasks <= 0) return;
   const int ch = fold_rows_per_chunk(n);
-  const size_t lds = (size_t)ch * n * 16;
-  hipLaunchKernelGGL(k_fold<PT>, dim3((unsigned)ntasks), dim3(256), lds, st, t, p, ch);
+  const size_t lds = (size_t)(ch + kFoldNB) * n * 16;
+  hipLaunchKernelGGL(k_fold<PT>, dim3((unsigned)ntasks), dim3(kFoldThreads), lds, st, t, p, ch);
 }
 template void launch_fold<double>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
 template void launch_fold<float>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);

@@ -97,26 +97,177 @@ __global__ void __launch_bounds__(256) k_mv_near(const NearRow* __restrict__ row
   }
 }
 
+// Multi right-hand-side variant: X is given row-major (all right-hand sides of a
+// row contiguous, XT[j * nrhs + r]); tiles of 64 rows of X are staged in LDS
+// once per workgroup and broadcast to the waves, so each matrix entry costs
+// one coalesced load plus NR complex FMAs from registers.
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_mv_near_multi(const NearRow* __restrict__ rows,
+                                                       const NearSeg* __restrict__ segs,
+                                                       const cpx<R>* __restrict__ XT,
+                                                       cpx<R>* __restrict__ Y, int64_t n, int nrhs) {
+  const NearRow rw = rows[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  __shared__ cpx<R> xs[64][NR];
+  __shared__ cpx<R> red[3][64][NR];
+  for (int r0 = 0; r0 < rw.nr; r0 += 64) {
+    const int i = r0 + lane;
+    const bool act = i < rw.nr;
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+      cpx<R> acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = cpx<R>{0, 0};
+      for (int sg = rw.seg_begin; sg < rw.seg_end; ++sg) {
+        const NearSeg s = segs[sg];
+        const cpx<R>* A = (const cpx<R>*)s.A + i;
+        for (int jt = 0; jt < s.ncols; jt += 64) {
+          const int tile = min(64, s.ncols - jt);
+          __syncthreads();
+          for (int e = tid; e < 64 * NR; e += 256) {
+            const int j = e / NR, r = e % NR;
+            cpx<R> v{0, 0};
+            if (j < tile && c0 + r < nrhs) v = XT[(s.x0 + jt + j) * nrhs + c0 + r];
+            xs[j][r] = v;
+          }
+          __syncthreads();
+          int jj = wave;
+          for (; jj + 12 < tile; jj += 16) {
+            cpx<R> a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              a[u] = act ? A[(int64_t)(jt + jj + 4 * u) * s.lda] : cpx<R>{0, 0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int r = 0; r < NR; ++r) cfma(acc[r], a[u], xs[jj + 4 * u][r]);
+          }
+          for (; jj < tile; jj += 4) {
+            const cpx<R> a = act ? A[(int64_t)(jt + jj) * s.lda] : cpx<R>{0, 0};
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cfma(acc[r], a, xs[jj][r]);
+          }
+        }
+      }
+      if (wave > 0)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) red[wave - 1][lane][r] = acc[r];
+      __syncthreads();
+      if (wave == 0 && act) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (c0 + r < nrhs) {
+            const cpx<R> v = acc[r] + red[0][lane][r] + red[1][lane][r] + red[2][lane][r];
+            Y[rw.row0 + i + (int64_t)(c0 + r) * n] = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Coupling phase y_tc = sum_b Stilde_b x_sc (the admissible leaves of eq. (vsw)
+// in the new bases): a workgroup per row slot; its eight half-waves take
+// interleaved blocks, lane = row of Stilde_b (coalesced along the column), all
+// right-hand sides in registers, partial sums combined through LDS.
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) k_mv_coupling(const CoupRow* __restrict__ rows,
+                                                     const CoupBlk* __restrict__ blks, int nrhs) {
+  const CoupRow rw = rows[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int li = tid & 31, unit = tid >> 5;
+  __shared__ cpx<R> red[7][32][NR];
+  cpx<R>* y = (cpx<R>*)rw.y;
+  for (int rc = 0; rc < rw.kq; rc += 32) {
+    const int i = rc + li;
+    const bool act = i < rw.kq;
+    for (int c0 = 0; c0 < nrhs; c0 += NR) {
+      cpx<R> acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = cpx<R>{0, 0};
+      for (int bb = rw.blk_begin + unit; bb < rw.blk_end; bb += 8) {
+        const CoupBlk b = blks[bb];
+        const cpx<R>* S = (const cpx<R>*)b.S + i;
+        const cpx<R>* x = (const cpx<R>*)b.x + (int64_t)c0 * b.ks;
+        for (int j = 0; j < b.ks; ++j) {
+          const cpx<R> a = act ? S[(int64_t)j * rw.kq] : cpx<R>{0, 0};
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            if (c0 + r < nrhs) cfma(acc[r], a, x[j + (int64_t)r * b.ks]);
+        }
+      }
+      if (unit > 0)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) red[unit - 1][li][r] = acc[r];
+      __syncthreads();
+      if (unit == 0 && act) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (c0 + r < nrhs) {
+            cpx<R> v = acc[r];
+            for (int u = 0; u < 7; ++u) v = v + red[u][li][r];
+            y[i + (int64_t)(c0 + r) * rw.kq] = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <typename R>
-void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
-                    int64_t n, int nrhs, hipStream_t st) {
+void launch_mv_coupling(const CoupRow* rows, int64_t nrows, const CoupBlk* blks, int nrhs,
+                        hipStream_t st) {
   if (nrows <= 0) return;
   const dim3 g((unsigned)nrows), b(256);
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_mv_near<R, 1>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
-  else if (nrhs == 2)
-    hipLaunchKernelGGL((k_mv_near<R, 2>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+    hipLaunchKernelGGL((k_mv_coupling<R, 1>), g, b, 0, st, rows, blks, nrhs);
   else if (nrhs <= 4)
-    hipLaunchKernelGGL((k_mv_near<R, 4>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+    hipLaunchKernelGGL((k_mv_coupling<R, 4>), g, b, 0, st, rows, blks, nrhs);
   else if (nrhs <= 8)
-    hipLaunchKernelGGL((k_mv_near<R, 8>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+    hipLaunchKernelGGL((k_mv_coupling<R, 8>), g, b, 0, st, rows, blks, nrhs);
   else
-    hipLaunchKernelGGL((k_mv_near<R, 16>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+    hipLaunchKernelGGL((k_mv_coupling<R, 16>), g, b, 0, st, rows, blks, nrhs);
+}
+template void launch_mv_coupling<double>(const CoupRow*, int64_t, const CoupBlk*, int, hipStream_t);
+template void launch_mv_coupling<float>(const CoupRow*, int64_t, const CoupBlk*, int, hipStream_t);
+
+// row-major copy of the gathered X: XT[p * nrhs + r] = Xp[p + r n]
+template <typename R>
+__global__ void k_mv_transpose(const cpx<R>* __restrict__ Xp, cpx<R>* __restrict__ XT, int64_t n,
+                               int nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t p = e / nrhs, r = e % nrhs;
+  XT[e] = Xp[p + r * n];
+}
+
+template <typename R>
+void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
+                    int64_t n, int nrhs, hipStream_t st, void* XT) {
+  if (nrows <= 0) return;
+  const dim3 g((unsigned)nrows), b(256);
+  if (nrhs == 1) {
+    hipLaunchKernelGGL((k_mv_near<R, 1>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
+    return;
+  }
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL(k_mv_transpose<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     (const cpx<R>*)X, (cpx<R>*)XT, n, nrhs);
+  if (nrhs == 2)
+    hipLaunchKernelGGL((k_mv_near_multi<R, 2>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL((k_mv_near_multi<R, 4>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL((k_mv_near_multi<R, 8>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
+  else
+    hipLaunchKernelGGL((k_mv_near_multi<R, 16>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
 }
 template void launch_mv_near<double>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
-                                     int64_t, int, hipStream_t);
+                                     int64_t, int, hipStream_t, void*);
 template void launch_mv_near<float>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
-                                    int64_t, int, hipStream_t);
+                                    int64_t, int, hipStream_t, void*);
 
 // gather: dst[p + r n] = src[perm[p] + r n];  scatter: dst[perm[p] + r n] = src[p + r n]
 template <typename R>

@@ -41,7 +41,26 @@ struct NearSeg {
 
 template <typename R>
 void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
-                    int64_t n, int nrhs, hipStream_t st);
+                    int64_t n, int nrhs, hipStream_t st, void* XT);
+
+// Coupling: y_q (kq x nrhs, leading dimension kq) = sum over the admissible
+// blocks of the row slot of Stilde_b (kq x ks) x_s (ks x nrhs, leading dimension ks).
+struct CoupRow {
+  void* y;
+  int32_t kq;
+  int32_t blk_begin, blk_end;
+  int32_t pad;
+};
+struct CoupBlk {
+  const void* S;
+  const void* x;
+  int32_t ks;
+  int32_t pad;
+};
+
+template <typename R>
+void launch_mv_coupling(const CoupRow* rows, int64_t nrows, const CoupBlk* blks, int nrhs,
+                        hipStream_t st);
 
 template <typename R>
 void launch_mv_terms(const MvOut* outs, int64_t nout, const MvTerm* terms, int nrhs, hipStream_t st);
