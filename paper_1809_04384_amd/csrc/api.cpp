@@ -170,6 +170,13 @@ struct dh2_problem {
   NearRow* near_rows_d = nullptr;
   NearSeg* near_segs_d = nullptr;
   int64_t n_near_rows = 0;
+  // matrix-core forms (four or more right-hand sides)
+  MfRow* near_mf_rows_d = nullptr;      // one per leaf, segments near_segs_d
+  MfRow* coup_mf_rows_d = nullptr;      // one per row slot, segments coup_mf_segs_d
+  NearSeg* coup_mf_segs_d = nullptr;
+  SlotT* xh_tr_d = nullptr;             // row-major copies of x_sc into xhT_d
+  void* xhT_d = nullptr;
+  int64_t n_xh_tr = 0;
   int64_t near_matvec_bytes = 0;    // matrix bytes streamed by the near-field kernel
 
   template <class T>
@@ -923,26 +930,50 @@ struct Builder {
         }
       end_phase();
     }
-    // coupling: its own kernel, one entry per row slot
+    // coupling: its own kernel, one entry per row slot.  The matrix-core form
+    // reads x_sc from a row-major copy: column slot q occupies rows
+    // [xro[q], xro[q] + k_q) of xhT.
+    std::vector<int64_t> xro(ns, -1);
+    std::vector<SlotT> xtr;
+    int64_t xrows = 0;
+    for (int64_t q = 0; q < ns; ++q)
+      if (h.rank_col[q] > 0) {
+        xro[q] = xrows;
+        xtr.push_back({xh + xo[q], xrows, h.rank_col[q], 0});
+        xrows += h.rank_col[q];
+      }
+    h.xhT_d = h.alloc<C64>((size_t)std::max<int64_t>(xrows * nr, 1));
     std::vector<CoupRow> crows;
     std::vector<CoupBlk> cblks;
+    std::vector<MfRow> mrows;
+    std::vector<NearSeg> msegs;
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_row[q] > 0) {
         const int kq = h.rank_row[q];
         CoupRow r{yh + yo[q], kq, (int32_t)cblks.size(), 0, 0};
+        MfRow mr{yh + yo[q], kq, kq, (int32_t)msegs.size(), 0};
         for (int64_t e = p.row_ptr[q]; e < p.row_ptr[q + 1]; ++e) {
           const int64_t b = p.row_blk[e];
           const AdmBlock& a = p.adm[b];
           const int64_t qs = p.slot_of(a.s, a.c);
           const int ks = h.rank_col[qs];
-          if (ks > 0) cblks.push_back({(C64*)h.St_d + h.St_off[b], xh + xo[qs], ks, 0});
+          if (ks > 0) {
+            cblks.push_back({(C64*)h.St_d + h.St_off[b], xh + xo[qs], ks, 0});
+            msegs.push_back({(C64*)h.St_d + h.St_off[b], xro[qs], kq, ks});
+          }
         }
         r.blk_end = (int32_t)cblks.size();
+        mr.seg_end = (int32_t)msegs.size();
         crows.push_back(r);
+        mrows.push_back(mr);
       }
     h.coup_rows_d = h.upload(crows);
     h.coup_blks_d = h.upload(cblks);
     h.n_coup_rows = (int64_t)crows.size();
+    h.coup_mf_rows_d = h.upload(mrows);
+    h.coup_mf_segs_d = h.upload(msegs);
+    h.xh_tr_d = h.upload(xtr);
+    h.n_xh_tr = (int64_t)xtr.size();
     // backward, top-down: y_{t'c'} += F_{t'c} y_tc
     group = 3;
     for (int l = 1; l <= p.depth; ++l) {
@@ -1000,6 +1031,12 @@ struct Builder {
     h.near_rows_d = h.upload(nrows);
     h.near_segs_d = h.upload(nsegs);
     h.n_near_rows = (int64_t)nrows.size();
+    {
+      std::vector<MfRow> mf;
+      mf.reserve(nrows.size());
+      for (const NearRow& r : nrows) mf.push_back({Yp + r.row0, (int32_t)n, r.nr, r.seg_begin, r.seg_end});
+      h.near_mf_rows_d = h.upload(mf);
+    }
     h.near_matvec_bytes = nbytes * (int64_t)sizeof(C64);
     // leaf output: Y_t += Q_tc y_tc (after the near field)
     group = 5;
@@ -1329,13 +1366,27 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
   launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
   mark(1);
   terms(1);
+  // four or more right-hand sides: matrix-core block rows on row-major copies
+  const bool mf = nrhs >= 4;
   mark(2);
-  launch_mv_coupling<double>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
+  if (mf) {
+    launch_mv_slot_transpose<double>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
+    launch_mv_rows_mfma<double>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, nrhs,
+                                h->stream);
+  } else {
+    launch_mv_coupling<double>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
+  }
   mark(3);
   terms(3);
   mark(4);
-  launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
-                         h->stream, h->XT_d);
+  if (mf) {
+    launch_mv_transpose<double>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
+    launch_mv_rows_mfma<double>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, nrhs,
+                                h->stream);
+  } else {
+    launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
+                           h->stream, h->XT_d);
+  }
   mark(5);
   terms(5);
   mark(6);

@@ -204,19 +204,23 @@ __global__ void __launch_bounds__(256) k_mv_near_multi(const NearRow* __restrict
   }
 }
 
-// Matrix-core form of the near field for four or more right-hand sides.  A
-// 16x16x4 MFMA multiplies a 16-row, 4-column slice of a segment by the
-// matching 4 x 16 slice of X (row-major XT); lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16].  The complex product uses three real products,
-//   T1 = (Re N + Im N) Re X,  T2 = Re N (Im X - Re X),  T3 = Im N (Re X + Im X),
+// Matrix-core block-row product for four or more right-hand sides, used by the
+// near field (a row = a leaf cluster, its segments = the inadmissible blocks
+// restricted to its rows) and by the coupling phase (a row = a row slot (t, c),
+// its segments = the recompressed couplings Stilde_b of its admissible blocks).
+// A 16x16x4 MFMA multiplies a 16-row, 4-column slice of a segment by the
+// matching 4 x 16 slice of the row-major right-hand side; lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  The complex product uses three real
+// products,
+//   T1 = (Re A + Im A) Re X,  T2 = Re A (Im X - Re X),  T3 = Im A (Re X + Im X),
 //   Re Y = T1 - T3,  Im Y = T1 + T2,
-// so every matrix entry is loaded once (16 bytes per lane, coalesced along the
-// column) and feeds three MFMAs.  A workgroup owns one leaf row cluster (at most
-// 64 rows = four row tiles); its waves take interleaved segments, the loads of
+// so every matrix entry is loaded once (one 16-byte load per lane, coalesced
+// along the column) and feeds three MFMAs.  A workgroup owns one row (64 rows =
+// four row tiles per pass); its waves take interleaved segments, the loads of
 // the next column slice are issued before the products of the current one, and
 // the wave partial sums are added in LDS.  Workgroups are mapped so that each
-// XCD walks a contiguous range of leaves (neighbouring leaves share X rows in
-// that XCD's L2).
+// XCD walks a contiguous range of rows (neighbouring rows share right-hand-side
+// rows in that XCD's L2).
 typedef double mf64x4 __attribute__((ext_vector_type(4)));
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 template <typename R>
@@ -240,107 +244,141 @@ struct Mfma<float> {
 };
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_mv_near_mfma(const NearRow* __restrict__ rows,
+__global__ void __launch_bounds__(256) k_mv_rows_mfma(const MfRow* __restrict__ rows,
                                                       const NearSeg* __restrict__ segs,
-                                                      const cpx<R>* __restrict__ XT,
-                                                      cpx<R>* __restrict__ Y, int64_t n, int nrhs,
+                                                      const cpx<R>* __restrict__ XT, int nrhs,
                                                       int nrow_total) {
   typedef typename Mfma<R>::acc_t acc_t;
   constexpr int KU = 2;                          // 4-column slices per step
   // XCD-aware order: workgroup b runs on XCD b % 8; XCD x takes the x-th
-  // contiguous share of the leaves
+  // contiguous share of the rows
   const int b = blockIdx.x;
   const int q = nrow_total >> 3, rm = nrow_total & 7, xcd = b & 7;
-  const NearRow rw = rows[xcd * q + min(xcd, rm) + (b >> 3)];
+  const MfRow rw = rows[xcd * q + min(xcd, rm) + (b >> 3)];
+  cpx<R>* __restrict__ Y = (cpx<R>*)rw.y;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kc = lane >> 4, rr = lane & 15;
-  const int ntile = (rw.nr + 15) >> 4;
   __shared__ cpx<R> red[16][65];
-  for (int c0 = 0; c0 < nrhs; c0 += 16) {
-    const bool bact = c0 + rr < nrhs;
-    acc_t t1[4], t2[4], t3[4];
+  for (int r0 = 0; r0 < rw.nr; r0 += 64) {
+    const int nr = min(64, rw.nr - r0);
+    const int ntile = (nr + 15) >> 4;
+    for (int c0 = 0; c0 < nrhs; c0 += 16) {
+      const bool bact = c0 + rr < nrhs;
+      acc_t t1[4], t2[4], t3[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) t1[rt][e] = t2[rt][e] = t3[rt][e] = R(0);
-    cpx<R> a[KU][4], x[KU], na[KU][4], nx[KU];
-    // (sg, j0): segment and first column of the next step of this wave
-    int sg = rw.seg_begin + wave, j0 = 0;
-    auto fetch = [&](int fsg, int fj0, cpx<R> (&fa)[KU][4], cpx<R> (&fx)[KU]) {
-      const bool ok = fsg < rw.seg_end;
-      NearSeg s{nullptr, 0, 0, 0};
-      if (ok) s = segs[fsg];
-      const cpx<R>* A = (const cpx<R>*)s.A;
-      const cpx<R>* xb = XT + s.x0 * nrhs + c0 + rr;
+        for (int e = 0; e < 4; ++e) t1[rt][e] = t2[rt][e] = t3[rt][e] = R(0);
+      cpx<R> a[KU][4], x[KU], na[KU][4], nx[KU];
+      auto fetch = [&](int fsg, int fj0, cpx<R> (&fa)[KU][4], cpx<R> (&fx)[KU]) {
+        const bool ok = fsg < rw.seg_end;
+        NearSeg s{nullptr, 0, 0, 0};
+        if (ok) s = segs[fsg];
+        const cpx<R>* A = (const cpx<R>*)s.A + r0;
+        const cpx<R>* xb = XT + s.x0 * nrhs + c0 + rr;
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const int j = fj0 + 4 * u + kc;
-        const bool cj = ok && j < s.ncols;
-        fx[u] = (cj && bact) ? xb[(int64_t)j * nrhs] : cpx<R>{0, 0};
+        for (int u = 0; u < KU; ++u) {
+          const int j = fj0 + 4 * u + kc;
+          const bool cj = ok && j < s.ncols;
+          fx[u] = (cj && bact) ? xb[(int64_t)j * nrhs] : cpx<R>{0, 0};
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const int i = rt * 16 + rr;
-          fa[u][rt] = (cj && i < rw.nr) ? A[i + (int64_t)j * s.lda] : cpx<R>{0, 0};
-        }
-      }
-    };
-    fetch(sg, j0, a, x);
-    while (sg < rw.seg_end) {
-      // advance to the following step and issue its loads
-      const int ncols = segs[sg].ncols;
-      int sg2 = sg, j2 = j0 + 4 * KU;
-      if (j2 >= ncols) {
-        sg2 += 4;
-        j2 = 0;
-      }
-      fetch(sg2, j2, na, nx);
-#pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const R b1 = x[u].x, b2 = x[u].y - x[u].x, b3 = x[u].x + x[u].y;
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          if (rt < ntile) {
-            t1[rt] = Mfma<R>::mac(a[u][rt].x + a[u][rt].y, b1, t1[rt]);
-            t2[rt] = Mfma<R>::mac(a[u][rt].x, b2, t2[rt]);
-            t3[rt] = Mfma<R>::mac(a[u][rt].y, b3, t3[rt]);
+          for (int rt = 0; rt < 4; ++rt) {
+            const int i = rt * 16 + rr;
+            fa[u][rt] = (cj && i < nr) ? A[i + (int64_t)j * s.lda] : cpx<R>{0, 0};
           }
         }
-      }
+      };
+      // (sg, j0): segment and first column of this wave's current step
+      int sg = rw.seg_begin + wave, j0 = 0;
+      fetch(sg, j0, a, x);
+      while (sg < rw.seg_end) {
+        // advance to the following step and issue its loads
+        const int ncols = segs[sg].ncols;
+        int sg2 = sg, j2 = j0 + 4 * KU;
+        if (j2 >= ncols) {
+          sg2 += 4;
+          j2 = 0;
+        }
+        fetch(sg2, j2, na, nx);
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        x[u] = nx[u];
+        for (int u = 0; u < KU; ++u) {
+          const R b1 = x[u].x, b2 = x[u].y - x[u].x, b3 = x[u].x + x[u].y;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) a[u][rt] = na[u][rt];
-      }
-      sg = sg2;
-      j0 = j2;
-    }
-    // wave partial sums into LDS, one wave after the other
-    for (int w = 0; w < 4; ++w) {
-      if (wave == w) {
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          if (rt < ntile) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int row = rt * 16 + Mfma<R>::row(lane, e);
-              const cpx<R> v{t1[rt][e] - t3[rt][e], t1[rt][e] + t2[rt][e]};
-              if (w == 0) red[rr][row] = v;
-              else red[rr][row] = red[rr][row] + v;
+          for (int rt = 0; rt < 4; ++rt) {
+            if (rt < ntile) {
+              t1[rt] = Mfma<R>::mac(a[u][rt].x + a[u][rt].y, b1, t1[rt]);
+              t2[rt] = Mfma<R>::mac(a[u][rt].x, b2, t2[rt]);
+              t3[rt] = Mfma<R>::mac(a[u][rt].y, b3, t3[rt]);
             }
           }
         }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+          x[u] = nx[u];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) a[u][rt] = na[u][rt];
+        }
+        sg = sg2;
+        j0 = j2;
+      }
+      // wave partial sums into LDS, one wave after the other
+      for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            if (rt < ntile) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int row = rt * 16 + Mfma<R>::row(lane, e);
+                const cpx<R> v{t1[rt][e] - t3[rt][e], t1[rt][e] + t2[rt][e]};
+                if (w == 0) red[rr][row] = v;
+                else red[rr][row] = red[rr][row] + v;
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      for (int e = tid; e < 16 * 64; e += 256) {
+        const int row = e & 63, r = e >> 6;
+        if (row < nr && c0 + r < nrhs) Y[r0 + row + (int64_t)(c0 + r) * rw.ldy] = red[r][row];
       }
       __syncthreads();
     }
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int row = e & 63, r = e >> 6;
-      if (row < rw.nr && c0 + r < nrhs) Y[rw.row0 + row + (int64_t)(c0 + r) * n] = red[r][row];
-    }
-    __syncthreads();
   }
 }
+
+template <typename R>
+void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT, int nrhs,
+                         hipStream_t st) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_mv_rows_mfma<R>, dim3((unsigned)nrows), dim3(256), 0, st, rows, segs,
+                     (const cpx<R>*)XT, nrhs, (int)nrows);
+}
+template void launch_mv_rows_mfma<double>(const MfRow*, int64_t, const NearSeg*, const void*, int, hipStream_t);
+template void launch_mv_rows_mfma<float>(const MfRow*, int64_t, const NearSeg*, const void*, int, hipStream_t);
+
+// row-major copies of the slot vectors x_sc (k x nrhs, leading dimension k):
+// dst[(row0 + j) * nrhs + r] = src[j + r k]; a workgroup per slot
+template <typename R>
+__global__ void __launch_bounds__(256) k_mv_slot_transpose(const SlotT* __restrict__ d,
+                                                           cpx<R>* __restrict__ dst, int nrhs) {
+  const SlotT t = d[blockIdx.x];
+  const cpx<R>* src = (const cpx<R>*)t.src;
+  for (int e = threadIdx.x; e < t.k * nrhs; e += blockDim.x) {
+    const int j = e / nrhs, r = e % nrhs;
+    dst[(t.row0 + j) * nrhs + r] = src[j + (int64_t)r * t.k];
+  }
+}
+
+template <typename R>
+void launch_mv_slot_transpose(const SlotT* d, int64_t cnt, void* dst, int nrhs, hipStream_t st) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_mv_slot_transpose<R>, dim3((unsigned)cnt), dim3(256), 0, st, d, (cpx<R>*)dst, nrhs);
+}
+template void launch_mv_slot_transpose<double>(const SlotT*, int64_t, void*, int, hipStream_t);
+template void launch_mv_slot_transpose<float>(const SlotT*, int64_t, void*, int, hipStream_t);
 
 // Coupling phase y_tc = sum_b Stilde_b x_sc (the admissible leaves of eq. (vsw)
 // in the new bases): a workgroup per row slot; its eight half-waves take
@@ -433,6 +471,16 @@ __global__ void k_mv_transpose(const cpx<R>* __restrict__ Xp, cpx<R>* __restrict
 }
 
 template <typename R>
+void launch_mv_transpose(const void* X, void* XT, int64_t n, int nrhs, hipStream_t st) {
+  const int64_t tot = n * nrhs;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_mv_transpose<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     (const cpx<R>*)X, (cpx<R>*)XT, n, nrhs);
+}
+template void launch_mv_transpose<double>(const void*, void*, int64_t, int, hipStream_t);
+template void launch_mv_transpose<float>(const void*, void*, int64_t, int, hipStream_t);
+
+template <typename R>
 void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
                     int64_t n, int nrhs, hipStream_t st, void* XT) {
   if (nrows <= 0) return;
@@ -446,9 +494,12 @@ void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, con
                      (const cpx<R>*)X, (cpx<R>*)XT, n, nrhs);
   if (nrhs == 2)
     hipLaunchKernelGGL((k_mv_near_multi<R, 2>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs <= 4)
+    hipLaunchKernelGGL((k_mv_near_multi<R, 4>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
+  else if (nrhs <= 8)
+    hipLaunchKernelGGL((k_mv_near_multi<R, 8>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
   else
-    hipLaunchKernelGGL(k_mv_near_mfma<R>, g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs,
-                       (int)nrows);
+    hipLaunchKernelGGL((k_mv_near_multi<R, 16>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
 }
 template void launch_mv_near<double>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
                                      int64_t, int, hipStream_t, void*);

@@ -62,6 +62,33 @@ template <typename R>
 void launch_mv_coupling(const CoupRow* rows, int64_t nrows, const CoupBlk* blks, int nrhs,
                         hipStream_t st);
 
+// Block row of the matrix-core product: y (nr x nrhs, leading dimension ldy) =
+// sum over the segments [seg_begin, seg_end) of A (nr x ncols, leading
+// dimension lda) times rows [x0, x0 + ncols) of a row-major right-hand side
+// XT[row * nrhs + r].  Used for the near field (Y rows of a leaf) and the
+// coupling phase (y_tc of a row slot).
+struct MfRow {
+  void* y;
+  int32_t ldy, nr;
+  int32_t seg_begin, seg_end;
+};
+template <typename R>
+void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT, int nrhs,
+                         hipStream_t st);
+
+// Row-major copy of one slot vector: dst[(row0 + j) * nrhs + r] = src[j + r k].
+struct SlotT {
+  const void* src;
+  int64_t row0;
+  int32_t k, pad;
+};
+template <typename R>
+void launch_mv_slot_transpose(const SlotT* d, int64_t cnt, void* dst, int nrhs, hipStream_t st);
+
+// The generic transpose of the gathered X into row-major XT (XT[p nrhs + r]).
+template <typename R>
+void launch_mv_transpose(const void* X, void* XT, int64_t n, int nrhs, hipStream_t st);
+
 template <typename R>
 void launch_mv_terms(const MvOut* outs, int64_t nout, const MvTerm* terms, int nrhs, hipStream_t st);
 template <typename R>
