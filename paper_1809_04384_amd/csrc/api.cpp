@@ -176,6 +176,7 @@ struct dh2_problem {
   NearSeg* coup_mf_segs_d = nullptr;
   SlotT* xh_tr_d = nullptr;             // row-major copies of x_sc into xhT_d
   void* xhT_d = nullptr;
+  void* zero16_d = nullptr;             // 16 zero elements, never written after the build
   int64_t n_xh_tr = 0;
   int64_t near_matvec_bytes = 0;    // matrix bytes streamed by the near-field kernel
 
@@ -943,6 +944,8 @@ struct Builder {
         xrows += h.rank_col[q];
       }
     h.xhT_d = h.alloc<C64>((size_t)std::max<int64_t>(xrows * nr, 1));
+    h.zero16_d = h.alloc<C64>(16);
+    HIPCHK(hipMemsetAsync(h.zero16_d, 0, 16 * sizeof(C64), h.stream));
     std::vector<CoupRow> crows;
     std::vector<CoupBlk> cblks;
     std::vector<MfRow> mrows;
@@ -1371,8 +1374,8 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
   mark(2);
   if (mf) {
     launch_mv_slot_transpose<double>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
-    launch_mv_rows_mfma<double>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, nrhs,
-                                h->stream);
+    launch_mv_rows_mfma<double>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d,
+                                nrhs, h->stream);
   } else {
     launch_mv_coupling<double>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
   }
@@ -1381,8 +1384,8 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
   mark(4);
   if (mf) {
     launch_mv_transpose<double>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
-    launch_mv_rows_mfma<double>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, nrhs,
-                                h->stream);
+    launch_mv_rows_mfma<double>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d,
+                                nrhs, h->stream);
   } else {
     launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
                            h->stream, h->XT_d);

@@ -243,103 +243,141 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
 };
 
+// Loads through a global (address space 1) pointer: the pointers of the
+// descriptors are generic, and generic (flat) loads make the compiler wait for
+// every outstanding load before the first use.
 template <typename R>
-__global__ void __launch_bounds__(256) k_mv_rows_mfma(const MfRow* __restrict__ rows,
-                                                      const NearSeg* __restrict__ segs,
-                                                      const cpx<R>* __restrict__ XT, int nrhs,
-                                                      int nrow_total) {
+__device__ __forceinline__ cpx<R> gload(const cpx<R>* p) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return cpx<R>{v.x, v.y};
+}
+
+// One pass of a block row: rows [r0, r0 + nr) (NT = ceil(nr / 16) row tiles)
+// and right-hand sides [c0, c0 + 16), over the T steps of this wave; the wave
+// partial sums are added into red[rhs][row] (one wave after the other).
+template <typename R, int KU, int S, int NT>
+__device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restrict__ segs,
+                                        const cpx<R>* __restrict__ XT, const cpx<R>* __restrict__ zero16,
+                                        int nrhs, int wave, int T, int r0, int nr, int c0,
+                                        cpx<R> (&red)[16][65]) {
   typedef typename Mfma<R>::acc_t acc_t;
-  constexpr int KU = 2;                          // 4-column slices per step
+  constexpr int SW = 4 * KU;
+  const int lane = threadIdx.x & 63;
+  const int kc = lane >> 4, rr = lane & 15;
+  const bool bact = c0 + rr < nrhs;
+  acc_t t1[NT], t2[NT], t3[NT];
+#pragma unroll
+  for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t1[rt][e] = t2[rt][e] = t3[rt][e] = R(0);
+  if (T > 0) {
+    cpx<R> a[S][KU][NT], x[S][KU];
+    // fetch position: segment fsg (descriptor fs), first column fj0.  Past the
+    // last segment fs keeps a valid address with no columns, so every load
+    // stays in bounds and the stage is zero.
+    int fsg = rw.seg_begin + wave, fj0 = 0;
+    NearSeg fs = segs[fsg];
+    // Loads are never masked (a select would wait for the data): rows past nr
+    // read row nr - 1 (those outputs are dropped), columns past the segment
+    // read its last column, and their right-hand side comes from zero16, so
+    // they add nothing.
+    auto fetch = [&](cpx<R> (&fa)[KU][NT], cpx<R> (&fx)[KU]) {
+      const cpx<R>* A = (const cpx<R>*)fs.A + r0;
+      const cpx<R>* xb = XT + fs.x0 * nrhs + c0 + rr;
+      const int jl = max(fs.ncols - 1, 0);
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int j = fj0 + 4 * u + kc;
+        const int jc = min(j, jl);
+        const cpx<R>* xp = (j < fs.ncols && bact) ? xb + (int64_t)j * nrhs : zero16 + rr;
+        fx[u] = gload(xp);
+#pragma unroll
+        for (int rt = 0; rt < NT; ++rt) fa[u][rt] = gload(A + min(rt * 16 + rr, nr - 1) + (int64_t)jc * fs.lda);
+      }
+    };
+    auto advance = [&]() {
+      fj0 += SW;
+      if (fj0 >= fs.ncols) {
+        fsg += 4;
+        fj0 = 0;
+        if (fsg < rw.seg_end) fs = segs[fsg];
+        else fs.ncols = 0;
+      }
+    };
+#pragma unroll
+    for (int st = 0; st < S - 1; ++st) {
+      fetch(a[st], x[st]);
+      advance();
+    }
+    for (int done = 0; done < T; done += S) {
+#pragma unroll
+      for (int st = 0; st < S; ++st) {
+        fetch(a[(st + S - 1) % S], x[(st + S - 1) % S]);
+        advance();
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+          const cpx<R> xv = x[st][u];
+          const R b1 = xv.x, b2 = xv.y - xv.x, b3 = xv.x + xv.y;
+#pragma unroll
+          for (int rt = 0; rt < NT; ++rt) {
+            const cpx<R> av = a[st][u][rt];
+            t1[rt] = Mfma<R>::mac(av.x + av.y, b1, t1[rt]);
+            t2[rt] = Mfma<R>::mac(av.x, b2, t2[rt]);
+            t3[rt] = Mfma<R>::mac(av.y, b3, t3[rt]);
+          }
+        }
+      }
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = rt * 16 + Mfma<R>::row(lane, e);
+          const cpx<R> v{t1[rt][e] - t3[rt][e], t1[rt][e] + t2[rt][e]};
+          if (w == 0) red[rr][row] = v;
+          else red[rr][row] = red[rr][row] + v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+#ifndef DH2_MF_WPE
+#define DH2_MF_WPE 2
+#endif
+template <typename R, int KU, int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF_WPE))) k_mv_rows_mfma(const MfRow* __restrict__ rows,
+                                                      const NearSeg* __restrict__ segs,
+                                                      const cpx<R>* __restrict__ XT,
+                                                      const cpx<R>* __restrict__ zero16, int nrhs,
+                                                      int nrow_total) {
+  // KU 4-column slices per step; S register stages (S - 1 steps in flight)
+  constexpr int SW = 4 * KU;
   // XCD-aware order: workgroup b runs on XCD b % 8; XCD x takes the x-th
   // contiguous share of the rows
   const int b = blockIdx.x;
   const int q = nrow_total >> 3, rm = nrow_total & 7, xcd = b & 7;
   const MfRow rw = rows[xcd * q + min(xcd, rm) + (b >> 3)];
   cpx<R>* __restrict__ Y = (cpx<R>*)rw.y;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int kc = lane >> 4, rr = lane & 15;
   __shared__ cpx<R> red[16][65];
+  // steps of this wave: its segments are seg_begin + wave + 4 i
+  int T = 0;
+  for (int sg = rw.seg_begin + wave; sg < rw.seg_end; sg += 4) T += (segs[sg].ncols + SW - 1) / SW;
   for (int r0 = 0; r0 < rw.nr; r0 += 64) {
     const int nr = min(64, rw.nr - r0);
     const int ntile = (nr + 15) >> 4;
     for (int c0 = 0; c0 < nrhs; c0 += 16) {
-      const bool bact = c0 + rr < nrhs;
-      acc_t t1[4], t2[4], t3[4];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) t1[rt][e] = t2[rt][e] = t3[rt][e] = R(0);
-      cpx<R> a[KU][4], x[KU], na[KU][4], nx[KU];
-      auto fetch = [&](int fsg, int fj0, cpx<R> (&fa)[KU][4], cpx<R> (&fx)[KU]) {
-        const bool ok = fsg < rw.seg_end;
-        NearSeg s{nullptr, 0, 0, 0};
-        if (ok) s = segs[fsg];
-        const cpx<R>* A = (const cpx<R>*)s.A + r0;
-        const cpx<R>* xb = XT + s.x0 * nrhs + c0 + rr;
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {
-          const int j = fj0 + 4 * u + kc;
-          const bool cj = ok && j < s.ncols;
-          fx[u] = (cj && bact) ? xb[(int64_t)j * nrhs] : cpx<R>{0, 0};
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const int i = rt * 16 + rr;
-            fa[u][rt] = (cj && i < nr) ? A[i + (int64_t)j * s.lda] : cpx<R>{0, 0};
-          }
-        }
-      };
-      // (sg, j0): segment and first column of this wave's current step
-      int sg = rw.seg_begin + wave, j0 = 0;
-      fetch(sg, j0, a, x);
-      while (sg < rw.seg_end) {
-        // advance to the following step and issue its loads
-        const int ncols = segs[sg].ncols;
-        int sg2 = sg, j2 = j0 + 4 * KU;
-        if (j2 >= ncols) {
-          sg2 += 4;
-          j2 = 0;
-        }
-        fetch(sg2, j2, na, nx);
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {
-          const R b1 = x[u].x, b2 = x[u].y - x[u].x, b3 = x[u].x + x[u].y;
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            if (rt < ntile) {
-              t1[rt] = Mfma<R>::mac(a[u][rt].x + a[u][rt].y, b1, t1[rt]);
-              t2[rt] = Mfma<R>::mac(a[u][rt].x, b2, t2[rt]);
-              t3[rt] = Mfma<R>::mac(a[u][rt].y, b3, t3[rt]);
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {
-          x[u] = nx[u];
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) a[u][rt] = na[u][rt];
-        }
-        sg = sg2;
-        j0 = j2;
-      }
-      // wave partial sums into LDS, one wave after the other
-      for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            if (rt < ntile) {
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const int row = rt * 16 + Mfma<R>::row(lane, e);
-                const cpx<R> v{t1[rt][e] - t3[rt][e], t1[rt][e] + t2[rt][e]};
-                if (w == 0) red[rr][row] = v;
-                else red[rr][row] = red[rr][row] + v;
-              }
-            }
-          }
-        }
-        __syncthreads();
-      }
+      if (ntile == 1) mf_pass<R, KU, S, 1>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      else if (ntile == 2) mf_pass<R, KU, S, 2>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      else if (ntile == 3) mf_pass<R, KU, S, 3>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      else mf_pass<R, KU, S, 4>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
       for (int e = tid; e < 16 * 64; e += 256) {
         const int row = e & 63, r = e >> 6;
         if (row < nr && c0 + r < nrhs) Y[r0 + row + (int64_t)(c0 + r) * rw.ldy] = red[r][row];
@@ -349,15 +387,24 @@ __global__ void __launch_bounds__(256) k_mv_rows_mfma(const MfRow* __restrict__ 
   }
 }
 
+#ifndef DH2_MF_KU
+#define DH2_MF_KU 1
+#endif
+#ifndef DH2_MF_S
+#define DH2_MF_S 4
+#endif
+
 template <typename R>
-void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT, int nrhs,
-                         hipStream_t st) {
+void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT,
+                         const void* zero16, int nrhs, hipStream_t st) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL(k_mv_rows_mfma<R>, dim3((unsigned)nrows), dim3(256), 0, st, rows, segs,
-                     (const cpx<R>*)XT, nrhs, (int)nrows);
+  hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S>), dim3((unsigned)nrows), dim3(256), 0, st, rows,
+                     segs, (const cpx<R>*)XT, (const cpx<R>*)zero16, nrhs, (int)nrows);
 }
-template void launch_mv_rows_mfma<double>(const MfRow*, int64_t, const NearSeg*, const void*, int, hipStream_t);
-template void launch_mv_rows_mfma<float>(const MfRow*, int64_t, const NearSeg*, const void*, int, hipStream_t);
+template void launch_mv_rows_mfma<double>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
+                                          hipStream_t);
+template void launch_mv_rows_mfma<float>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
+                                         hipStream_t);
 
 // row-major copies of the slot vectors x_sc (k x nrhs, leading dimension k):
 // dst[(row0 + j) * nrhs + r] = src[j + r k]; a workgroup per slot
