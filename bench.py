@@ -40,7 +40,46 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=3)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain streaming kernel (read MIB MiB, write MIB MiB) and exit; "
+                         "its HBM counters calibrate the traffic of the profiled kernels")
     return ap.parse_args()
+
+
+PMC_FILE = os.path.join(ROOT, "profiles", "k_mv_rows_mfma_near_sphere131k_pmc.txt")
+MATVEC_SRC = os.path.join(ROOT, "paper_1809_04384_amd", "csrc", "matvec.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the near-field kernel from the stored rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the
+    streaming-kernel calibration), or None when the summary is missing or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    for line in open(PMC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(MATVEC_SRC, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
 
 
 def log(*a):
@@ -104,6 +143,9 @@ def main():
         print("bench.py measures one GPU; --gpus %d is not supported (the path runs on one "
               "MI355X; see the design notes for how it would shard)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
     from paper_1809_04384_amd import dh2
 
@@ -211,8 +253,10 @@ def main():
             "coupling": round(st["coupling_entries"] * 16 / 1024 / n, 1),
             "basis": round(st["basis_entries"] * 16 / 1024 / n, 1)},
         "roofline": {"bound": "hbm", "achieved": round(near_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(near_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_mv_near (near-field matvec)",
+                     "frac": round(near_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic() if args.workload == "sphere131k" else None,
+                     "kernel": ("k_mv_rows_mfma<double,1,4,0> (near-field block rows on matrix cores)" if nrhs >= 4
+                                else "k_mv_near (near-field rows, vector ALU)"),
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
         "cpu_baseline": base,
     }

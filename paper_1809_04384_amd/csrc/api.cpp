@@ -1365,31 +1365,29 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
         launch_mv_terms<double>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
                                 nrhs, h->stream);
   };
-  mark(0);
-  launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
-  mark(1);
-  terms(1);
   // four or more right-hand sides: matrix-core block rows on row-major copies
   const bool mf = nrhs >= 4;
+  mark(0);
+  launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
+  if (mf) launch_mv_transpose<double>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
+  mark(1);
+  terms(1);
+  if (mf) launch_mv_slot_transpose<double>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
   mark(2);
-  if (mf) {
-    launch_mv_slot_transpose<double>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
+  if (mf)
     launch_mv_rows_mfma<double>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d,
-                                nrhs, h->stream);
-  } else {
+                                nrhs, 1, h->stream);
+  else
     launch_mv_coupling<double>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
-  }
   mark(3);
   terms(3);
   mark(4);
-  if (mf) {
-    launch_mv_transpose<double>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
+  if (mf)
     launch_mv_rows_mfma<double>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d,
-                                nrhs, h->stream);
-  } else {
+                                nrhs, 0, h->stream);
+  else
     launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
                            h->stream, h->XT_d);
-  }
   mark(5);
   terms(5);
   mark(6);

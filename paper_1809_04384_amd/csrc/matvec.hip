@@ -350,7 +350,9 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
 #ifndef DH2_MF_WPE
 #define DH2_MF_WPE 2
 #endif
-template <typename R, int KU, int S>
+// ROLE only names the instantiation (0 near field, 1 coupling) so that the two
+// uses are told apart in kernel traces.
+template <typename R, int KU, int S, int ROLE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF_WPE))) k_mv_rows_mfma(const MfRow* __restrict__ rows,
                                                       const NearSeg* __restrict__ segs,
                                                       const cpx<R>* __restrict__ XT,
@@ -396,15 +398,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF
 
 template <typename R>
 void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT,
-                         const void* zero16, int nrhs, hipStream_t st) {
+                         const void* zero16, int nrhs, int role, hipStream_t st) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S>), dim3((unsigned)nrows), dim3(256), 0, st, rows,
-                     segs, (const cpx<R>*)XT, (const cpx<R>*)zero16, nrhs, (int)nrows);
+  if (role == 0)
+    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0>), dim3((unsigned)nrows), dim3(256), 0, st,
+                       rows, segs, (const cpx<R>*)XT, (const cpx<R>*)zero16, nrhs, (int)nrows);
+  else
+    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1>), dim3((unsigned)nrows), dim3(256), 0, st,
+                       rows, segs, (const cpx<R>*)XT, (const cpx<R>*)zero16, nrhs, (int)nrows);
 }
 template void launch_mv_rows_mfma<double>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
-                                          hipStream_t);
+                                          int, hipStream_t);
 template void launch_mv_rows_mfma<float>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
-                                         hipStream_t);
+                                         int, hipStream_t);
 
 // row-major copies of the slot vectors x_sc (k x nrhs, leading dimension k):
 // dst[(row0 + j) * nrhs + r] = src[j + r k]; a workgroup per slot

@@ -73,10 +73,10 @@ struct MfRow {
   int32_t seg_begin, seg_end;
 };
 // zero16: 16 zero elements (device), read in place of right-hand-side entries
-// outside a segment.
+// outside a segment.  role: 0 near field, 1 coupling (names the kernel only).
 template <typename R>
 void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT,
-                         const void* zero16, int nrhs, hipStream_t st);
+                         const void* zero16, int nrhs, int role, hipStream_t st);
 
 // Row-major copy of one slot vector: dst[(row0 + j) * nrhs + r] = src[j + r k].
 struct SlotT {
