@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=3)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming kernel (read MIB MiB, write MIB MiB) and exit; "
                          "its HBM counters calibrate the traffic of the profiled kernels")
@@ -137,6 +138,59 @@ def cpu_baseline(w, V, T, X, nleaves):
     }
 
 
+def fp32_form(args, w, V, T, X, Y64, dh2, torch):
+    """The FP32 form on the same workload: one build, event-timed matvecs on
+    complex64 right-hand sides (the FP64 draw rounded), and the relative
+    Frobenius difference of the full n x nrhs result from the FP64 form."""
+    nrhs = X.shape[0]
+    Xd = torch.from_numpy(X.astype(np.complex64)).to("cuda:0")
+    Yd = torch.empty_like(Xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
+                   max_nrhs=max(nrhs, 1))
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    st = h.stats()
+    h.matvec(Xd, Yd)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(args.matvec_reps):
+        ev0.record()
+        h.matvec(Xd, Yd)
+        ev1.record()
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    mv_ms = statistics.median(times)
+    mv_bytes = st["matvec_bytes"] + nrhs * st["matvec_bytes_per_rhs"]
+    phases = {}
+    near_ms = []
+    near_bytes = 0.0
+    for _ in range(args.matvec_reps):
+        ph, near_bytes = h.matvec_profile(Xd, Yd)
+        near_ms.append(ph["near"])
+        for k, v in ph.items():
+            phases.setdefault(k, []).append(v)
+    near_avg = sum(near_ms) / len(near_ms)
+    near_alg = near_bytes + 2.0 * 8.0 * len(T) * nrhs
+    h.matvec(Xd, Yd)
+    torch.cuda.synchronize()
+    err = (torch.linalg.vector_norm(Yd.to(torch.complex128) - Y64) / torch.linalg.vector_norm(Y64)).item()
+    h.free()
+    log("fp32 form: build %.2f s, matvec %.3f ms (%.1f GB/s), near %.3f ms (%.1f GB/s), rel. diff vs FP64 %.2e"
+        % (tb, mv_ms, mv_bytes / (mv_ms * 1e-3) / 1e9, near_avg, near_alg / (near_avg * 1e-3) / 1e9, err))
+    return {
+        "dtype": "f32 matvec and near field; FP64 recompression", "build_s": round(tb, 3),
+        "matvec_ms": round(mv_ms, 3), "value": round(mv_bytes / (mv_ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+        "rel_diff_vs_fp64": err,
+        "matvec_phases_ms": {k: round(sum(v) / len(v), 4) for k, v in phases.items()},
+        "near": {"achieved": round(near_alg / (near_avg * 1e-3) / 1e9, 1), "unit": "GB/s",
+                 "frac": round(near_alg / (near_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
+        "build_phases_ms": {k[3:]: round(v, 1) for k, v in st.items() if k.startswith("ms_")},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -215,7 +269,13 @@ def main():
     near_gbs = near_alg / (near_avg * 1e-3) / 1e9
     log("matvec %.3f ms (%.1f GB/s); near field %.3f ms, %.2f GB -> %.1f GB/s"
         % (mv_ms, mv_gbs, near_avg, near_alg / 1e9, near_gbs))
+    h.matvec(Xd, Yd)
+    Y64 = Yd.clone()
     h.free()
+
+    fp32 = None
+    if not args.no_fp32:
+        fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch)
 
     base = None
     if not args.no_cpu_baseline:
@@ -259,6 +319,7 @@ def main():
                                 else "k_mv_near (near-field rows, vector ALU)"),
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
         "cpu_baseline": base,
+        "fp32_form": fp32,
     }
     print(json.dumps(out), flush=True)
 

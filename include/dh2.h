@@ -50,9 +50,13 @@ typedef struct {
   const int32_t* triangles;
 } dh2_geometry;
 
-/* Precision of a handle: arithmetic of the interpolation, couplings, GEMMs and
- * matvec, and the element type of X / Y.  Householder QR and SVD of the
- * recompression are always FP64. */
+/* Precision of a handle.
+ *   DH2_FP64  everything in FP64; X / Y are complex128.
+ *   DH2_FP32  the near field is evaluated and stored in FP32; interpolation and
+ *             recompression run in FP64 (the same ranks as the FP64 form); the
+ *             recompressed couplings and bases are then rounded to complex64
+ *             and the matvec runs in FP32 on complex64 X / Y.
+ * Householder QR and SVD of the recompression are FP64 in both forms. */
 typedef enum { DH2_FP64 = 0, DH2_FP32 = 1 } dh2_precision;
 
 /* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then

@@ -157,7 +157,9 @@ struct dh2_problem {
   // compressed representation
   std::vector<z64*> Qr_ptr, Qc_ptr;   // Qhat per slot (m x rank, column-major)
   std::vector<int32_t> Qr_m, Qc_m;
-  void* St_d = nullptr;  std::vector<int64_t> St_off;
+  void* St_d = nullptr;  std::vector<int64_t> St_off;   // Stilde_b (element type of the handle)
+  int64_t St_total = 0;
+  std::vector<void*> Qr32, Qc32;      // FP32 handles: complex64 copies of Qhat used by the matvec
   // matvec schedule
   void* Xp_d = nullptr; void* Yp_d = nullptr; void* xh_d = nullptr; void* yh_d = nullptr;
   void* XT_d = nullptr;   // row-major copy of the gathered X (multi right-hand-side near field)
@@ -835,6 +837,7 @@ struct Builder {
       tot += (int64_t)h.rank_row[p.slot_of(a.t, a.c)] * h.rank_col[p.slot_of(a.s, a.c)];
     }
     h.St_d = h.alloc<C64>((size_t)std::max<int64_t>(tot, 1));
+    h.St_total = tot;
     const size_t per = (size_t)2 * k * k * sizeof(C64);
     const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
     for (int64_t b0 = 0; b0 < nb; b0 += batch) {
@@ -875,25 +878,75 @@ struct Builder {
   }
 
   // ------------------------------------------------------------------
-  // matvec schedule: phases of MvOut lists (see matvec.hip)
+  // FP32 handles: the recompressed couplings and the new bases are rounded to
+  // complex64 once, after the FP64 recompression; the FP64 couplings are freed.
+  void narrow_to_fp32() {
+    z32* St32 = h.alloc<z32>((size_t)std::max<int64_t>(h.St_total, 1));
+    launch_narrow(h.St_d, St32, h.St_total, h.stream);
+    h.check_launch();
+    h.sync();
+    h.release(h.St_d);
+    h.St_d = St32;
+    int64_t tot = 0;
+    for (int64_t q = 0; q < ns; ++q) {
+      if (h.rank_row[q] > 0) tot += (int64_t)h.Qr_m[q] * h.rank_row[q];
+      if (h.rank_col[q] > 0) tot += (int64_t)h.Qc_m[q] * h.rank_col[q];
+    }
+    z32* Q32 = h.alloc<z32>((size_t)std::max<int64_t>(tot, 1));
+    std::vector<NarrowDesc> nd;
+    h.Qr32.assign(ns, nullptr);
+    h.Qc32.assign(ns, nullptr);
+    int64_t off = 0;
+    for (int64_t q = 0; q < ns; ++q) {
+      if (h.rank_row[q] > 0) {
+        const int64_t m = (int64_t)h.Qr_m[q] * h.rank_row[q];
+        h.Qr32[q] = Q32 + off;
+        nd.push_back({h.Qr_ptr[q], Q32 + off, m});
+        off += m;
+      }
+      if (h.rank_col[q] > 0) {
+        const int64_t m = (int64_t)h.Qc_m[q] * h.rank_col[q];
+        h.Qc32[q] = Q32 + off;
+        nd.push_back({h.Qc_ptr[q], Q32 + off, m});
+        off += m;
+      }
+    }
+    if (!nd.empty()) {
+      NarrowDesc* ndd = h.upload(nd);
+      launch_narrow_list(ndd, (int64_t)nd.size(), h.stream);
+      h.check_launch();
+      h.sync();
+      h.release(ndd);
+    }
+  }
+
+  // ------------------------------------------------------------------
+  // matvec schedule: phases of MvOut lists (see matvec.hip).  Pointers are
+  // formed in elements of the handle's type (complex128 or complex64).
   void matvec_schedule() {
     const int nr = h.max_nrhs;
     const int64_t n = p.n;
-    h.Xp_d = h.alloc<C64>((size_t)n * nr);
-    h.XT_d = h.alloc<C64>((size_t)n * nr);
-    h.Yp_d = h.alloc<C64>((size_t)n * nr);
+    const bool f32 = h.precision == DH2_FP32;
+    const int64_t es = f32 ? (int64_t)sizeof(z32) : (int64_t)sizeof(C64);
+    auto at = [es](const void* base, int64_t e) -> char* { return (char*)base + e * es; };
+    auto valloc = [&](int64_t elems) -> char* { return h.alloc<char>((size_t)std::max<int64_t>(elems, 1) * es); };
+    auto Qr = [&](int64_t q) -> const void* { return f32 ? h.Qr32[q] : (const void*)h.Qr_ptr[q]; };
+    auto Qc = [&](int64_t q) -> const void* { return f32 ? h.Qc32[q] : (const void*)h.Qc_ptr[q]; };
+    h.Xp_d = valloc(n * nr);
+    h.XT_d = valloc(n * nr);
+    h.Yp_d = valloc(n * nr);
     std::vector<int64_t> xo(ns, -1), yo(ns, -1);
     int64_t xt = 0, yt = 0;
     for (int64_t q = 0; q < ns; ++q) {
       if (h.rank_col[q] > 0) { xo[q] = xt; xt += (int64_t)h.rank_col[q] * nr; }
       if (h.rank_row[q] > 0) { yo[q] = yt; yt += (int64_t)h.rank_row[q] * nr; }
     }
-    C64* xh = h.alloc<C64>((size_t)std::max<int64_t>(xt, 1));
-    C64* yh = h.alloc<C64>((size_t)std::max<int64_t>(yt, 1));
+    char* xh = valloc(xt);
+    char* yh = valloc(yt);
     h.xh_d = xh;
     h.yh_d = yh;
-    C64* Xp = (C64*)h.Xp_d;
-    C64* Yp = (C64*)h.Yp_d;
+    char* Xp = (char*)h.Xp_d;
+    char* Yp = (char*)h.Yp_d;
     std::vector<MvOut> outs;
     std::vector<MvTerm> terms;
     h.mv_phases.clear();
@@ -905,8 +958,8 @@ struct Builder {
     for (int64_t q = 0; q < ns; ++q)
       if (si[q].leaf && h.rank_col[q] > 0) {
         const int kq = h.rank_col[q];
-        MvOut o{xh + xo[q], kq, kq, (int32_t)terms.size(), 0, 0, 0};
-        terms.push_back({h.Qc_ptr[q], Xp + si[q].row0, si[q].nrows, si[q].nrows, (int32_t)n, 2});
+        MvOut o{at(xh, xo[q]), kq, kq, (int32_t)terms.size(), 0, 0, 0};
+        terms.push_back({Qc(q), at(Xp, si[q].row0), si[q].nrows, si[q].nrows, (int32_t)n, 2});
         o.term_end = (int32_t)terms.size();
         outs.push_back(o);
       }
@@ -917,13 +970,13 @@ struct Builder {
       for (int64_t q = 0; q < ns; ++q)
         if (si[q].level == l && !si[q].leaf && h.rank_col[q] > 0) {
           const int kq = h.rank_col[q];
-          MvOut o{xh + xo[q], kq, kq, (int32_t)terms.size(), 0, 0, 0};
+          MvOut o{at(xh, xo[q]), kq, kq, (int32_t)terms.size(), 0, 0, 0};
           int off = 0;
           for (int i = 0; i < 2; ++i) {
             const int64_t cq = si[q].child_slot[i];
             const int kc = h.rank_col[cq];
             if (kc > 0)
-              terms.push_back({h.Qc_ptr[q] + off, xh + xo[cq], kc, h.Qc_m[q], kc, 2});
+              terms.push_back({at(Qc(q), off), at(xh, xo[cq]), kc, h.Qc_m[q], kc, 2});
             off += kc;
           }
           o.term_end = (int32_t)terms.size();
@@ -940,10 +993,10 @@ struct Builder {
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_col[q] > 0) {
         xro[q] = xrows;
-        xtr.push_back({xh + xo[q], xrows, h.rank_col[q], 0});
+        xtr.push_back({at(xh, xo[q]), xrows, h.rank_col[q], 0});
         xrows += h.rank_col[q];
       }
-    h.xhT_d = h.alloc<C64>((size_t)std::max<int64_t>(xrows * nr, 1));
+    h.xhT_d = valloc(xrows * nr);
     h.zero16_d = h.alloc<C64>(16);
     HIPCHK(hipMemsetAsync(h.zero16_d, 0, 16 * sizeof(C64), h.stream));
     std::vector<CoupRow> crows;
@@ -953,16 +1006,16 @@ struct Builder {
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_row[q] > 0) {
         const int kq = h.rank_row[q];
-        CoupRow r{yh + yo[q], kq, (int32_t)cblks.size(), 0, 0};
-        MfRow mr{yh + yo[q], kq, kq, (int32_t)msegs.size(), 0};
+        CoupRow r{at(yh, yo[q]), kq, (int32_t)cblks.size(), 0, 0};
+        MfRow mr{at(yh, yo[q]), kq, kq, (int32_t)msegs.size(), 0};
         for (int64_t e = p.row_ptr[q]; e < p.row_ptr[q + 1]; ++e) {
           const int64_t b = p.row_blk[e];
           const AdmBlock& a = p.adm[b];
           const int64_t qs = p.slot_of(a.s, a.c);
           const int ks = h.rank_col[qs];
           if (ks > 0) {
-            cblks.push_back({(C64*)h.St_d + h.St_off[b], xh + xo[qs], ks, 0});
-            msegs.push_back({(C64*)h.St_d + h.St_off[b], xro[qs], kq, ks});
+            cblks.push_back({at(h.St_d, h.St_off[b]), at(xh, xo[qs]), ks, 0});
+            msegs.push_back({at(h.St_d, h.St_off[b]), xro[qs], kq, ks});
           }
         }
         r.blk_end = (int32_t)cblks.size();
@@ -984,13 +1037,13 @@ struct Builder {
       for (int64_t q = 0; q < ns; ++q)
         if (si[q].level == l && h.rank_row[q] > 0) {
           const int kq = h.rank_row[q];
-          MvOut o{yh + yo[q], kq, kq, (int32_t)terms.size(), 0, 1, 0};
+          MvOut o{at(yh, yo[q]), kq, kq, (int32_t)terms.size(), 0, 1, 0};
           const int ci = child_index(si[q].t);
           for (int64_t pq : parents_of(q, p.slot_row)) {
             const int kp = h.rank_row[pq];
             if (kp <= 0) continue;
             const int off = ci == 0 ? 0 : h.rank_row[si[pq].child_slot[0]];
-            terms.push_back({h.Qr_ptr[pq] + off, yh + yo[pq], kp, h.Qr_m[pq], kp, 0});
+            terms.push_back({at(Qr(pq), off), at(yh, yo[pq]), kp, h.Qr_m[pq], kp, 0});
           }
           o.term_end = (int32_t)terms.size();
           if (o.term_end > o.term_begin) outs.push_back(o);
@@ -1024,7 +1077,7 @@ struct Builder {
         const NearBlock& nbk = p.near[pr.first];
         const Cluster& tt = p.cl[nbk.t];
         const Cluster& ss = p.cl[nbk.s];
-        nsegs.push_back({(C64*)h.near_d + h.near_off[pr.first] + pr.second, ss.first, (int32_t)tt.size,
+        nsegs.push_back({at(h.near_d, h.near_off[pr.first] + pr.second), ss.first, (int32_t)tt.size,
                          (int32_t)ss.size});
         nbytes += c.size * ss.size;
       }
@@ -1037,21 +1090,21 @@ struct Builder {
     {
       std::vector<MfRow> mf;
       mf.reserve(nrows.size());
-      for (const NearRow& r : nrows) mf.push_back({Yp + r.row0, (int32_t)n, r.nr, r.seg_begin, r.seg_end});
+      for (const NearRow& r : nrows) mf.push_back({at(Yp, r.row0), (int32_t)n, r.nr, r.seg_begin, r.seg_end});
       h.near_mf_rows_d = h.upload(mf);
     }
-    h.near_matvec_bytes = nbytes * (int64_t)sizeof(C64);
+    h.near_matvec_bytes = nbytes * es;
     // leaf output: Y_t += Q_tc y_tc (after the near field)
     group = 5;
     begin_phase();
     for (int64_t t = 0; t < (int64_t)p.cl.size(); ++t) {
       const Cluster& c = p.cl[t];
       if (!c.leaf()) continue;
-      MvOut o{Yp + c.first, (int32_t)c.size, (int32_t)n, (int32_t)terms.size(), 0, 1, 0};
+      MvOut o{at(Yp, c.first), (int32_t)c.size, (int32_t)n, (int32_t)terms.size(), 0, 1, 0};
       for (const auto& pr : p.cl_slots[t]) {
         const int64_t q = pr.second;
         if (h.rank_row[q] > 0)
-          terms.push_back({h.Qr_ptr[q], yh + yo[q], h.rank_row[q], (int32_t)c.size, h.rank_row[q], 0});
+          terms.push_back({Qr(q), at(yh, yo[q]), h.rank_row[q], (int32_t)c.size, h.rank_row[q], 0});
       }
       o.term_end = (int32_t)terms.size();
       if (o.term_end > o.term_begin) outs.push_back(o);
@@ -1153,9 +1206,14 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
       off += t.size * s.size;
     }
     h.stats.near_entries = off;
-    h.near_d = h.alloc<C64>((size_t)std::max<int64_t>(off, 1));
     NearDesc* ndd = h.upload(nd);
-    launch_near<double>(ndd, (int64_t)nd.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+    if (h.precision == DH2_FP32) {
+      h.near_d = h.alloc<z32>((size_t)std::max<int64_t>(off, 1));
+      launch_near<float>(ndd, (int64_t)nd.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+    } else {
+      h.near_d = h.alloc<C64>((size_t)std::max<int64_t>(off, 1));
+      launch_near<double>(ndd, (int64_t)nd.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+    }
     h.check_launch();
     h.sync();
     h.release(ndd);
@@ -1211,6 +1269,7 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   h.release(selfl);
   h.release(Vd);
   h.release(Td);
+  if (h.precision == DH2_FP32) bd.narrow_to_fp32();
   bd.matvec_schedule();
   h.sync();
   h.stats.ms_total = now_ms() - t_start;
@@ -1299,10 +1358,6 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     g_err = "unknown precision";
     return DH2_ERR_ARG;
   }
-  if (opt.precision == DH2_FP32) {
-    g_err = "FP32 form is not available in this build";
-    return DH2_ERR_ARG;
-  }
   const double eta1 = opt.eta1 > 0 ? opt.eta1 : 10.0;
   const int max_nrhs = opt.max_nrhs > 0 ? opt.max_nrhs : 16;
   const double wsgb = opt.workspace_gb > 0 ? opt.workspace_gb : 8.0;
@@ -1350,11 +1405,13 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
   return DH2_OK;
 }
 
+extern "C++" {
 namespace {
 // Runs the matvec phases on the handle's stream; with ev != NULL records
 // ev[g] before group g (0 gather, 1 forward, 2 coupling, 3 backward, 4 near,
 // 5 leaf output, 6 scatter) and ev[7] at the end.
-void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
+template <typename R>
+void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
   const int64_t n = h->plan.n;
   auto mark = [&](int g) {
     if (ev) HIPCHK(hipEventRecord(ev[g], h->stream));
@@ -1362,40 +1419,46 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
   auto terms = [&](int g) {
     for (const auto& ph : h->mv_phases)
       if (ph.group == g && ph.out_end > ph.out_begin)
-        launch_mv_terms<double>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
+        launch_mv_terms<R>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
                                 nrhs, h->stream);
   };
   // four or more right-hand sides: matrix-core block rows on row-major copies
   const bool mf = nrhs >= 4;
   mark(0);
-  launch_mv_permute<double>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
-  if (mf) launch_mv_transpose<double>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
+  launch_mv_permute<R>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
+  if (mf) launch_mv_transpose<R>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
   mark(1);
   terms(1);
-  if (mf) launch_mv_slot_transpose<double>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
+  if (mf) launch_mv_slot_transpose<R>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
   mark(2);
   if (mf)
-    launch_mv_rows_mfma<double>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d,
+    launch_mv_rows_mfma<R>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d,
                                 nrhs, 1, h->stream);
   else
-    launch_mv_coupling<double>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
+    launch_mv_coupling<R>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
   mark(3);
   terms(3);
   mark(4);
   if (mf)
-    launch_mv_rows_mfma<double>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d,
+    launch_mv_rows_mfma<R>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d,
                                 nrhs, 0, h->stream);
   else
-    launch_mv_near<double>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
+    launch_mv_near<R>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
                            h->stream, h->XT_d);
   mark(5);
   terms(5);
   mark(6);
-  launch_mv_permute<double>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, h->stream);
+  launch_mv_permute<R>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, h->stream);
   mark(7);
   HIPCHK(hipGetLastError());
 }
+
+void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
+  if (h->precision == DH2_FP32) run_matvec_t<float>(h, X, Y, nrhs, ev);
+  else run_matvec_t<double>(h, X, Y, nrhs, ev);
+}
 }  // namespace
+}  // extern "C++"
 
 dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs) {
   if (!h || !X || !Y) {
@@ -1473,7 +1536,22 @@ dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64
         if (index < 0 || index >= (int64_t)p.near.size()) throw Fail{DH2_ERR_ARG, "index out of range"};
         r = p.cl[p.near[index].t].size;
         c = p.cl[p.near[index].s].size;
-        src = (const z64*)h->near_d + h->near_off[index];
+        if (h->precision == DH2_FP32) {
+          // complex64 storage, widened on the host
+          if (out && r * c > 0) {
+            HIPCHK(hipStreamSynchronize(h->stream));
+            std::vector<z32> tmp((size_t)(r * c));
+            HIPCHK(hipMemcpy(tmp.data(), (const z32*)h->near_d + h->near_off[index], tmp.size() * sizeof(z32),
+                             hipMemcpyDeviceToHost));
+            host.resize(2 * tmp.size());
+            for (size_t i = 0; i < tmp.size(); ++i) {
+              host[2 * i] = tmp[i].x;
+              host[2 * i + 1] = tmp[i].y;
+            }
+          }
+        } else {
+          src = (const z64*)h->near_d + h->near_off[index];
+        }
         break;
       }
       case DH2_INSPECT_LEAF_BASIS: {

@@ -747,6 +747,13 @@ __global__ void k_narrow(const z64* __restrict__ a, z32* __restrict__ b, int64_t
   if (i < n) b[i] = z32{(float)a[i].x, (float)a[i].y};
 }
 
+__global__ void __launch_bounds__(256) k_narrow_list(const NarrowDesc* __restrict__ d) {
+  const NarrowDesc t = d[blockIdx.x];
+  const z64* a = (const z64*)t.src;
+  z32* b = (z32*)t.dst;
+  for (int64_t i = threadIdx.x; i < t.n; i += blockDim.x) b[i] = z32{(float)a[i].x, (float)a[i].y};
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 void launch_tri_data(int64_t n, const double* V, const int32_t* T, const int64_t* perm,
@@ -864,6 +871,13 @@ void launch_narrow(const void* a, void* b, int64_t n, hipStream_t st) {
   if (n > 0)
     hipLaunchKernelGGL(k_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        (const z64*)a, (z32*)b, n);
+}
+
+void launch_narrow_list(const NarrowDesc* d, int64_t nd, hipStream_t st) {
+  for (int64_t o = 0; o < nd; o += (1 << 30)) {
+    const int64_t cnt = nd - o < (1 << 30) ? nd - o : (1 << 30);
+    hipLaunchKernelGGL(k_narrow_list, dim3((unsigned)cnt), dim3(256), 0, st, d + o);
+  }
 }
 
 }  // namespace dh2

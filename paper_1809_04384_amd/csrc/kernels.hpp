@@ -118,5 +118,12 @@ void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st);
 template <typename R>
 void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st);
 void launch_narrow(const void* a, void* b, int64_t n, hipStream_t st);
+// complex128 -> complex64 of many small arrays: dst[i] = src[i], i < n
+struct NarrowDesc {
+  const void* src;
+  void* dst;
+  int64_t n;
+};
+void launch_narrow_list(const NarrowDesc* d, int64_t nd, hipStream_t st);
 
 }  // namespace dh2
