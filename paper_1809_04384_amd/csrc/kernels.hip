@@ -3,6 +3,8 @@
 // interleaved (re, im); matrices are column-major unless stated.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -329,6 +331,59 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
 constexpr int kFoldNB = 8;
 constexpr int kFoldThreads = 512;
 
+// Cross-lane sums without the LDS crossbar: DPP row operations (quad swaps,
+// half-row and row mirrors) give every lane the sum of its aligned group of
+// 4, 8 or 16 lanes; the four row sums of a wave are then read with readlane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// sum over aligned groups of G lanes (G = 4, 8, 16); every lane of a group gets it
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_mov<0xB1>(v);                 // lanes i ^ 1
+  v += dpp_mov<0x4E>(v);                 // lanes i ^ 2
+  if (G >= 8) v += dpp_mov<0x141>(v);    // half-row mirror
+  if (G >= 16) v += dpp_mov<0x140>(v);   // row mirror
+  return v;
+}
+// sum over the whole wave (all lanes active), the same value in every lane
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group_sum<16>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_mov<0xB1>(v));
+  v = fmax(v, dpp_mov<0x4E>(v));
+  v = fmax(v, dpp_mov<0x141>(v));
+  v = fmax(v, dpp_mov<0x140>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+
+// Global-memory accesses through address space 1: the task pointers are
+// generic, and generic (flat) accesses would make every LDS access wait for
+// them.
+template <typename T>
+__device__ __forceinline__ cpx<T> gld(const cpx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return cpx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gst(cpx<T>* p, cpx<T> x) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  *(__attribute__((address_space(1))) v2*)p = v2{x.x, x.y};
+}
+
 template <typename PT>
 __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restrict__ tasks,
                                                        const FoldPiece* __restrict__ pieces, int ch) {
@@ -340,18 +395,14 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
   z64* Rp = P + (size_t)ch * n;                 // [NB][n]: rows j0.. of R during a panel
   __shared__ z64 s_tauc[kFoldNB];               // conj(tau) per panel column (0 if skipped)
   __shared__ z64 s_T[kFoldNB][kFoldNB];         // block reflector factor
-  __shared__ z64 s_G[kFoldNB][kFoldNB];         // Y^H Y
   __shared__ double s_wmax[kFoldThreads / 64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   constexpr int nwaves = kFoldThreads / 64;
-  // trailing-update layout: lane = 4 * column + row group
-  const int q = lane & 3;                       // row group
-  const int cw = wave * 16 + (lane >> 2);       // column slot within a block of 128
   if (tk.init_zero)
     for (int e = tid; e < n * n; e += kFoldThreads) {
       const int i = e % n, j = e / n;
-      R[i + (int64_t)j * tk.ldr] = z64{0, 0};
+      gst(R + i + (int64_t)j * tk.ldr, z64{0, 0});
     }
   __syncthreads();
   for (int pc = tk.piece_begin; pc < tk.piece_end; ++pc) {
@@ -360,13 +411,26 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
     for (int r0 = 0; r0 < pp.rows; r0 += ch) {
       const int p = min(ch, pp.rows - r0);
       double lmax = 0.0;
-      for (int e = tid; e < p * n; e += kFoldThreads) {
-        const int i = e % p, j = e / p;
-        const cpx<PT> v = src[(r0 + i) + (int64_t)j * pp.ld];
-        P[i * n + j] = z64{(double)v.x, (double)v.y};
-        lmax = fmax(lmax, fmax(fabs((double)v.x), fabs((double)v.y)));
+      // four loads in flight per thread before their LDS stores
+      for (int e0 = tid; e0 < p * n; e0 += 4 * kFoldThreads) {
+        cpx<PT> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * kFoldThreads;
+          const int i = e % p, j = e / p;
+          if (e < p * n) v[u] = gld(src + (r0 + i) + (int64_t)j * pp.ld);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * kFoldThreads;
+          const int i = e % p, j = e / p;
+          if (e < p * n) {
+            P[i * n + j] = z64{(double)v[u].x, (double)v[u].y};
+            lmax = fmax(lmax, fmax(fabs((double)v[u].x), fabs((double)v[u].y)));
+          }
+        }
       }
-      for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+      lmax = wave_max(lmax);
       if (lane == 0) s_wmax[wave] = lmax;
       __syncthreads();
       double cmax = 0.0;
@@ -377,153 +441,192 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
         const int pe = j0 + nb;                 // end of the panel
         for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
           const int a = e % nb, jj = j0 + e / nb;
-          Rp[a * n + jj] = R[j0 + a + (int64_t)jj * tk.ldr];
+          Rp[a * n + jj] = gld(R + j0 + a + (int64_t)jj * tk.ldr);
         }
         __syncthreads();
-        // ---- panel: reflectors column by column, updates inside the panel
-        for (int jl = 0; jl < nb; ++jl) {
-          const int j = j0 + jl;
-          if (wave == 0) {
-            double mx = 0.0;
-            for (int i = lane; i < p; i += 64) {
-              const z64 v = P[i * n + j];
-              mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-            }
-            for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-            if (mx <= skip_below) {
-              for (int i = lane; i < p; i += 64) P[i * n + j] = z64{0, 0};
-              if (lane == 0) s_tauc[jl] = z64{0, 0};
-            } else {
-              const z64 a = Rp[jl * n + j];
-              const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
-              const double inv = 1.0 / scale;
-              double part = 0.0;
-              for (int i = lane; i < p; i += 64) {
-                const z64 v = P[i * n + j];
-                part += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
-              }
-              for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-              const z64 as{a.x * inv, a.y * inv};
-              const double aas = sqrt(abs2(as));
-              const double sig_s = sqrt(aas * aas + part);
-              const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
-              const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
-              const z64 d_s = as - beta_s;
-              const double dd = 1.0 / abs2(d_s);
-              const z64 dinv{d_s.x * dd, -d_s.y * dd};
-              for (int i = lane; i < p; i += 64) {
-                const z64 v = P[i * n + j];
-                P[i * n + j] = z64{v.x * inv, v.y * inv} * dinv;
-              }
-              if (lane == 0) {
+        // ---- panel, by wave 0 alone: lane i holds row i of the chunk (p <= 64)
+        // for the panel columns.  A reflector changes only its own pivot row of
+        // R, so every panel entry of R is read once before its single update.
+        // Reductions are wave butterflies; independent ones run together (the
+        // column maximum with its sum of squares, all dot products of a
+        // reflector with the later panel columns, all of Y^H Y for T), so the
+        // panel costs a few butterfly chains per column and no workgroup
+        // barrier.  The same wave forms the block reflector factor T (lane a
+        // holds row a of T).
+        if (wave == 0) {
+          const bool rowok = lane < p;
+          z64 y[kFoldNB], tcs[kFoldNB];
+#pragma unroll
+          for (int a = 0; a < kFoldNB; ++a) {
+            y[a] = (rowok && a < nb) ? P[lane * n + j0 + a] : z64{0, 0};
+            tcs[a] = z64{0, 0};
+          }
+#pragma unroll
+          for (int jl = 0; jl < kFoldNB; ++jl) {
+            if (jl < nb) {
+              const int j = j0 + jl;
+              const double mx = wave_max(fmax(fabs(y[jl].x), fabs(y[jl].y)));
+              const double sq = wave_sum(y[jl].x * y[jl].x + y[jl].y * y[jl].y);
+              if (mx <= skip_below) {
+                y[jl] = z64{0, 0};
+              } else {
+                const z64 a = Rp[jl * n + j];
+                const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
+                const double inv = 1.0 / scale;
+                double part;
+                if (mx > 1e-140 && mx < 1e140) {
+                  part = sq * inv * inv;          // no under- or overflow in the squares
+                } else {
+                  part = wave_sum((y[jl].x * inv) * (y[jl].x * inv) + (y[jl].y * inv) * (y[jl].y * inv));
+                }
+                const z64 as{a.x * inv, a.y * inv};
+                const double aas = sqrt(abs2(as));
+                const double sig_s = sqrt(aas * aas + part);
+                const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
+                const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
+                const z64 d_s = as - beta_s;
+                const double dd = 1.0 / abs2(d_s);
+                const z64 dinv{d_s.x * dd, -d_s.y * dd};
+                y[jl] = z64{y[jl].x * inv, y[jl].y * inv} * dinv;
                 const double bb = 1.0 / abs2(beta_s);
                 const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
-                s_tauc[jl] = conj(tau);
-                Rp[jl * n + j] = z64{beta_s.x * scale, beta_s.y * scale};
+                const z64 tc = conj(tau);
+                tcs[jl] = tc;
+                if (lane == 0) Rp[jl * n + j] = z64{beta_s.x * scale, beta_s.y * scale};
+                // remaining panel columns: all dot products in one butterfly
+                z64 w[kFoldNB];
+#pragma unroll
+                for (int jc = 0; jc < kFoldNB; ++jc) {
+                  w[jc] = z64{0, 0};
+                  if (jc > jl) cfmac(w[jc], y[jl], y[jc]);
+                }
+#pragma unroll
+                for (int jc = 0; jc < kFoldNB; ++jc) {
+                  if (jc > jl) {
+                    w[jc].x = wave_sum(w[jc].x);
+                    w[jc].y = wave_sum(w[jc].y);
+                  }
+                }
+#pragma unroll
+                for (int jc = 0; jc < kFoldNB; ++jc) {
+                  if (jc > jl && jc < nb) {
+                    const z64 rj = Rp[jl * n + j0 + jc];
+                    const z64 tw = tc * (rj + w[jc]);
+                    y[jc] = y[jc] - y[jl] * tw;
+                    if (lane == 0) Rp[jl * n + j0 + jc] = rj - tw;
+                  }
+                }
               }
             }
           }
-          __syncthreads();
-          // remaining panel columns: one wave per column, lanes over rows
-          const z64 tc = s_tauc[jl];
-          if (tc.x != 0.0 || tc.y != 0.0) {
-            for (int jj = j + 1 + wave; jj < pe; jj += nwaves) {
-              z64 w{0, 0};
-              for (int i = lane; i < p; i += 64) cfmac(w, P[i * n + j], P[i * n + jj]);
-              for (int off = 32; off > 0; off >>= 1) {
-                w.x += __shfl_xor(w.x, off);
-                w.y += __shfl_xor(w.y, off);
-              }
-              z64* rj = &Rp[jl * n + jj];
-              const z64 tw = tc * (*rj + w);
-              for (int i = lane; i < p; i += 64) P[i * n + jj] = P[i * n + jj] - P[i * n + j] * tw;
-              __builtin_amdgcn_wave_barrier();
-              if (lane == 0) *rj = *rj - tw;
-            }
-          }
-          __syncthreads();
-        }
-        if (pe < n) {
-        // ---- T: T[a][a] = tau_a, T[0:a][a] = -tau_a T[0:a][0:a] (Y[:,0:a]^H Y[:,a])
-        for (int e = tid; e < nb * nb; e += kFoldThreads) {
-          const int a = e % nb, b = e / nb;
-          z64 g{0, 0};
-          if (a < b)
-            for (int i = 0; i < p; ++i) cfmac(g, P[i * n + j0 + a], P[i * n + j0 + b]);
-          s_G[a][b] = g;
-        }
-        __syncthreads();
-        if (tid == 0) {
-          for (int b = 0; b < nb; ++b) {
-            const z64 tau = conj(s_tauc[b]);
-            for (int a = 0; a < b; ++a) {
-              z64 acc{0, 0};
-              for (int c = a; c < b; ++c) cfma(acc, s_T[a][c], s_G[c][b]);
-              s_T[a][b] = z64{0, 0} - tau * acc;
-            }
-            s_T[b][b] = tau;
-            for (int a = b + 1; a < nb; ++a) s_T[a][b] = z64{0, 0};
-          }
-        }
-        __syncthreads();
-        // ---- trailing columns, 128 at a time: lane = 4 * column + row group.
-        // Every value of a column lives in its four lanes, so no barrier is needed:
-        // W = R[panel rows, jj] + Y^H P[:, jj], W <- T^H W,
-        // R[panel rows, jj] -= W, P[:, jj] -= Y W.
-        for (int jb = pe; jb < n; jb += 128) {
-          const int jj = jb + cw;
-          const bool colok = jj < n;
-          z64 w[kFoldNB];
-#pragma unroll
-          for (int a = 0; a < kFoldNB; ++a) w[a] = z64{0, 0};
-          if (colok)
-            for (int i = q; i < p; i += 4) {
-              const z64 pv = P[i * n + jj];
-#pragma unroll
-              for (int a = 0; a < kFoldNB; ++a)
-                if (a < nb) cfmac(w[a], P[i * n + j0 + a], pv);
-            }
-#pragma unroll
-          for (int a = 0; a < kFoldNB; ++a) {
-            w[a].x += __shfl_xor(w[a].x, 1);
-            w[a].y += __shfl_xor(w[a].y, 1);
-            w[a].x += __shfl_xor(w[a].x, 2);
-            w[a].y += __shfl_xor(w[a].y, 2);
-          }
-          if (!colok) continue;
 #pragma unroll
           for (int a = 0; a < kFoldNB; ++a)
-            if (a < nb) w[a] = w[a] + Rp[a * n + jj];
-          z64 w2[kFoldNB];
+            if (rowok && a < nb) P[lane * n + j0 + a] = y[a];
 #pragma unroll
-          for (int a = 0; a < kFoldNB; ++a) {
-            z64 acc{0, 0};
+          for (int a = 0; a < kFoldNB; ++a)
+            if (lane == a) s_tauc[a] = tcs[a];
+          if (pe < n) {
+            // G[c][b] = y_c^H y_b (c < b), all in one butterfly
+            z64 g[kFoldNB * (kFoldNB - 1) / 2];
 #pragma unroll
-            for (int b = 0; b <= a; ++b) cfmac(acc, s_T[b][a], w[b]);
-            w2[a] = a < nb ? acc : z64{0, 0};
-          }
-          if (q == 0) {
+            for (int b = 1, e = 0; b < kFoldNB; ++b)
 #pragma unroll
-            for (int a = 0; a < kFoldNB; ++a)
-              if (a < nb) {
-                z64* r = &Rp[a * n + jj];
-                *r = *r - w2[a];
+              for (int c = 0; c < b; ++c, ++e) {
+                g[e] = z64{0, 0};
+                cfmac(g[e], y[c], y[b]);
               }
-          }
-          for (int i = q; i < p; i += 4) {
-            z64 acc = P[i * n + jj];
 #pragma unroll
-            for (int a = 0; a < kFoldNB; ++a)
-              if (a < nb) acc = acc - P[i * n + j0 + a] * w2[a];
-            P[i * n + jj] = acc;
+            for (int e = 0; e < kFoldNB * (kFoldNB - 1) / 2; ++e) {
+              g[e].x = wave_sum(g[e].x);
+              g[e].y = wave_sum(g[e].y);
+            }
+            // T[b][b] = tau_b, T[a][b] = -tau_b sum_{c<b} T[a][c] G[c][b]
+            z64 trow[kFoldNB];
+#pragma unroll
+            for (int b = 0; b < kFoldNB; ++b) trow[b] = z64{0, 0};
+#pragma unroll
+            for (int b = 0, e0 = 0; b < kFoldNB; e0 += b, ++b) {
+              if (b < nb) {
+                const z64 tau = conj(tcs[b]);
+                z64 acc{0, 0};
+#pragma unroll
+                for (int c = 0; c < b; ++c) cfma(acc, trow[c], g[e0 + c]);
+                trow[b] = lane == b ? tau : (lane < b ? z64{0, 0} - tau * acc : z64{0, 0});
+              }
+            }
+            if (lane < kFoldNB)
+#pragma unroll
+              for (int b = 0; b < kFoldNB; ++b) s_T[lane][b] = trow[b];
           }
         }
+        __syncthreads();
+        if (pe < n) {
+        // ---- trailing columns: G lanes per column (G = 4, 8 or 16, more
+        // lanes per column when fewer columns remain), 512 / G columns per
+        // pass.  Every value of a column lives in its G lanes, so no barrier
+        // is needed: W = R[panel rows, jj] + Y^H P[:, jj], W <- T^H W,
+        // R[panel rows, jj] -= W, P[:, jj] -= Y W.
+        auto trailing = [&](auto gc) {
+          constexpr int G = decltype(gc)::value;
+          const int qg = lane % G;                          // row group
+          const int cwg = wave * (64 / G) + lane / G;       // column slot
+          for (int jb = pe; jb < n; jb += kFoldThreads / G) {
+            const int jj = jb + cwg;
+            const bool colok = jj < n;
+            z64 w[kFoldNB];
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a) w[a] = z64{0, 0};
+            if (colok)
+              for (int i = qg; i < p; i += G) {
+                const z64 pv = P[i * n + jj];
+#pragma unroll
+                for (int a = 0; a < kFoldNB; ++a)
+                  if (a < nb) cfmac(w[a], P[i * n + j0 + a], pv);
+              }
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a) {
+              w[a].x = group_sum<G>(w[a].x);
+              w[a].y = group_sum<G>(w[a].y);
+            }
+            if (!colok) continue;
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a)
+              if (a < nb) w[a] = w[a] + Rp[a * n + jj];
+            z64 w2[kFoldNB];
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a) {
+              z64 acc{0, 0};
+#pragma unroll
+              for (int b = 0; b <= a; ++b) cfmac(acc, s_T[b][a], w[b]);
+              w2[a] = a < nb ? acc : z64{0, 0};
+            }
+            if (qg == 0) {
+#pragma unroll
+              for (int a = 0; a < kFoldNB; ++a)
+                if (a < nb) {
+                  z64* r = &Rp[a * n + jj];
+                  *r = *r - w2[a];
+                }
+            }
+            for (int i = qg; i < p; i += G) {
+              z64 acc = P[i * n + jj];
+#pragma unroll
+              for (int a = 0; a < kFoldNB; ++a)
+                if (a < nb) acc = acc - P[i * n + j0 + a] * w2[a];
+              P[i * n + jj] = acc;
+            }
+          }
+        };
+        const int nt = n - pe;
+        if (nt > kFoldThreads / 8) trailing(std::integral_constant<int, 4>{});
+        else if (nt > kFoldThreads / 16) trailing(std::integral_constant<int, 8>{});
+        else trailing(std::integral_constant<int, 16>{});
         __syncthreads();
         }
         // panel rows of R back to global memory
         for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
           const int a = e % nb, jj = j0 + e / nb;
-          R[j0 + a + (int64_t)jj * tk.ldr] = Rp[a * n + jj];
+          gst(R + j0 + a + (int64_t)jj * tk.ldr, Rp[a * n + jj]);
         }
         __syncthreads();
       }
@@ -539,7 +642,7 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
     if (tid == 0) {
       int c = 0;
       for (int j = 0; j < n; ++j) {
-        const z64 dg = R[j + (int64_t)j * tk.ldr];
+        const z64 dg = gld(R + j + (int64_t)j * tk.ldr);
         if (dg.x != 0.0 || dg.y != 0.0) s_rows[c++] = j;
       }
       s_cnt = c;
@@ -550,9 +653,9 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
     for (int jj = tid; jj < n; jj += kFoldThreads) {
       for (int r = 0; r < c; ++r) {
         const int i = s_rows[r];
-        if (i != r) R[r + (int64_t)jj * tk.ldr] = R[i + (int64_t)jj * tk.ldr];
+        if (i != r) gst(R + r + (int64_t)jj * tk.ldr, gld(R + i + (int64_t)jj * tk.ldr));
       }
-      for (int r = c; r < n; ++r) R[r + (int64_t)jj * tk.ldr] = z64{0, 0};
+      for (int r = c; r < n; ++r) gst(R + r + (int64_t)jj * tk.ldr, z64{0, 0});
     }
   }
 }
@@ -829,6 +932,8 @@ void set_lds_limit(size_t bytes) {
   g_lds_limit = bytes > 24576 ? bytes - 12288 : 12288;
 }
 
+// The panel factorization keeps one chunk row per lane of a wave, so a chunk
+// has at most 64 rows.
 int fold_rows_per_chunk(int n) {
   int ch = (int)(g_lds_limit / ((size_t)n * 16)) - kFoldNB;
   if (ch > 64) ch = 64;
