@@ -394,7 +394,6 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
   z64* P = (z64*)lds_raw;                       // [ch][n]
   z64* Rp = P + (size_t)ch * n;                 // [NB][n]: rows j0.. of R during a panel
   __shared__ z64 s_tauc[kFoldNB];               // conj(tau) per panel column (0 if skipped)
-  __shared__ z64 s_T[kFoldNB][kFoldNB];         // block reflector factor
   __shared__ double s_wmax[kFoldThreads / 64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -525,103 +524,58 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
 #pragma unroll
           for (int a = 0; a < kFoldNB; ++a)
             if (lane == a) s_tauc[a] = tcs[a];
-          if (pe < n) {
-            // G[c][b] = y_c^H y_b (c < b), all in one butterfly
-            z64 g[kFoldNB * (kFoldNB - 1) / 2];
-#pragma unroll
-            for (int b = 1, e = 0; b < kFoldNB; ++b)
-#pragma unroll
-              for (int c = 0; c < b; ++c, ++e) {
-                g[e] = z64{0, 0};
-                cfmac(g[e], y[c], y[b]);
-              }
-#pragma unroll
-            for (int e = 0; e < kFoldNB * (kFoldNB - 1) / 2; ++e) {
-              g[e].x = wave_sum(g[e].x);
-              g[e].y = wave_sum(g[e].y);
-            }
-            // T[b][b] = tau_b, T[a][b] = -tau_b sum_{c<b} T[a][c] G[c][b]
-            z64 trow[kFoldNB];
-#pragma unroll
-            for (int b = 0; b < kFoldNB; ++b) trow[b] = z64{0, 0};
-#pragma unroll
-            for (int b = 0, e0 = 0; b < kFoldNB; e0 += b, ++b) {
-              if (b < nb) {
-                const z64 tau = conj(tcs[b]);
-                z64 acc{0, 0};
-#pragma unroll
-                for (int c = 0; c < b; ++c) cfma(acc, trow[c], g[e0 + c]);
-                trow[b] = lane == b ? tau : (lane < b ? z64{0, 0} - tau * acc : z64{0, 0});
-              }
-            }
-            if (lane < kFoldNB)
-#pragma unroll
-              for (int b = 0; b < kFoldNB; ++b) s_T[lane][b] = trow[b];
-          }
         }
         __syncthreads();
         if (pe < n) {
-        // ---- trailing columns: G lanes per column (G = 4, 8 or 16, more
-        // lanes per column when fewer columns remain), 512 / G columns per
-        // pass.  Every value of a column lives in its G lanes, so no barrier
-        // is needed: W = R[panel rows, jj] + Y^H P[:, jj], W <- T^H W,
-        // R[panel rows, jj] -= W, P[:, jj] -= Y W.
-        auto trailing = [&](auto gc) {
-          constexpr int G = decltype(gc)::value;
-          const int qg = lane % G;                          // row group
-          const int cwg = wave * (64 / G) + lane / G;       // column slot
-          for (int jb = pe; jb < n; jb += kFoldThreads / G) {
-            const int jj = jb + cwg;
-            const bool colok = jj < n;
-            z64 w[kFoldNB];
+        // ---- trailing columns: the panel reflectors are applied one after
+        // another (w = R[a, jj] + y_a^H P[:, jj], R[a, jj] -= conj(tau_a) w,
+        // P[:, jj] -= y_a conj(tau_a) w).  16 lanes per column, lane q holds
+        // rows q, q + 16, q + 32, q + 48 (p <= 64) of the column and of every
+        // reflector in registers, so LDS is read once per panel; the sums
+        // over the 16 lanes of a column are DPP row reductions.
+          const int qg = lane & 15;
+          const int cs = wave * 4 + (lane >> 4);
+          z64 yv[4][kFoldNB], tcv[kFoldNB];
 #pragma unroll
-            for (int a = 0; a < kFoldNB; ++a) w[a] = z64{0, 0};
-            if (colok)
-              for (int i = qg; i < p; i += G) {
-                const z64 pv = P[i * n + jj];
+          for (int a = 0; a < kFoldNB; ++a) {
+            tcv[a] = a < nb ? s_tauc[a] : z64{0, 0};
 #pragma unroll
-                for (int a = 0; a < kFoldNB; ++a)
-                  if (a < nb) cfmac(w[a], P[i * n + j0 + a], pv);
-              }
-#pragma unroll
-            for (int a = 0; a < kFoldNB; ++a) {
-              w[a].x = group_sum<G>(w[a].x);
-              w[a].y = group_sum<G>(w[a].y);
-            }
-            if (!colok) continue;
-#pragma unroll
-            for (int a = 0; a < kFoldNB; ++a)
-              if (a < nb) w[a] = w[a] + Rp[a * n + jj];
-            z64 w2[kFoldNB];
-#pragma unroll
-            for (int a = 0; a < kFoldNB; ++a) {
-              z64 acc{0, 0};
-#pragma unroll
-              for (int b = 0; b <= a; ++b) cfmac(acc, s_T[b][a], w[b]);
-              w2[a] = a < nb ? acc : z64{0, 0};
-            }
-            if (qg == 0) {
-#pragma unroll
-              for (int a = 0; a < kFoldNB; ++a)
-                if (a < nb) {
-                  z64* r = &Rp[a * n + jj];
-                  *r = *r - w2[a];
-                }
-            }
-            for (int i = qg; i < p; i += G) {
-              z64 acc = P[i * n + jj];
-#pragma unroll
-              for (int a = 0; a < kFoldNB; ++a)
-                if (a < nb) acc = acc - P[i * n + j0 + a] * w2[a];
-              P[i * n + jj] = acc;
+            for (int r = 0; r < 4; ++r) {
+              const int i = qg + 16 * r;
+              yv[r][a] = (i < p && a < nb) ? P[i * n + j0 + a] : z64{0, 0};
             }
           }
-        };
-        const int nt = n - pe;
-        if (nt > kFoldThreads / 8) trailing(std::integral_constant<int, 4>{});
-        else if (nt > kFoldThreads / 16) trailing(std::integral_constant<int, 8>{});
-        else trailing(std::integral_constant<int, 16>{});
-        __syncthreads();
+          for (int jb = pe; jb < n; jb += 4 * nwaves) {
+            const int jj = jb + cs;
+            const bool colok = jj < n;
+            z64 pv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = qg + 16 * r;
+              pv[r] = (colok && i < p) ? P[i * n + jj] : z64{0, 0};
+            }
+#pragma unroll
+            for (int a = 0; a < kFoldNB; ++a) {
+              if (a < nb) {
+                z64 w{0, 0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cfmac(w, yv[r][a], pv[r]);
+                w.x = group_sum<16>(w.x);
+                w.y = group_sum<16>(w.y);
+                const z64 rj = colok ? Rp[a * n + jj] : z64{0, 0};
+                const z64 tw = tcv[a] * (rj + w);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) pv[r] = pv[r] - yv[r][a] * tw;
+                if (colok && qg == 0) Rp[a * n + jj] = rj - tw;
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = qg + 16 * r;
+              if (colok && i < p) P[i * n + jj] = pv[r];
+            }
+          }
+          __syncthreads();
         }
         // panel rows of R back to global memory
         for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
