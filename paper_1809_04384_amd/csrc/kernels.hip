@@ -243,8 +243,39 @@ __global__ void __launch_bounds__(256) k_coupling(const CoupDesc* __restrict__ d
 // Batched complex GEMM, C = alpha op(A) op(B) (+ C if accumulate), op in
 // {N, T, C (conjugate transpose)}.  32 x 32 output tile per workgroup of 256
 // threads (2 x 2 outputs each), K staged through LDS in slices of 16.
+// Matrix-core tile products: a 16x16x4 MFMA multiplies A (16 x 4) by
+// B (4 x 16); lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+typedef double gm_f64x4 __attribute__((ext_vector_type(4)));
+typedef float gm_f32x4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct GMfma;
+template <>
+struct GMfma<double> {
+  typedef gm_f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int e) { return 4 * e + (l >> 4); }
+};
+template <>
+struct GMfma<float> {
+  typedef gm_f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
+};
+
+// Batched complex GEMM C = alpha op(A) op(B) (+ C), the products of the
+// recompression (Section 3.2: weighted couplings R S^*, transfers, basis
+// changes and projections).  A workgroup computes a 32 x 32 tile: 16-deep
+// slices of op(A) and op(B) are staged in LDS (transposition and conjugation
+// happen there), and each wave multiplies a 16 x 16 sub-tile on the matrix
+// cores, four real products per complex product:
+//   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
 template <typename R>
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, int ntm) {
+  typedef typename GMfma<R>::acc_t acc_t;
   const GemmDesc d = dd[blockIdx.y];
   const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
   const int m0 = tm * 32, n0 = tn * 32;
@@ -254,10 +285,12 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
   cpx<R>* C = (cpx<R>*)d.C;
   __shared__ cpx<R> As[16][33];
   __shared__ cpx<R> Bs[16][33];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  cpx<R> acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = cpx<R>{0, 0};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sm = (wave & 1) * 16, sn = (wave >> 1) * 16;   // sub-tile of this wave
+  const int li = lane & 15, lk = lane >> 4;
+  acc_t cre, cim;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) cre[e] = cim[e] = R(0);
   for (int k0 = 0; k0 < d.K; k0 += 16) {
     for (int e = threadIdx.x; e < 512; e += 256) {
       // A slice: rows m0..m0+31 of op(A), columns k0..k0+15
@@ -286,27 +319,27 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
       Bs[kb][j] = w;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      const cpx<R> a0 = As[kk][tx], a1 = As[kk][tx + 16];
-      const cpx<R> b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
-      cfma(acc[0][0], a0, b0);
-      cfma(acc[0][1], a0, b1);
-      cfma(acc[1][0], a1, b0);
-      cfma(acc[1][1], a1, b1);
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const cpx<R> a = As[ks + lk][sm + li];
+      const cpx<R> b = Bs[ks + lk][sn + li];
+      cre = GMfma<R>::mac(a.x, b.x, cre);
+      cre = GMfma<R>::mac(-a.y, b.y, cre);
+      cim = GMfma<R>::mac(a.x, b.y, cim);
+      cim = GMfma<R>::mac(a.y, b.x, cim);
     }
     __syncthreads();
   }
   const cpx<R> al{(R)d.alpha_re, (R)d.alpha_im};
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int gi = m0 + tx + 16 * a, gj = n0 + ty + 16 * b;
-      if (gi < d.M && gj < d.N) {
-        const cpx<R> v = al * acc[a][b];
-        cpx<R>& dst = C[gi + (int64_t)gj * d.ldc];
-        dst = d.accumulate ? dst + v : v;
-      }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int gi = m0 + sm + GMfma<R>::row(lane, e), gj = n0 + sn + li;
+    if (gi < d.M && gj < d.N) {
+      const cpx<R> v = al * cpx<R>{cre[e], cim[e]};
+      cpx<R>& dst = C[gi + (int64_t)gj * d.ldc];
+      dst = d.accumulate ? dst + v : v;
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +361,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
 // C <- C - V T^H (V^H C) with all threads.  Rows of the current piece are
 // staged in LDS (row-major, CH rows), followed by the NB rows of R of the
 // current panel, so the serial column steps never wait on global memory.
-constexpr int kFoldNB = 8;
+constexpr int kFoldNB = 4;
 constexpr int kFoldThreads = 512;
 
 // Cross-lane sums without the LDS crossbar: DPP row operations (quad swaps,
