@@ -291,10 +291,18 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
   acc_t cre, cim;
 #pragma unroll
   for (int e = 0; e < 4; ++e) cre[e] = cim[e] = R(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
-    for (int e = threadIdx.x; e < 512; e += 256) {
-      // A slice: rows m0..m0+31 of op(A), columns k0..k0+15
-      const int i = e % 32, kk = e / 32;
+  // Slice loads: consecutive threads read consecutive memory for every op
+  // (for op = N the fast index is the row of the stored matrix, otherwise the
+  // column); the next slice is loaded into registers while the current one
+  // is multiplied.
+  cpx<R> va[2], vb[2];
+  auto load_slice = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      int i, kk;
+      if (d.opA == 0) { i = e % 32; kk = e / 32; }
+      else { kk = e % 16; i = e / 16; }
       const int gi = m0 + i, gk = k0 + kk;
       cpx<R> v{0, 0};
       if (gi < d.M && gk < d.K) {
@@ -304,9 +312,10 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
           if (d.opA == 2) v = conj(v);
         }
       }
-      As[kk][i] = v;
-      // B slice: rows k0..k0+15 of op(B), columns n0..n0+31
-      const int kb = e % 16, j = e / 16;
+      va[h] = v;
+      int kb, j;
+      if (d.opB == 0) { kb = e % 16; j = e / 16; }
+      else { j = e % 32; kb = e / 32; }
       const int gkb = k0 + kb, gj = n0 + j;
       cpx<R> w{0, 0};
       if (gkb < d.K && gj < d.N) {
@@ -316,9 +325,24 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
           if (d.opB == 2) w = conj(w);
         }
       }
-      Bs[kb][j] = w;
+      vb[h] = w;
     }
+  };
+  auto store_slice = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      if (d.opA == 0) As[e / 32][e % 32] = va[h];
+      else As[e % 16][e / 16] = va[h];
+      if (d.opB == 0) Bs[e % 16][e / 16] = vb[h];
+      else Bs[e / 32][e % 32] = vb[h];
+    }
+  };
+  load_slice(0);
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    store_slice();
     __syncthreads();
+    if (k0 + 16 < d.K) load_slice(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       const cpx<R> a = As[ks + lk][sm + li];
@@ -425,8 +449,8 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
   const int n = tk.n;
   z64* R = (z64*)tk.R;
   z64* P = (z64*)lds_raw;                       // [ch][n]
-  z64* Rp = P + (size_t)ch * n;                 // [NB][n]: rows j0.. of R during a panel
-  __shared__ z64 s_tauc[kFoldNB];               // conj(tau) per panel column (0 if skipped)
+  z64* Rp = P + (size_t)ch * n;                 // [3][NB][n]: rows of R of three panels
+  __shared__ z64 s_tauc[2][kFoldNB];            // conj(tau) per panel column (0 if skipped)
   __shared__ double s_wmax[kFoldThreads / 64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -437,6 +461,135 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
       gst(R + i + (int64_t)j * tk.ldr, z64{0, 0});
     }
   __syncthreads();
+  // ---- panel factorization, by wave 0 alone: lane i holds row i of the
+  // chunk (p <= 64) for the panel columns j0 .. j0 + nb - 1.  A reflector
+  // changes only its own pivot row of R (Rb, the panel's rows), so every panel
+  // entry of R is read once before its single update.  Reductions are DPP
+  // wave sums; the dot products of a reflector with the later panel columns
+  // run together.  Writes the reflectors into P and conj(tau) into tc_out.
+  auto factor_panel = [&](z64* Rb, z64* tc_out, int j0, int nb, int p, double skip_below) {
+    const bool rowok = lane < p;
+    z64 y[kFoldNB], tcs[kFoldNB];
+#pragma unroll
+    for (int a = 0; a < kFoldNB; ++a) {
+      y[a] = (rowok && a < nb) ? P[lane * n + j0 + a] : z64{0, 0};
+      tcs[a] = z64{0, 0};
+    }
+#pragma unroll
+    for (int jl = 0; jl < kFoldNB; ++jl) {
+      if (jl < nb) {
+        const int j = j0 + jl;
+        const double mx = wave_max(fmax(fabs(y[jl].x), fabs(y[jl].y)));
+        const double sq = wave_sum(y[jl].x * y[jl].x + y[jl].y * y[jl].y);
+        if (mx <= skip_below) {
+          y[jl] = z64{0, 0};
+        } else {
+          const z64 a = Rb[jl * n + j];
+          const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
+          const double inv = 1.0 / scale;
+          double part;
+          if (mx > 1e-140 && mx < 1e140) {
+            part = sq * inv * inv;          // no under- or overflow in the squares
+          } else {
+            part = wave_sum((y[jl].x * inv) * (y[jl].x * inv) + (y[jl].y * inv) * (y[jl].y * inv));
+          }
+          const z64 as{a.x * inv, a.y * inv};
+          const double aas = sqrt(abs2(as));
+          const double sig_s = sqrt(aas * aas + part);
+          const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
+          const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
+          const z64 d_s = as - beta_s;
+          const double dd = 1.0 / abs2(d_s);
+          const z64 dinv{d_s.x * dd, -d_s.y * dd};
+          y[jl] = z64{y[jl].x * inv, y[jl].y * inv} * dinv;
+          const double bb = 1.0 / abs2(beta_s);
+          const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
+          const z64 tc = conj(tau);
+          tcs[jl] = tc;
+          if (lane == 0) Rb[jl * n + j] = z64{beta_s.x * scale, beta_s.y * scale};
+          z64 w[kFoldNB];
+#pragma unroll
+          for (int jc = 0; jc < kFoldNB; ++jc) {
+            w[jc] = z64{0, 0};
+            if (jc > jl) cfmac(w[jc], y[jl], y[jc]);
+          }
+#pragma unroll
+          for (int jc = 0; jc < kFoldNB; ++jc) {
+            if (jc > jl) {
+              w[jc].x = wave_sum(w[jc].x);
+              w[jc].y = wave_sum(w[jc].y);
+            }
+          }
+#pragma unroll
+          for (int jc = 0; jc < kFoldNB; ++jc) {
+            if (jc > jl && jc < nb) {
+              const z64 rj = Rb[jl * n + j0 + jc];
+              const z64 tw = tc * (rj + w[jc]);
+              y[jc] = y[jc] - y[jl] * tw;
+              if (lane == 0) Rb[jl * n + j0 + jc] = rj - tw;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kFoldNB; ++a)
+      if (rowok && a < nb) P[lane * n + j0 + a] = y[a];
+#pragma unroll
+    for (int a = 0; a < kFoldNB; ++a)
+      if (lane == a) tc_out[a] = tcs[a];
+  };
+  // ---- apply the reflectors of panel j0 .. j0 + nb - 1 (in P, conj(tau) in
+  // tc_in, R rows in Rb) one after another to columns [cb, ce):
+  //   w = R[a, jj] + y_a^H P[:, jj],  R[a, jj] -= conj(tau_a) w,  P[:, jj] -= y_a conj(tau_a) w.
+  // 16 lanes per column (slot), lane q holds rows q, q + 16, q + 32, q + 48
+  // (p <= 64) of the column and of every reflector in registers; the sums over
+  // the 16 lanes of a column are DPP row reductions.  Every lane of the wave
+  // takes part (the reductions need the whole row).
+  auto apply_panel = [&](z64* Rb, const z64* tc_in, int j0, int nb, int cb, int ce, int slot, int nslots,
+                         int p) {
+    const int qg = lane & 15;
+    z64 yv[4][kFoldNB], tcv[kFoldNB];
+#pragma unroll
+    for (int a = 0; a < kFoldNB; ++a) {
+      tcv[a] = a < nb ? tc_in[a] : z64{0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = qg + 16 * r;
+        yv[r][a] = (i < p && a < nb) ? P[i * n + j0 + a] : z64{0, 0};
+      }
+    }
+    for (int jb = cb; jb < ce; jb += nslots) {
+      const int jj = jb + slot;
+      const bool colok = jj < ce;
+      z64 pv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = qg + 16 * r;
+        pv[r] = (colok && i < p) ? P[i * n + jj] : z64{0, 0};
+      }
+#pragma unroll
+      for (int a = 0; a < kFoldNB; ++a) {
+        if (a < nb) {
+          z64 w{0, 0};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cfmac(w, yv[r][a], pv[r]);
+          w.x = group_sum<16>(w.x);
+          w.y = group_sum<16>(w.y);
+          const z64 rj = colok ? Rb[a * n + jj] : z64{0, 0};
+          const z64 tw = tcv[a] * (rj + w);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pv[r] = pv[r] - yv[r][a] * tw;
+          if (colok && qg == 0) Rb[a * n + jj] = rj - tw;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = qg + 16 * r;
+        if (colok && i < p) P[i * n + jj] = pv[r];
+      }
+    }
+  };
   for (int pc = tk.piece_begin; pc < tk.piece_end; ++pc) {
     const FoldPiece pp = pieces[pc];
     const cpx<PT>* src = (const cpx<PT>*)pp.P;
@@ -468,155 +621,46 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
       double cmax = 0.0;
       for (int w = 0; w < nwaves; ++w) cmax = fmax(cmax, s_wmax[w]);
       const double skip_below = 1e-14 * cmax;
-      for (int j0 = 0; j0 < n; j0 += kFoldNB) {
-        const int nb = min(kFoldNB, n - j0);
-        const int pe = j0 + nb;                 // end of the panel
-        for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
-          const int a = e % nb, jj = j0 + e / nb;
-          Rp[a * n + jj] = gld(R + j0 + a + (int64_t)jj * tk.ldr);
-        }
-        __syncthreads();
-        // ---- panel, by wave 0 alone: lane i holds row i of the chunk (p <= 64)
-        // for the panel columns.  A reflector changes only its own pivot row of
-        // R, so every panel entry of R is read once before its single update.
-        // Reductions are wave butterflies; independent ones run together (the
-        // column maximum with its sum of squares, all dot products of a
-        // reflector with the later panel columns, all of Y^H Y for T), so the
-        // panel costs a few butterfly chains per column and no workgroup
-        // barrier.  The same wave forms the block reflector factor T (lane a
-        // holds row a of T).
-        if (wave == 0) {
-          const bool rowok = lane < p;
-          z64 y[kFoldNB], tcs[kFoldNB];
-#pragma unroll
-          for (int a = 0; a < kFoldNB; ++a) {
-            y[a] = (rowok && a < nb) ? P[lane * n + j0 + a] : z64{0, 0};
-            tcs[a] = z64{0, 0};
-          }
-#pragma unroll
-          for (int jl = 0; jl < kFoldNB; ++jl) {
-            if (jl < nb) {
-              const int j = j0 + jl;
-              const double mx = wave_max(fmax(fabs(y[jl].x), fabs(y[jl].y)));
-              const double sq = wave_sum(y[jl].x * y[jl].x + y[jl].y * y[jl].y);
-              if (mx <= skip_below) {
-                y[jl] = z64{0, 0};
-              } else {
-                const z64 a = Rp[jl * n + j];
-                const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
-                const double inv = 1.0 / scale;
-                double part;
-                if (mx > 1e-140 && mx < 1e140) {
-                  part = sq * inv * inv;          // no under- or overflow in the squares
-                } else {
-                  part = wave_sum((y[jl].x * inv) * (y[jl].x * inv) + (y[jl].y * inv) * (y[jl].y * inv));
-                }
-                const z64 as{a.x * inv, a.y * inv};
-                const double aas = sqrt(abs2(as));
-                const double sig_s = sqrt(aas * aas + part);
-                const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
-                const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
-                const z64 d_s = as - beta_s;
-                const double dd = 1.0 / abs2(d_s);
-                const z64 dinv{d_s.x * dd, -d_s.y * dd};
-                y[jl] = z64{y[jl].x * inv, y[jl].y * inv} * dinv;
-                const double bb = 1.0 / abs2(beta_s);
-                const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
-                const z64 tc = conj(tau);
-                tcs[jl] = tc;
-                if (lane == 0) Rp[jl * n + j] = z64{beta_s.x * scale, beta_s.y * scale};
-                // remaining panel columns: all dot products in one butterfly
-                z64 w[kFoldNB];
-#pragma unroll
-                for (int jc = 0; jc < kFoldNB; ++jc) {
-                  w[jc] = z64{0, 0};
-                  if (jc > jl) cfmac(w[jc], y[jl], y[jc]);
-                }
-#pragma unroll
-                for (int jc = 0; jc < kFoldNB; ++jc) {
-                  if (jc > jl) {
-                    w[jc].x = wave_sum(w[jc].x);
-                    w[jc].y = wave_sum(w[jc].y);
-                  }
-                }
-#pragma unroll
-                for (int jc = 0; jc < kFoldNB; ++jc) {
-                  if (jc > jl && jc < nb) {
-                    const z64 rj = Rp[jl * n + j0 + jc];
-                    const z64 tw = tc * (rj + w[jc]);
-                    y[jc] = y[jc] - y[jl] * tw;
-                    if (lane == 0) Rp[jl * n + j0 + jc] = rj - tw;
-                  }
-                }
-              }
-            }
-          }
-#pragma unroll
-          for (int a = 0; a < kFoldNB; ++a)
-            if (rowok && a < nb) P[lane * n + j0 + a] = y[a];
-#pragma unroll
-          for (int a = 0; a < kFoldNB; ++a)
-            if (lane == a) s_tauc[a] = tcs[a];
-        }
-        __syncthreads();
-        if (pe < n) {
-        // ---- trailing columns: the panel reflectors are applied one after
-        // another (w = R[a, jj] + y_a^H P[:, jj], R[a, jj] -= conj(tau_a) w,
-        // P[:, jj] -= y_a conj(tau_a) w).  16 lanes per column, lane q holds
-        // rows q, q + 16, q + 32, q + 48 (p <= 64) of the column and of every
-        // reflector in registers, so LDS is read once per panel; the sums
-        // over the 16 lanes of a column are DPP row reductions.
-          const int qg = lane & 15;
-          const int cs = wave * 4 + (lane >> 4);
-          z64 yv[4][kFoldNB], tcv[kFoldNB];
-#pragma unroll
-          for (int a = 0; a < kFoldNB; ++a) {
-            tcv[a] = a < nb ? s_tauc[a] : z64{0, 0};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = qg + 16 * r;
-              yv[r][a] = (i < p && a < nb) ? P[i * n + j0 + a] : z64{0, 0};
-            }
-          }
-          for (int jb = pe; jb < n; jb += 4 * nwaves) {
-            const int jj = jb + cs;
-            const bool colok = jj < n;
-            z64 pv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = qg + 16 * r;
-              pv[r] = (colok && i < p) ? P[i * n + jj] : z64{0, 0};
-            }
-#pragma unroll
-            for (int a = 0; a < kFoldNB; ++a) {
-              if (a < nb) {
-                z64 w{0, 0};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) cfmac(w, yv[r][a], pv[r]);
-                w.x = group_sum<16>(w.x);
-                w.y = group_sum<16>(w.y);
-                const z64 rj = colok ? Rp[a * n + jj] : z64{0, 0};
-                const z64 tw = tcv[a] * (rj + w);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) pv[r] = pv[r] - yv[r][a] * tw;
-                if (colok && qg == 0) Rp[a * n + jj] = rj - tw;
-              }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = qg + 16 * r;
-              if (colok && i < p) P[i * n + jj] = pv[r];
-            }
-          }
-          __syncthreads();
-        }
-        // panel rows of R back to global memory
-        for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
-          const int a = e % nb, jj = j0 + e / nb;
-          gst(R + j0 + a + (int64_t)jj * tk.ldr, Rp[a * n + jj]);
-        }
-        __syncthreads();
+      // Panels of kFoldNB columns with one panel of look-ahead: while waves
+      // 1..7 apply panel q to the columns after panel q + 1, wave 0 applies
+      // it to the columns of panel q + 1 and factors that panel.  Panel q
+      // keeps its rows of R in Rp buffer q % 3 and its conj(tau) in s_tauc
+      // buffer q % 2, so one barrier per panel suffices.
+      const int nb0 = min(kFoldNB, n);
+      for (int e = tid; e < nb0 * n; e += kFoldThreads) {
+        const int a = e % nb0, jj = e / nb0;
+        Rp[a * n + jj] = gld(R + a + (int64_t)jj * tk.ldr);
       }
+      __syncthreads();
+      if (wave == 0) factor_panel(Rp, s_tauc[0], 0, nb0, p, skip_below);
+      __syncthreads();
+      for (int q = 0, j0 = 0; j0 < n; ++q, j0 += kFoldNB) {
+        const int nb = min(kFoldNB, n - j0);
+        const int pe = j0 + nb;                 // end of panel q
+        const int nb2 = min(kFoldNB, n - pe);
+        const int pe2 = pe + nb2;               // end of panel q + 1
+        z64* Rq = Rp + (size_t)(q % 3) * kFoldNB * n;
+        z64* Rn = Rp + (size_t)((q + 1) % 3) * kFoldNB * n;
+        if (wave == 0) {
+          if (nb2 > 0) {
+            for (int e = lane; e < nb2 * (n - pe); e += 64) {
+              const int a = e % nb2, jj = pe + e / nb2;
+              Rn[a * n + jj] = gld(R + pe + a + (int64_t)jj * tk.ldr);
+            }
+            apply_panel(Rq, s_tauc[q % 2], j0, nb, pe, pe2, lane >> 4, 4, p);
+            factor_panel(Rn, s_tauc[(q + 1) % 2], pe, nb2, p, skip_below);
+          }
+        } else if (pe2 < n) {
+          apply_panel(Rq, s_tauc[q % 2], j0, nb, pe2, n, (wave - 1) * 4 + (lane >> 4), 4 * (nwaves - 1), p);
+        }
+        __syncthreads();
+        // rows of panel q of R back to global memory
+        for (int e = tid; e < nb * (n - j0); e += kFoldThreads) {
+          const int a = e % nb, jj = j0 + e / nb;
+          gst(R + j0 + a + (int64_t)jj * tk.ldr, Rq[a * n + jj]);
+        }
+      }
+      __syncthreads();
     }
   }
   if (tk.compact) {
@@ -913,8 +957,10 @@ template void launch_gemm<double>(const GemmDesc*, int64_t, int, int, hipStream_
 template void launch_gemm<float>(const GemmDesc*, int64_t, int, int, hipStream_t);
 
 static size_t g_lds_limit = 65536;   // per-workgroup LDS bytes usable for dynamic buffers
+static size_t g_lds_total = 65536;   // per-workgroup LDS bytes of the device
 
 void set_lds_limit(size_t bytes) {
+  g_lds_total = bytes;
   // keep 12 KB for the kernels' static shared variables
   g_lds_limit = bytes > 24576 ? bytes - 12288 : 12288;
 }
@@ -922,7 +968,8 @@ void set_lds_limit(size_t bytes) {
 // The panel factorization keeps one chunk row per lane of a wave, so a chunk
 // has at most 64 rows.
 int fold_rows_per_chunk(int n) {
-  int ch = (int)(g_lds_limit / ((size_t)n * 16)) - kFoldNB;
+  // the fold's own static LDS is below 4 KB
+  int ch = (int)((g_lds_total - 4096) / ((size_t)n * 16)) - 3 * kFoldNB;
   if (ch > 64) ch = 64;
   if (ch < 1) ch = 1;
   return ch;
@@ -932,7 +979,7 @@ template <typename PT>
 void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, hipStream_t st) {
   if (ntasks <= 0) return;
   const int ch = fold_rows_per_chunk(n);
-  const size_t lds = (size_t)(ch + kFoldNB) * n * 16;
+  const size_t lds = (size_t)(ch + 3 * kFoldNB) * n * 16;
   hipLaunchKernelGGL(k_fold<PT>, dim3((unsigned)ntasks), dim3(kFoldThreads), lds, st, t, p, ch);
 }
 template void launch_fold<double>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
