@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
   const int n = tk.n;
   z64* R = (z64*)tk.R;
   z64* P = (z64*)lds_raw;                       // [ch][n]
-  z64* Rp = P + (size_t)ch * n;                 // [3][NB][n]: rows of R of three panels
+  z64* Rp = P + (size_t)ch * n;                 // [4][NB][n]: rows of R of four panels
   __shared__ z64 s_tauc[2][kFoldNB];            // conj(tau) per panel column (0 if skipped)
   __shared__ double s_wmax[kFoldThreads / 64];
   const int tid = threadIdx.x;
@@ -470,10 +470,15 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
   auto factor_panel = [&](z64* Rb, z64* tc_out, int j0, int nb, int p, double skip_below) {
     const bool rowok = lane < p;
     z64 y[kFoldNB], tcs[kFoldNB];
+    // the panel block of R (rows and columns j0 .. j0 + nb - 1), upper part,
+    // read once; reflector jl changes only row jl of it
+    z64 rb[kFoldNB][kFoldNB];
 #pragma unroll
     for (int a = 0; a < kFoldNB; ++a) {
       y[a] = (rowok && a < nb) ? P[lane * n + j0 + a] : z64{0, 0};
       tcs[a] = z64{0, 0};
+#pragma unroll
+      for (int c = 0; c < kFoldNB; ++c) rb[a][c] = (c >= a && c < nb) ? Rb[a * n + j0 + c] : z64{0, 0};
     }
 #pragma unroll
     for (int jl = 0; jl < kFoldNB; ++jl) {
@@ -484,29 +489,41 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
         if (mx <= skip_below) {
           y[jl] = z64{0, 0};
         } else {
-          const z64 a = Rb[jl * n + j];
-          const double scale = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
-          const double inv = 1.0 / scale;
+          // Scaled by an exact power of two 2^e >= max|x| (no rounding, no
+          // over- or underflow in the squares).  With q = |alpha|, S = |x|:
+          // beta = -alpha S / q, tau = 1 + q / S (real), and the reflector
+          // entries x_i / (alpha - beta) = x_i conj(alpha) / (q^2 + q S).
+          const z64 a = rb[jl][jl];
+          int ex;
+          (void)frexp(fmax(mx, fmax(fabs(a.x), fabs(a.y))), &ex);
+          const double inv = ldexp(1.0, -ex);
           double part;
           if (mx > 1e-140 && mx < 1e140) {
-            part = sq * inv * inv;          // no under- or overflow in the squares
+            part = sq * inv * inv;
           } else {
             part = wave_sum((y[jl].x * inv) * (y[jl].x * inv) + (y[jl].y * inv) * (y[jl].y * inv));
           }
           const z64 as{a.x * inv, a.y * inv};
-          const double aas = sqrt(abs2(as));
-          const double sig_s = sqrt(aas * aas + part);
-          const z64 ph = aas > 0.0 ? z64{as.x / aas, as.y / aas} : z64{1.0, 0.0};
-          const z64 beta_s{-ph.x * sig_s, -ph.y * sig_s};
-          const z64 d_s = as - beta_s;
-          const double dd = 1.0 / abs2(d_s);
-          const z64 dinv{d_s.x * dd, -d_s.y * dd};
+          const double a2 = abs2(as);
+          const double S = sqrt(a2 + part);
+          const double qa = sqrt(a2);
+          z64 beta_s, dinv;
+          double tau;
+          if (qa > 0.0) {
+            const double f = 1.0 / (a2 + qa * S);
+            dinv = z64{as.x * f, -as.y * f};
+            const double rr = S / qa;
+            beta_s = z64{-as.x * rr, -as.y * rr};
+            tau = 1.0 + qa / S;
+          } else {
+            dinv = z64{1.0 / S, 0.0};
+            beta_s = z64{-S, 0.0};
+            tau = 1.0;
+          }
           y[jl] = z64{y[jl].x * inv, y[jl].y * inv} * dinv;
-          const double bb = 1.0 / abs2(beta_s);
-          const z64 tau = z64{-d_s.x, -d_s.y} * z64{beta_s.x * bb, -beta_s.y * bb};
-          const z64 tc = conj(tau);
+          const z64 tc{tau, 0.0};
           tcs[jl] = tc;
-          if (lane == 0) Rb[jl * n + j] = z64{beta_s.x * scale, beta_s.y * scale};
+          rb[jl][jl] = z64{ldexp(beta_s.x, ex), ldexp(beta_s.y, ex)};
           z64 w[kFoldNB];
 #pragma unroll
           for (int jc = 0; jc < kFoldNB; ++jc) {
@@ -523,10 +540,10 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
 #pragma unroll
           for (int jc = 0; jc < kFoldNB; ++jc) {
             if (jc > jl && jc < nb) {
-              const z64 rj = Rb[jl * n + j0 + jc];
-              const z64 tw = tc * (rj + w[jc]);
+              const z64 sw = rb[jl][jc] + w[jc];
+              const z64 tw{tc.x * sw.x, tc.x * sw.y};
               y[jc] = y[jc] - y[jl] * tw;
-              if (lane == 0) Rb[jl * n + j0 + jc] = rj - tw;
+              rb[jl][jc] = rb[jl][jc] - tw;
             }
           }
         }
@@ -538,6 +555,12 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
 #pragma unroll
     for (int a = 0; a < kFoldNB; ++a)
       if (lane == a) tc_out[a] = tcs[a];
+    if (lane == 0)
+#pragma unroll
+      for (int a = 0; a < kFoldNB; ++a)
+#pragma unroll
+        for (int c = 0; c < kFoldNB; ++c)
+          if (c >= a && c < nb) Rb[a * n + j0 + c] = rb[a][c];
   };
   // ---- apply the reflectors of panel j0 .. j0 + nb - 1 (in P, conj(tau) in
   // tc_in, R rows in Rb) one after another to columns [cb, ce):
@@ -568,21 +591,35 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
         const int i = qg + 16 * r;
         pv[r] = (colok && i < p) ? P[i * n + jj] : z64{0, 0};
       }
+      // the R entries of this column (one per reflector) are read up front:
+      // reflector a changes only entry a
+      z64 rj[kFoldNB];
+#pragma unroll
+      for (int a = 0; a < kFoldNB; ++a) rj[a] = (colok && a < nb) ? Rb[a * n + jj] : z64{0, 0};
 #pragma unroll
       for (int a = 0; a < kFoldNB; ++a) {
         if (a < nb) {
-          z64 w{0, 0};
+          // conj(y) p over this lane's four rows as a tree (short dependency chain)
+          z64 t[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) cfmac(w, yv[r][a], pv[r]);
+          for (int r = 0; r < 4; ++r) {
+            t[r] = z64{0, 0};
+            cfmac(t[r], yv[r][a], pv[r]);
+          }
+          z64 w = (t[0] + t[1]) + (t[2] + t[3]);
           w.x = group_sum<16>(w.x);
           w.y = group_sum<16>(w.y);
-          const z64 rj = colok ? Rb[a * n + jj] : z64{0, 0};
-          const z64 tw = tcv[a] * (rj + w);
+          const z64 sw = rj[a] + w;
+          const z64 tw{tcv[a].x * sw.x - tcv[a].y * sw.y, tcv[a].x * sw.y + tcv[a].y * sw.x};
 #pragma unroll
           for (int r = 0; r < 4; ++r) pv[r] = pv[r] - yv[r][a] * tw;
-          if (colok && qg == 0) Rb[a * n + jj] = rj - tw;
+          rj[a] = rj[a] - tw;
         }
       }
+      if (colok && qg == 0)
+#pragma unroll
+        for (int a = 0; a < kFoldNB; ++a)
+          if (a < nb) Rb[a * n + jj] = rj[a];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = qg + 16 * r;
@@ -622,36 +659,64 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
       for (int w = 0; w < nwaves; ++w) cmax = fmax(cmax, s_wmax[w]);
       const double skip_below = 1e-14 * cmax;
       // Panels of kFoldNB columns with one panel of look-ahead: while waves
-      // 1..7 apply panel q to the columns after panel q + 1, wave 0 applies
-      // it to the columns of panel q + 1 and factors that panel.  Panel q
-      // keeps its rows of R in Rp buffer q % 3 and its conj(tau) in s_tauc
-      // buffer q % 2, so one barrier per panel suffices.
-      const int nb0 = min(kFoldNB, n);
-      for (int e = tid; e < nb0 * n; e += kFoldThreads) {
-        const int a = e % nb0, jj = e / nb0;
-        Rp[a * n + jj] = gld(R + a + (int64_t)jj * tk.ldr);
-      }
+      // 1..7 apply panel q to the columns after panel q + 1 (and fetch the R
+      // rows of panel q + 2), wave 0 applies panel q to the columns of panel
+      // q + 1 and factors that panel.  Panel q keeps its rows of R in Rp
+      // buffer q % 4 and its conj(tau) in s_tauc buffer q % 2, so one barrier
+      // per panel suffices.
+      auto load_rows = [&](int q0, int t0, int nthr) {   // R rows of panel q0 -> buffer q0 % 4
+        const int jb = q0 * kFoldNB;
+        const int nbq = min(kFoldNB, n - jb);
+        z64* Rb = Rp + (size_t)(q0 % 4) * kFoldNB * n;
+        for (int e = t0; e < nbq * (n - jb); e += nthr) {
+          const int a = e % nbq, jj = jb + e / nbq;
+          Rb[a * n + jj] = gld(R + jb + a + (int64_t)jj * tk.ldr);
+        }
+      };
+      load_rows(0, tid, kFoldThreads);
+      if (kFoldNB < n) load_rows(1, tid, kFoldThreads);
       __syncthreads();
-      if (wave == 0) factor_panel(Rp, s_tauc[0], 0, nb0, p, skip_below);
+      if (wave == 0) factor_panel(Rp, s_tauc[0], 0, min(kFoldNB, n), p, skip_below);
       __syncthreads();
       for (int q = 0, j0 = 0; j0 < n; ++q, j0 += kFoldNB) {
         const int nb = min(kFoldNB, n - j0);
         const int pe = j0 + nb;                 // end of panel q
         const int nb2 = min(kFoldNB, n - pe);
         const int pe2 = pe + nb2;               // end of panel q + 1
-        z64* Rq = Rp + (size_t)(q % 3) * kFoldNB * n;
-        z64* Rn = Rp + (size_t)((q + 1) % 3) * kFoldNB * n;
+        z64* Rq = Rp + (size_t)(q % 4) * kFoldNB * n;
+        z64* Rn = Rp + (size_t)((q + 1) % 4) * kFoldNB * n;
         if (wave == 0) {
           if (nb2 > 0) {
-            for (int e = lane; e < nb2 * (n - pe); e += 64) {
-              const int a = e % nb2, jj = pe + e / nb2;
-              Rn[a * n + jj] = gld(R + pe + a + (int64_t)jj * tk.ldr);
-            }
             apply_panel(Rq, s_tauc[q % 2], j0, nb, pe, pe2, lane >> 4, 4, p);
             factor_panel(Rn, s_tauc[(q + 1) % 2], pe, nb2, p, skip_below);
           }
-        } else if (pe2 < n) {
-          apply_panel(Rq, s_tauc[q % 2], j0, nb, pe2, n, (wave - 1) * 4 + (lane >> 4), 4 * (nwaves - 1), p);
+        } else {
+          // R rows of panel q + 2: loads issued before the update, stored after it
+          const int jb2 = pe2;
+          const int nb3 = min(kFoldNB, n - jb2);
+          constexpr int kPre = (kFoldNB * kMaxOrder * kMaxOrder * kMaxOrder + 64 * (nwaves - 1) - 1) /
+                               (64 * (nwaves - 1));
+          z64 pre[kPre];
+          const int t1 = tid - 64;
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const int e = t1 + u * 64 * (nwaves - 1);
+            if (nb3 > 0 && e < nb3 * (n - jb2)) {
+              const int a = e % nb3, jj = jb2 + e / nb3;
+              pre[u] = gld(R + jb2 + a + (int64_t)jj * tk.ldr);
+            }
+          }
+          if (pe2 < n)
+            apply_panel(Rq, s_tauc[q % 2], j0, nb, pe2, n, (wave - 1) * 4 + (lane >> 4), 4 * (nwaves - 1), p);
+          z64* R3 = Rp + (size_t)((q + 2) % 4) * kFoldNB * n;
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const int e = t1 + u * 64 * (nwaves - 1);
+            if (nb3 > 0 && e < nb3 * (n - jb2)) {
+              const int a = e % nb3, jj = jb2 + e / nb3;
+              R3[a * n + jj] = pre[u];
+            }
+          }
         }
         __syncthreads();
         // rows of panel q of R back to global memory
@@ -969,7 +1034,7 @@ void set_lds_limit(size_t bytes) {
 // has at most 64 rows.
 int fold_rows_per_chunk(int n) {
   // the fold's own static LDS is below 4 KB
-  int ch = (int)((g_lds_total - 4096) / ((size_t)n * 16)) - 3 * kFoldNB;
+  int ch = (int)((g_lds_total - 4096) / ((size_t)n * 16)) - 4 * kFoldNB;
   if (ch > 64) ch = 64;
   if (ch < 1) ch = 1;
   return ch;
@@ -979,7 +1044,7 @@ template <typename PT>
 void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, hipStream_t st) {
   if (ntasks <= 0) return;
   const int ch = fold_rows_per_chunk(n);
-  const size_t lds = (size_t)(ch + 3 * kFoldNB) * n * 16;
+  const size_t lds = (size_t)(ch + 4 * kFoldNB) * n * 16;
   hipLaunchKernelGGL(k_fold<PT>, dim3((unsigned)ntasks), dim3(kFoldThreads), lds, st, t, p, ch);
 }
 template void launch_fold<double>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
