@@ -1,0 +1,126 @@
+"""GPU checks at the full sizes of the sphere workloads (n = 32768, one
+right-hand side; n = 131072, 16 right-hand sides, the benchmark launch), where
+the whole oracle build does not finish in reasonable time.  What the oracle
+computes one by one is compared directly:
+  - the block structure (counts of admissible and inadmissible leaves);
+  - sampled near-field blocks, element by element (FP64: 1e-13 of the block's
+    largest entry);
+  - sampled rows of Y = G~ X against the same rows of the reference Galerkin
+    matrix G (Q7 x Q7 far, Q16 near, singular self term), within the
+    interpolation + recompression error (1e-2 relative, a consistency bound:
+    the tight FP64 parity is checked element by element at n <= 2048);
+and properties that hold at any size:
+  - linearity of the matvec (1e-12);
+  - the FP32 form within 1e-4 of the FP64 form over the full n x nrhs result.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import say, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _structure(w, V, T):
+    from oracle.structure import build_structure
+    return build_structure(V, T, w.kappa, w.eta, w.leaf, w.eta1)
+
+
+def _dense_rows(st, tri, rows, kappa, n):
+    """Rows of the reference Galerkin matrix, assembled block by block."""
+    from oracle import cquad
+    rows = [int(i) for i in rows]
+    where = {i: r for r, i in enumerate(rows)}
+    # position of each triangle in the cluster order; cluster t holds the
+    # positions [first[t], first[t] + size[t])
+    pos = np.empty(n, dtype=np.int64)
+    pos[st.perm] = np.arange(n)
+    member = {}
+    for t in range(len(st.first)):
+        lo, hi = int(st.first[t]), int(st.first[t] + st.size[t])
+        sel = [i for i in rows if lo <= pos[i] < hi]
+        if sel:
+            member[t] = sel
+    out = np.zeros((len(rows), n), dtype=np.complex128)
+    for (t, s, c) in st.adm:
+        sel = member.get(t)
+        if sel:
+            blk = cquad.far_block(tri, np.array(sel), st.idx(s), kappa)
+            for r, i in enumerate(sel):
+                out[where[i], st.idx(s)] = blk[r]
+    for (t, s) in st.near:
+        sel = member.get(t)
+        if sel:
+            blk = cquad.near_block(tri, np.array(sel), st.idx(s), kappa)
+            for r, i in enumerate(sel):
+                out[where[i], st.idx(s)] = blk[r]
+    return out
+
+
+def _matvec(h, X, dtype):
+    import torch
+    Xd = torch.from_numpy(np.ascontiguousarray(X.astype(dtype))).to("cuda:0")
+    Yd = torch.empty_like(Xd)
+    h.matvec(Xd, Yd)
+    torch.cuda.synchronize()
+    return Yd.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("name", ["sphere32k", "sphere131k"])
+def test_full_size(name):
+    from paper_1809_04384_amd import dh2
+    from oracle.quadrature import triangle_data
+    from oracle import cquad
+    w = synth.WORKLOADS[name]
+    V, T = synth.make_mesh(w)
+    n = len(T)
+    nrhs = w.nrhs
+    say("[gpu] full-size %s: n=%d nrhs=%d, oracle structure" % (name, n, nrhs))
+    st = _structure(w, V, T)
+    tri = triangle_data(V, T)
+    say("[gpu] dh2_build FP64 %s" % name)
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 2))
+    try:
+        s = h.stats()
+        assert s["n"] == n
+        assert s["n_adm"] == len(st.adm)
+        assert s["n_near"] == len(st.near)
+        # sampled near-field blocks, element by element
+        rng = np.random.default_rng(3)
+        for b in sorted(rng.choice(len(st.near), size=12, replace=False).tolist()):
+            t, sc = st.near[b]
+            ref = cquad.near_block(tri, st.idx(t), st.idx(sc), w.kappa)
+            N = h.inspect("near", b)
+            assert N.shape == ref.shape
+            assert np.max(np.abs(N - ref)) <= 1e-13 * np.max(np.abs(ref))
+        say("[gpu] %s near blocks ok" % name)
+        # matvec: sampled rows against the reference Galerkin matrix
+        X = synth.complex_gaussian(n, nrhs, seed=0)             # (nrhs, n)
+        Y = _matvec(h, X, np.complex128)
+        rows = sorted(np.random.default_rng(4).choice(n, size=4, replace=False).tolist())
+        G = _dense_rows(st, tri, rows, w.kappa, n)
+        Yref = G @ X.T                                           # (rows, nrhs)
+        err = rel(Y[:, rows].T, Yref)
+        say("[gpu] %s sampled rows vs Galerkin matrix: rel err %.3e" % (name, err))
+        assert err <= 1e-2
+        # linearity (two right-hand sides, or the first two of the batch)
+        X1 = synth.complex_gaussian(n, 2, seed=5)
+        Y1 = _matvec(h, X1, np.complex128)
+        Xc = np.stack([X1[0] + 2.0 * X1[1], X1[1]])
+        Yc = _matvec(h, Xc, np.complex128)
+        assert rel(Yc[0], Y1[0] + 2.0 * Y1[1]) <= 1e-12
+        say("[gpu] %s linearity ok" % name)
+    finally:
+        h.free()
+    if nrhs >= 4:
+        say("[gpu] dh2_build FP32 %s" % name)
+        h32 = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
+                         max_nrhs=nrhs)
+        try:
+            Y32 = _matvec(h32, X, np.complex64)
+            err32 = rel(Y32, Y)
+            say("[gpu] %s FP32 vs FP64: rel diff %.3e" % (name, err32))
+            assert err32 <= 1e-4
+        finally:
+            h32.free()
