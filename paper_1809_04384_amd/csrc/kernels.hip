@@ -627,29 +627,43 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
       }
     }
   };
-  for (int pc = tk.piece_begin; pc < tk.piece_end; ++pc) {
-    const FoldPiece pp = pieces[pc];
-    const cpx<PT>* src = (const cpx<PT>*)pp.P;
-    for (int r0 = 0; r0 < pp.rows; r0 += ch) {
-      const int p = min(ch, pp.rows - r0);
+  // Rows stream through LDS in chunks of up to ch rows, filled from as many
+  // consecutive pieces as fit (stacking order does not change the R factor).
+  int pc = tk.piece_begin, pr0 = 0;                      // next piece and its next row
+  while (pc < tk.piece_end && pieces[pc].rows <= 0) ++pc;
+  while (pc < tk.piece_end) {
+    {
+      int p = 0;
       double lmax = 0.0;
-      // four loads in flight per thread before their LDS stores
-      for (int e0 = tid; e0 < p * n; e0 += 4 * kFoldThreads) {
-        cpx<PT> v[4];
+      while (p < ch && pc < tk.piece_end) {
+        const FoldPiece pp = pieces[pc];
+        const cpx<PT>* src = (const cpx<PT>*)pp.P;
+        const int take = min(ch - p, pp.rows - pr0);
+        // four loads in flight per thread before their LDS stores
+        for (int e0 = tid; e0 < take * n; e0 += 4 * kFoldThreads) {
+          cpx<PT> v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = e0 + u * kFoldThreads;
-          const int i = e % p, j = e / p;
-          if (e < p * n) v[u] = gld(src + (r0 + i) + (int64_t)j * pp.ld);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = e0 + u * kFoldThreads;
-          const int i = e % p, j = e / p;
-          if (e < p * n) {
-            P[i * n + j] = z64{(double)v[u].x, (double)v[u].y};
-            lmax = fmax(lmax, fmax(fabs((double)v[u].x), fabs((double)v[u].y)));
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kFoldThreads;
+            const int i = e % take, j = e / take;
+            if (e < take * n) v[u] = gld(src + (pr0 + i) + (int64_t)j * pp.ld);
           }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kFoldThreads;
+            const int i = e % take, j = e / take;
+            if (e < take * n) {
+              P[(p + i) * n + j] = z64{(double)v[u].x, (double)v[u].y};
+              lmax = fmax(lmax, fmax(fabs((double)v[u].x), fabs((double)v[u].y)));
+            }
+          }
+        }
+        p += take;
+        pr0 += take;
+        if (pr0 >= pp.rows) {
+          ++pc;
+          pr0 = 0;
+          while (pc < tk.piece_end && pieces[pc].rows <= 0) ++pc;
         }
       }
       lmax = wave_max(lmax);
