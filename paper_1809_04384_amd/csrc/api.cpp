@@ -599,13 +599,23 @@ struct Builder {
         launch_gemm<double>(upload_tmp(gd, tmp), (int64_t)gd.size(), k, k, h.stream);
         h.check_launch();
         // TSQR split: fold segments of each item into temporaries when the
-        // batch has few slots, then fold the temporaries into Zhat
+        // batch has few slots, merge the temporaries in a tree of 8-way folds
+        // (in parallel), then fold the last ones into Zhat
         const int64_t want = 512;
         int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
-        G = std::min<int64_t>(G, std::max<int64_t>(1, maxT / (int64_t)items.size()));
-        std::vector<FoldTask> t1, t2;
+        G = std::min<int64_t>(G, std::max<int64_t>(1, (maxT * 4 / 5) / (int64_t)items.size()));
+        constexpr int64_t kMerge = 8;
+        std::vector<FoldTask> t1;
+        std::vector<std::vector<FoldTask>> tiers;       // merge levels
+        std::vector<FoldTask> t2;
         std::vector<FoldPiece> p2;
         int64_t tcount = 0;
+        auto new_temp = [&]() {
+          C64* Rt = Tbuf + (size_t)tcount * k * k;
+          ++tcount;
+          if (tcount > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the TSQR temporaries"};
+          return Rt;
+        };
         for (size_t ii = 0; ii < items.size(); ++ii) {
           const Item& it = items[ii];
           const int64_t q = qs[it.a];
@@ -619,16 +629,42 @@ struct Builder {
             fin.piece_end = (int32_t)pe;
             t2.push_back(fin);
           } else {
-            fin.piece_begin = (int32_t)(pieces.size() + p2.size());
-            for (int64_t s = 0; s < g; ++s) {
-              const size_t sb = pb + (size_t)(np * s / g), se = pb + (size_t)(np * (s + 1) / g);
-              C64* Rt = Tbuf + (size_t)tcount * k * k;
-              ++tcount;
+            // first level: g segments of the item's pieces, balanced by rows
+            std::vector<int64_t> rows_prefix(np + 1, 0);
+            for (int64_t e = 0; e < np; ++e) rows_prefix[e + 1] = rows_prefix[e] + pieces[pb + e].rows;
+            std::vector<C64*> cur;
+            size_t sb = pb;
+            for (int64_t sgi = 0; sgi < g; ++sgi) {
+              const int64_t target = rows_prefix[np] * (sgi + 1) / g;
+              size_t se = sb;
+              while (se < pe && (rows_prefix[se - pb] < target || se == sb)) ++se;
+              if (sgi == g - 1) se = pe;
+              if (se <= sb) continue;
+              C64* Rt = new_temp();
               t1.push_back(FoldTask{Rt, k, k, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
-              // all k rows: in floating point a compacted factor may keep more
-              // nonzero rows than the rows folded into it
-              p2.push_back({Rt, k, k});
+              cur.push_back(Rt);
+              sb = se;
             }
+            // merge levels: groups of kMerge temporaries (all k rows each: in
+            // floating point a compacted factor may keep more nonzero rows
+            // than the rows folded into it)
+            size_t lvl = 0;
+            while ((int64_t)cur.size() > kMerge) {
+              if (tiers.size() <= lvl) tiers.emplace_back();
+              std::vector<C64*> nxt;
+              for (size_t a0 = 0; a0 < cur.size(); a0 += kMerge) {
+                const size_t a1 = std::min(cur.size(), a0 + (size_t)kMerge);
+                C64* Rt = new_temp();
+                const int32_t b0 = (int32_t)(pieces.size() + p2.size());
+                for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], k, k});
+                tiers[lvl].push_back(FoldTask{Rt, k, k, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
+                nxt.push_back(Rt);
+              }
+              cur.swap(nxt);
+              ++lvl;
+            }
+            fin.piece_begin = (int32_t)(pieces.size() + p2.size());
+            for (C64* Rt : cur) p2.push_back({Rt, k, k});
             fin.piece_end = (int32_t)(pieces.size() + p2.size());
             t2.push_back(fin);
           }
@@ -637,6 +673,8 @@ struct Builder {
         pieces.insert(pieces.end(), p2.begin(), p2.end());
         FoldPiece* pd = upload_tmp(pieces, tmp);
         if (!t1.empty()) launch_fold<double>(upload_tmp(t1, tmp), (int64_t)t1.size(), pd, k, h.stream);
+        for (const auto& tier : tiers)
+          if (!tier.empty()) launch_fold<double>(upload_tmp(tier, tmp), (int64_t)tier.size(), pd, k, h.stream);
         launch_fold<double>(upload_tmp(t2, tmp), (int64_t)t2.size(), pd, k, h.stream);
         h.check_launch();
         free_tmp(tmp);
