@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -601,7 +602,7 @@ struct Builder {
         // TSQR split: fold segments of each item into temporaries when the
         // batch has few slots, merge the temporaries in a tree of 8-way folds
         // (in parallel), then fold the last ones into Zhat
-        const int64_t want = 512;
+        const int64_t want = 1024;
         int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
         G = std::min<int64_t>(G, std::max<int64_t>(1, (maxT * 4 / 5) / (int64_t)items.size()));
         constexpr int64_t kMerge = 8;
@@ -1244,17 +1245,47 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
       off += t.size * s.size;
     }
     h.stats.near_entries = off;
-    NearDesc* ndd = h.upload(nd);
-    if (h.precision == DH2_FP32) {
-      h.near_d = h.alloc<z32>((size_t)std::max<int64_t>(off, 1));
-      launch_near<float>(ndd, (int64_t)nd.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
-    } else {
-      h.near_d = h.alloc<C64>((size_t)std::max<int64_t>(off, 1));
-      launch_near<double>(ndd, (int64_t)nd.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+    // The Galerkin matrix is symmetric: of the pair (t, s), (s, t) only the
+    // block with t < s is evaluated, its mirror is its transpose.
+    std::map<std::pair<int64_t, int64_t>, int64_t> where;
+    for (size_t b = 0; b < p.near.size(); ++b) where[{p.near[b].t, p.near[b].s}] = (int64_t)b;
+    std::vector<NearDesc> eval;
+    std::vector<std::pair<int64_t, int64_t>> mirrors;      // (mirror block, evaluated block)
+    for (size_t b = 0; b < p.near.size(); ++b) {
+      const int64_t t = p.near[b].t, sc = p.near[b].s;
+      if (t > sc) {
+        auto it = where.find({sc, t});
+        if (it != where.end()) {
+          mirrors.push_back({(int64_t)b, it->second});
+          continue;
+        }
+      }
+      eval.push_back(nd[b]);
     }
+    const int es = h.precision == DH2_FP32 ? (int)sizeof(z32) : (int)sizeof(C64);
+    h.near_d = h.alloc<char>((size_t)std::max<int64_t>(off, 1) * es);
+    NearDesc* ndd = h.upload(eval);
+    if (h.precision == DH2_FP32)
+      launch_near<float>(ndd, (int64_t)eval.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+    else
+      launch_near<double>(ndd, (int64_t)eval.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
     h.check_launch();
+    std::vector<CopyDesc> cp;
+    cp.reserve(mirrors.size());
+    for (const auto& mb : mirrors) {
+      const NearDesc& a = nd[mb.second];                  // evaluated: a.nr x a.nc
+      cp.push_back({(char*)h.near_d + a.off * es, (char*)h.near_d + nd[mb.first].off * es, a.nr, a.nc,
+                    a.nr, a.nc});
+    }
+    CopyDesc* cpd = cp.empty() ? nullptr : h.upload(cp);
+    if (!cp.empty()) {
+      if (h.precision == DH2_FP32) launch_transpose_blocks<float>(cpd, (int64_t)cp.size(), h.stream);
+      else launch_transpose_blocks<double>(cpd, (int64_t)cp.size(), h.stream);
+      h.check_launch();
+    }
     h.sync();
     h.release(ndd);
+    if (cpd) h.release(cpd);
   }
   h.stats.ms_near = now_ms() - t0;
 

@@ -954,6 +954,32 @@ __global__ void k_copy(const CopyDesc* __restrict__ dd) {
   }
 }
 
+// Mirror near-field blocks: dst (N x M, leading dimension ldd) = src^T for
+// src (M x N, leading dimension lds).  The Galerkin matrix is symmetric, so
+// the inadmissible block (s, t) is the transpose of (t, s); 32 x 32 tiles go
+// through LDS so that reads and writes are both coalesced.
+template <typename R>
+__global__ void __launch_bounds__(256) k_transpose_blocks(const CopyDesc* __restrict__ dd) {
+  const CopyDesc d = dd[blockIdx.x];
+  const cpx<R>* src = (const cpx<R>*)d.src;
+  cpx<R>* dst = (cpx<R>*)d.dst;
+  __shared__ cpx<R> tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int i0 = 0; i0 < d.M; i0 += 32)
+    for (int j0 = 0; j0 < d.N; j0 += 32) {
+      for (int jj = ty; jj < 32; jj += 8) {
+        const int i = i0 + tx, j = j0 + jj;
+        if (i < d.M && j < d.N) tile[jj][tx] = src[i + (int64_t)j * d.lds];
+      }
+      __syncthreads();
+      for (int ii = ty; ii < 32; ii += 8) {
+        const int j = j0 + tx, i = i0 + ii;
+        if (i < d.M && j < d.N) dst[j + (int64_t)i * d.ldd] = tile[tx][ii];
+      }
+      __syncthreads();
+    }
+}
+
 // FP64 -> FP32 narrowing of a complex array (basis data of the FP32 form).
 __global__ void k_narrow(const z64* __restrict__ a, z32* __restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1084,6 +1110,16 @@ void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st) {
 }
 template void launch_copy<double>(const CopyDesc*, int64_t, hipStream_t);
 template void launch_copy<float>(const CopyDesc*, int64_t, hipStream_t);
+
+template <typename R>
+void launch_transpose_blocks(const CopyDesc* d, int64_t nb, hipStream_t st) {
+  for (int64_t o = 0; o < nb; o += (1 << 30)) {
+    const int64_t cnt = nb - o < (1 << 30) ? nb - o : (1 << 30);
+    hipLaunchKernelGGL(k_transpose_blocks<R>, dim3((unsigned)cnt), dim3(256), 0, st, d + o);
+  }
+}
+template void launch_transpose_blocks<double>(const CopyDesc*, int64_t, hipStream_t);
+template void launch_transpose_blocks<float>(const CopyDesc*, int64_t, hipStream_t);
 
 void launch_narrow(const void* a, void* b, int64_t n, hipStream_t st) {
   if (n > 0)

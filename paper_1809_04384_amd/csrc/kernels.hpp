@@ -117,6 +117,9 @@ template <typename R>
 void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st);
 template <typename R>
 void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st);
+// dst (N x M, leading dimension ldd) = transpose of src (M x N, leading dimension lds), per descriptor
+template <typename R>
+void launch_transpose_blocks(const CopyDesc* d, int64_t nb, hipStream_t st);
 void launch_narrow(const void* a, void* b, int64_t n, hipStream_t st);
 // complex128 -> complex64 of many small arrays: dst[i] = src[i], i < n
 struct NarrowDesc {
