@@ -218,24 +218,41 @@ __global__ void __launch_bounds__(256) k_coupling(const CoupDesc* __restrict__ d
   const double* bt = box + 6 * d.t;
   const double* bs = box + 6 * d.s;
   const double c[3] = {dirs[3 * d.dir], dirs[3 * d.dir + 1], dirs[3 * d.dir + 2]};
+  // interpolation points of t (rows) and s (columns): xi_nu = (x_{jx}, y_{jy}, z_{jz}),
+  // nu = jx + m (jy + m jz); the point tables are built once per block
   __shared__ double pt[3][kMaxOrder], ps[3][kMaxOrder];
+  __shared__ double qs[3][kMaxOrder * kMaxOrder * kMaxOrder];
   if (threadIdx.x < 3 * m) {
     const int a = threadIdx.x / m, j = threadIdx.x % m;
     pt[a][j] = axis_point(ct, bt[a], bt[a + 3], j);
     ps[a][j] = axis_point(ct, bs[a], bs[a + 3], j);
   }
   __syncthreads();
+  for (int mu = threadIdx.x; mu < k; mu += blockDim.x) {
+    qs[0][mu] = ps[0][mu % m];
+    qs[1][mu] = ps[1][(mu / m) % m];
+    qs[2][mu] = ps[2][mu / (m * m)];
+  }
+  __syncthreads();
   cpx<R>* o = out + (int64_t)blockIdx.x * k * k;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    const int nu = e % k, mu = e / k;
-    const double dx = pt[0][nu % m] - ps[0][mu % m];
-    const double dy = pt[1][(nu / m) % m] - ps[1][(mu / m) % m];
-    const double dz = pt[2][nu / (m * m)] - ps[2][mu / (m * m)];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    double sn, cs;
-    sincos(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
-    const double f = 0.25 / M_PI / r;
-    o[e] = cpx<R>{(R)(f * cs), (R)(f * sn)};
+  const double f0 = 0.25 / M_PI;
+  // thread = row nu (its point in registers), the column points are read from
+  // LDS (the same for every lane of an iteration); writes are coalesced
+  const int ng = blockDim.x / 128;
+  for (int nu0 = 0; nu0 < k; nu0 += 128) {
+    const int nu = nu0 + (threadIdx.x & 127);
+    if (nu >= k) continue;
+    const double xt = pt[0][nu % m], yt = pt[1][(nu / m) % m], zt = pt[2][nu / (m * m)];
+    for (int mu = threadIdx.x >> 7; mu < k; mu += ng) {
+      const double dx = xt - qs[0][mu];
+      const double dy = yt - qs[1][mu];
+      const double dz = zt - qs[2][mu];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double sn, cs;
+      sincos(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
+      const double f = f0 / r;
+      o[nu + (int64_t)mu * k] = cpx<R>{(R)(f * cs), (R)(f * sn)};
+    }
   }
 }
 
