@@ -283,6 +283,35 @@ struct Builder {
     tmp.push_back(d);
     return d;
   }
+  // Batched GEMMs launched with grids of exactly their tiles: descriptors are
+  // grouped by (row tiles, column tiles) of 32, one launch per group, so no
+  // workgroup is started for a tile outside its product.
+  void gemm(const std::vector<GemmDesc>& gd, std::vector<void*>& tmp) {
+    if (gd.empty()) return;
+    auto key = [](const GemmDesc& g) {
+      return std::min((g.M + 31) / 32, 16) * 17 + std::min((g.N + 31) / 32, 16);
+    };
+    std::vector<GemmDesc> v;
+    v.reserve(gd.size());
+    for (const GemmDesc& g : gd)
+      if (g.M > 0 && g.N > 0) v.push_back(g);
+    if (v.empty()) return;
+    std::stable_sort(v.begin(), v.end(), [&](const GemmDesc& a, const GemmDesc& b) { return key(a) < key(b); });
+    const GemmDesc* d = upload_tmp(v, tmp);
+    size_t i0 = 0;
+    while (i0 < v.size()) {
+      const int kk = key(v[i0]);
+      size_t i1 = i0;
+      int maxM = 0, maxN = 0;
+      while (i1 < v.size() && key(v[i1]) == kk) {
+        maxM = std::max(maxM, v[i1].M);
+        maxN = std::max(maxN, v[i1].N);
+        ++i1;
+      }
+      launch_gemm<double>(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
+      i0 = i1;
+    }
+  }
   void free_tmp(std::vector<void*>& tmp) {
     h.sync();
     for (void* x : tmp) h.release(x);
@@ -416,7 +445,7 @@ struct Builder {
           tasks.push_back(tk);
         }
         std::vector<void*> tmp;
-        if (!gd.empty()) launch_gemm<double>(upload_tmp(gd, tmp), (int64_t)gd.size(), k, k, h.stream);
+        gemm(gd, tmp);
         launch_fold<double>(upload_tmp(tasks, tmp), (int64_t)tasks.size(), upload_tmp(pieces, tmp), k,
                             h.stream);
         h.check_launch();
@@ -476,8 +505,8 @@ struct Builder {
         g2.push_back(g2d);
         fd.push_back({T2 + i * k * k, rt, rs, std::max(rt, 1), 0, b});
       }
-      launch_gemm<double>(upload_tmp(g1, tmp), (int64_t)g1.size(), k, k, h.stream);
-      launch_gemm<double>(upload_tmp(g2, tmp), (int64_t)g2.size(), k, k, h.stream);
+      gemm(g1, tmp);
+      gemm(g2, tmp);
       launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
       h.check_launch();
       free_tmp(tmp);
@@ -597,7 +626,7 @@ struct Builder {
           }
           item_pieces.push_back({pb, pieces.size()});
         }
-        launch_gemm<double>(upload_tmp(gd, tmp), (int64_t)gd.size(), k, k, h.stream);
+        gemm(gd, tmp);
         h.check_launch();
         // TSQR split: fold segments of each item into temporaries when the
         // batch has few slots, merge the temporaries in a tree of 8-way folds
@@ -803,8 +832,8 @@ struct Builder {
           sv.push_back(st);
         }
         if (maxm > 256) throw Fail{DH2_ERR_ARG, "truncation matrix with more than 256 rows"};
-        if (!g1.empty()) launch_gemm<double>(upload_tmp(g1, tmp), (int64_t)g1.size(), k, k, h.stream);
-        if (!g2.empty()) launch_gemm<double>(upload_tmp(g2, tmp), (int64_t)g2.size(), k, std::max(maxm, 1), h.stream);
+        gemm(g1, tmp);
+        gemm(g2, tmp);
         if (!ft.empty()) {
           // fold per m: n differs per task, LDS sized for the largest
           launch_fold<double>(upload_tmp(ft, tmp), (int64_t)ft.size(), upload_tmp(fp, tmp), maxm, h.stream);
@@ -856,7 +885,7 @@ struct Builder {
           }
         }
         if (!cp.empty()) launch_copy<double>(upload_tmp(cp, tmp), (int64_t)cp.size(), h.stream);
-        if (!g3.empty()) launch_gemm<double>(upload_tmp(g3, tmp), (int64_t)g3.size(), k, k, h.stream);
+        gemm(g3, tmp);
         h.check_launch();
         free_tmp(tmp);
         i0 = i1;
@@ -908,8 +937,8 @@ struct Builder {
         g2.push_back(gg);
       }
       if (!g1.empty()) {
-        launch_gemm<double>(upload_tmp(g1, tmp), (int64_t)g1.size(), k, k, h.stream);
-        launch_gemm<double>(upload_tmp(g2, tmp), (int64_t)g2.size(), k, k, h.stream);
+        gemm(g1, tmp);
+        gemm(g2, tmp);
       }
       h.check_launch();
       free_tmp(tmp);
