@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=3)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
+    ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-control build")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming kernel (read MIB MiB, write MIB MiB) and exit; "
                          "its HBM counters calibrate the traffic of the profiled kernels")
@@ -191,6 +192,62 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch):
     }
 
 
+# The paper's row for this workload in its table of the spectral-norm sphere
+# experiment (Section 5): mean rank, recompressed basis and matrix storage in
+# KB per degree of freedom, relative spectral error.
+SPECTRAL_PAPER = {"rank": 15, "basis_kb_per_dof": 1.7, "matrix_kb_per_dof": 312.3, "rel_error": 1.74e-5}
+
+
+def spectral_form(args, dh2, torch):
+    """The spectral-norm error control on its own workload (sphere n = 32768,
+    kappa 32, m 4, leaf 32, eps 1e-4): one build after one warm-up build, ranks
+    and storage against the paper's row, event-timed single-vector matvecs."""
+    w = synth.WORKLOADS["sphere32k_spec"]
+    V, T = synth.make_mesh(w)
+    n = len(T)
+    X = synth.complex_gaussian(n, 1, seed=0)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    Yd = torch.empty_like(Xd)
+    tb = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=1,
+                       norm=dh2.NORM_SPECTRAL)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        if len(tb) < 2:
+            h.free()
+    st = h.stats()
+    h.matvec(Xd, Yd)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(args.matvec_reps):
+        ev0.record()
+        h.matvec(Xd, Yd)
+        ev1.record()
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    h.free()
+    mv_ms = statistics.median(times)
+    mv_bytes = st["matvec_bytes"] + st["matvec_bytes_per_rhs"]
+    matrix = (st["near_entries"] + st["coupling_entries"]) * 16 / 1024 / n
+    basis = st["basis_entries"] * 16 / 1024 / n
+    log("spectral control %s: build %.2f s, mean rank %.1f / %.1f, matrix %.1f KB/DOF, basis %.2f KB/DOF, "
+        "matvec %.3f ms" % (w.name, tb[-1], st["rank_mean_row"], st["rank_mean_col"], matrix, basis, mv_ms))
+    return {
+        "workload": "%s: unit sphere n=%d, kappa=%g, m=%d, leaf %d, eta=%g, eta1=%g, tol=%g, spectral control, "
+                    "FP64, 1 right-hand side" % (w.name, n, w.kappa, w.order, w.leaf, w.eta, w.eta1, w.tol),
+        "build_s": round(tb[-1], 3),
+        "build_phases_ms": {k[3:]: round(v, 1) for k, v in st.items() if k.startswith("ms_")},
+        "rank_mean_row": round(st["rank_mean_row"], 2), "rank_mean_col": round(st["rank_mean_col"], 2),
+        "rank_max_row": st["rank_max_row"],
+        "matrix_kb_per_dof": round(matrix, 1), "basis_kb_per_dof": round(basis, 2),
+        "matvec_ms": round(mv_ms, 3), "matvec_gbs": round(mv_bytes / (mv_ms * 1e-3) / 1e9, 1),
+        "paper_row": SPECTRAL_PAPER,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -277,6 +334,10 @@ def main():
     if not args.no_fp32:
         fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch)
 
+    spec = None
+    if not args.no_spectral:
+        spec = spectral_form(args, dh2, torch)
+
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -320,6 +381,7 @@ def main():
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
         "cpu_baseline": base,
         "fp32_form": fp32,
+        "spectral_form": spec,
     }
     print(json.dumps(out), flush=True)
 

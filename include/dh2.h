@@ -59,6 +59,18 @@ typedef struct {
  * Householder QR and SVD of the recompression are FP64 in both forms. */
 typedef enum { DH2_FP64 = 0, DH2_FP32 = 1 } dh2_precision;
 
+/* Error control of the recompression (Section 5).  Block weights
+ * omega_b = |R_tc S_b R_sc^*|, the norm of the interpolated block, and the
+ * rank rule per cluster and direction on the block-normalised total-weight
+ * matrix with singular values sigma_1 >= sigma_2 >= ...:
+ *   DH2_NORM_FROBENIUS  Frobenius norm; rank = smallest k with
+ *                       sum_{i>k} sigma_i^2 <= eps^2 (the default, used for the
+ *                       sphere and cube experiments of Section 5)
+ *   DH2_NORM_SPECTRAL   spectral norm; rank = smallest k with sigma_{k+1} <= eps
+ *                       (the variant of the sphere experiment at doubled wave
+ *                       numbers, Section 5) */
+typedef enum { DH2_NORM_FROBENIUS = 0, DH2_NORM_SPECTRAL = 1 } dh2_norm;
+
 /* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then
  * override fields; zero fields take the defaults given here. */
 typedef struct {
@@ -68,7 +80,7 @@ typedef struct {
                          Remark on the construction of directions; default 10 (Section 5) */
   int32_t max_nrhs;   /* largest nrhs dh2_matvec will be called with; the matvec
                          workspace is reserved at build time.  Default 16.          */
-  int32_t reserved0;
+  int32_t norm;       /* dh2_norm, default DH2_NORM_FROBENIUS                        */
   void* stream;       /* hipStream_t for all work of this handle; NULL = default stream */
   double workspace_gb;/* device workspace for the recompression batches; default 8 */
 } dh2_options;
@@ -85,7 +97,8 @@ typedef struct dh2_problem* dh2_handle;
  *   leafsize  maximal number of triangles in a leaf cluster, >= 1
  *   tol       recompression accuracy eps >= 0: per cluster and direction the rank is
  *             the smallest with sum_{i>k} sigma_i^2 <= eps^2 for the block-normalised
- *             total-weight matrices (block-relative Frobenius control, Section 5);
+ *             total-weight matrices (block-relative Frobenius control, Section 5;
+ *             options.norm = DH2_NORM_SPECTRAL: the smallest with sigma_{k+1} <= eps);
  *             tol = 0 keeps every nonzero singular value
  *   out       receives the handle; *out is set to NULL on failure
  * Errors: DH2_ERR_ARG (bad scalar), DH2_ERR_GEOMETRY (index out of range,

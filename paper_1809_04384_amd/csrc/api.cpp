@@ -469,7 +469,7 @@ struct Builder {
   }
 
   // ------------------------------------------------------------------
-  // block weights omega_b = |R_tc S_b R_sc^*|_F
+  // block weights omega_b = |R_tc S_b R_sc^*|_F, or its spectral norm
   void block_weights() {
     const int64_t nb = (int64_t)p.adm.size();
     double* om_d = h.alloc<double>(nb);
@@ -507,13 +507,72 @@ struct Builder {
       }
       gemm(g1, tmp);
       gemm(g2, tmp);
-      launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
+      if (h.norm_mode == 0)
+        launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
+      else
+        spectral_weights(b0, b1, S, T1, T2, om_d, tmp);
       h.check_launch();
       free_tmp(tmp);
     }
     h.omega.resize(nb);
     if (nb) HIPCHK(hipMemcpy(h.omega.data(), om_d, nb * sizeof(double), hipMemcpyDeviceToHost));
     h.release(om_d);
+  }
+
+  // omega_b = |M_b|_2 for M_b = R_tc S_b R_sc^* (rt x rs, column-major in T2 with
+  // leading dimension max(rt, 1)), blocks [b0, b1).  The Gram matrix of the
+  // smaller side is squared kSpecSquarings times, each time after an exact
+  // power-of-two normalisation, so Gs ~ G^(2^j); a column of Gs then spans the
+  // dominant eigenvector up to (lambda_2 / lambda_1)^(2^j) and its Rayleigh
+  // quotient gives |M_b|_2 (k_spec_final).  S and T1 hold the two ping-pong
+  // copies of the Gram power.
+  static constexpr int kSpecSquarings = 10;
+  void spectral_weights(int64_t b0, int64_t b1, C64* S, C64* T1, C64* T2, double* om_d,
+                        std::vector<void*>& tmp) {
+    const size_t kk = (size_t)k * k;
+    std::vector<GemmDesc> gram, sq[2];
+    std::vector<FrobDesc> sc[2];
+    std::vector<SpecDesc> sd;
+    for (int64_t b = b0; b < b1; ++b) {
+      const AdmBlock& a = p.adm[b];
+      const int rt = rR[p.slot_of(a.t, a.c)], rs = rR[p.slot_of(a.s, a.c)];
+      const size_t i = (size_t)(b - b0);
+      const int side = rs <= rt ? 0 : 1;
+      const int pp = side == 0 ? rs : rt;
+      const int ldm = std::max(rt, 1), ldg = std::max(pp, 1);
+      C64* M = T2 + i * kk;
+      C64* G[2] = {S + i * kk, T1 + i * kk};
+      if (rt > 0 && rs > 0) {
+        GemmDesc g{};
+        g.A = M; g.lda = ldm;
+        g.B = M; g.ldb = ldm;
+        if (side == 0) {            // M^* M
+          g.opA = 2; g.M = rs; g.K = rt; g.N = rs;
+        } else {                    // M M^*
+          g.opB = 2; g.M = rt; g.K = rs; g.N = rt;
+        }
+        g.C = G[0]; g.ldc = ldg;
+        g.alpha_re = 1.0;
+        gram.push_back(g);
+        for (int j = 0; j < 2; ++j) {
+          sc[j].push_back({G[j], pp, pp, ldg, 0, 0});
+          GemmDesc q{};
+          q.A = G[j]; q.lda = ldg; q.M = pp; q.K = pp;
+          q.B = G[j]; q.ldb = ldg; q.N = pp;
+          q.C = G[1 - j]; q.ldc = ldg;
+          q.alpha_re = 1.0;
+          sq[j].push_back(q);
+        }
+      }
+      sd.push_back({G[kSpecSquarings % 2], M, rt > 0 && rs > 0 ? pp : 0, ldg, rt, rs, ldm, side, b});
+    }
+    gemm(gram, tmp);
+    const FrobDesc* scd[2] = {upload_tmp(sc[0], tmp), upload_tmp(sc[1], tmp)};
+    for (int j = 0; j < kSpecSquarings; ++j) {
+      launch_scale_pow2(scd[j % 2], (int64_t)sc[j % 2].size(), h.stream);
+      gemm(sq[j % 2], tmp);
+    }
+    launch_spec_final(upload_tmp(sd, tmp), (int64_t)sd.size(), om_d, h.stream);
   }
 
   // ------------------------------------------------------------------
@@ -1456,6 +1515,10 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     g_err = "unknown precision";
     return DH2_ERR_ARG;
   }
+  if (opt.norm != DH2_NORM_FROBENIUS && opt.norm != DH2_NORM_SPECTRAL) {
+    g_err = "unknown norm";
+    return DH2_ERR_ARG;
+  }
   const double eta1 = opt.eta1 > 0 ? opt.eta1 : 10.0;
   const int max_nrhs = opt.max_nrhs > 0 ? opt.max_nrhs : 16;
   const double wsgb = opt.workspace_gb > 0 ? opt.workspace_gb : 8.0;
@@ -1477,7 +1540,7 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     h->stream = (hipStream_t)opt.stream;
     h->max_nrhs = max_nrhs;
     h->tol = tol;
-    h->norm_mode = 0;
+    h->norm_mode = opt.norm;
     h->plan.kappa = kappa;
     h->plan.order = order;
     h->plan.eta = eta;

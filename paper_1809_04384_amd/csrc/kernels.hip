@@ -959,6 +959,122 @@ __global__ void __launch_bounds__(256) k_frob(const FrobDesc* __restrict__ dd, d
   if (threadIdx.x == 0) out[d.index] = sqrt(red[0]);
 }
 
+// Exact power-of-two normalisation of a batch of matrices in place: A <- A 2^-e
+// with 2^(e-1) <= max |a_ij| < 2^e (real and imaginary parts); a zero matrix
+// stays zero.  Keeps the repeated squaring of the Gram matrices (spectral block
+// weights) in range without rounding.
+__global__ void __launch_bounds__(256) k_scale_pow2(const FrobDesc* __restrict__ dd) {
+  const FrobDesc d = dd[blockIdx.x];
+  z64* A = (z64*)const_cast<void*>(d.A);
+  const int64_t cnt = (int64_t)d.M * d.N;
+  double mx = 0.0;
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+    const z64 v = A[(e % d.M) + (e / d.M) * (int64_t)d.ld];
+    mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (!(red[0] > 0.0)) return;
+  int ex = 0;
+  frexp(red[0], &ex);
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+    z64& v = A[(e % d.M) + (e / d.M) * (int64_t)d.ld];
+    v = z64{ldexp(v.x, -ex), ldexp(v.y, -ex)};
+  }
+}
+
+// Largest singular value of M (rt x rs) from a high power of its Gram matrix:
+// Gs ~ (M^* M)^(2^j) (side 0, p = rs) or (M M^*)^(2^j) (side 1, p = rt).  The
+// column v of Gs with the largest norm lies, up to a component that the powers
+// have driven below rounding, in the dominant eigenspace, so the Rayleigh
+// quotient |M v| / |v| (side 0) or |M^* v| / |v| (side 1) is |M|_2.  A zero M
+// gives 0.  One workgroup per matrix; p <= kSpecMaxP.
+__global__ void __launch_bounds__(256) k_spec_final(const SpecDesc* __restrict__ dd, double* __restrict__ out) {
+  const SpecDesc d = dd[blockIdx.x];
+  const z64* G = (const z64*)d.G;
+  const z64* M = (const z64*)d.M;
+  const int tid = threadIdx.x;
+  __shared__ double s_val[256];
+  __shared__ int s_idx[256];
+  __shared__ z64 s_v[kSpecMaxP];
+  // column of largest norm (ties: the smallest index)
+  double best = -1.0;
+  int bi = 0;
+  for (int j = tid; j < d.p; j += 256) {
+    double a = 0.0;
+    for (int i = 0; i < d.p; ++i) {
+      const z64 g = G[i + (int64_t)j * d.ldg];
+      a += g.x * g.x + g.y * g.y;
+    }
+    if (a > best) {
+      best = a;
+      bi = j;
+    }
+  }
+  s_val[tid] = best;
+  s_idx[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double o = s_val[tid + s];
+      const int oi = s_idx[tid + s];
+      if (o > s_val[tid] || (o == s_val[tid] && oi < s_idx[tid])) {
+        s_val[tid] = o;
+        s_idx[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (!(s_val[0] > 0.0)) {
+    if (tid == 0) out[d.index] = 0.0;
+    return;
+  }
+  const int jv = s_idx[0];
+  for (int i = tid; i < d.p; i += 256) s_v[i] = G[i + (int64_t)jv * d.ldg];
+  __syncthreads();
+  double vv = 0.0, yy = 0.0;
+  for (int i = tid; i < d.p; i += 256) vv += s_v[i].x * s_v[i].x + s_v[i].y * s_v[i].y;
+  if (d.side == 0) {
+    for (int i = tid; i < d.rt; i += 256) {
+      double ar = 0.0, ai = 0.0;
+      for (int j = 0; j < d.rs; ++j) {
+        const z64 a = M[i + (int64_t)j * d.ldm], v = s_v[j];
+        ar += a.x * v.x - a.y * v.y;
+        ai += a.x * v.y + a.y * v.x;
+      }
+      yy += ar * ar + ai * ai;
+    }
+  } else {
+    for (int j = tid; j < d.rs; j += 256) {
+      double ar = 0.0, ai = 0.0;
+      for (int i = 0; i < d.rt; ++i) {
+        const z64 a = M[i + (int64_t)j * d.ldm], v = s_v[i];
+        ar += a.x * v.x + a.y * v.y;
+        ai += a.x * v.y - a.y * v.x;
+      }
+      yy += ar * ar + ai * ai;
+    }
+  }
+  __syncthreads();
+  s_val[tid] = vv;
+  __shared__ double s_y[256];
+  s_y[tid] = yy;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      s_val[tid] += s_val[tid + s];
+      s_y[tid] += s_y[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) out[d.index] = sqrt(s_y[0] / s_val[0]);
+}
+
 // Copy of a sub-matrix (column selection / layout change).
 template <typename R>
 __global__ void k_copy(const CopyDesc* __restrict__ dd) {
@@ -1120,6 +1236,14 @@ void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st) {
 }
 template void launch_frob<double>(const FrobDesc*, int64_t, double*, hipStream_t);
 template void launch_frob<float>(const FrobDesc*, int64_t, double*, hipStream_t);
+
+void launch_scale_pow2(const FrobDesc* d, int64_t nb, hipStream_t st) {
+  if (nb > 0) hipLaunchKernelGGL(k_scale_pow2, dim3((unsigned)nb), dim3(256), 0, st, d);
+}
+
+void launch_spec_final(const SpecDesc* d, int64_t nb, double* out, hipStream_t st) {
+  if (nb > 0) hipLaunchKernelGGL(k_spec_final, dim3((unsigned)nb), dim3(256), 0, st, d, out);
+}
 
 template <typename R>
 void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st) {

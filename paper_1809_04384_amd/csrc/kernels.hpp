@@ -84,6 +84,17 @@ struct FrobDesc {
   int64_t index;
 };
 
+// Spectral norm of M (rt x rs, leading dimension ldm) from the normalised power
+// Gs (p x p, leading dimension ldg) of its Gram matrix: side 0 Gs ~ (M^* M)^(2^j)
+// with p = rs, side 1 Gs ~ (M M^*)^(2^j) with p = rt.  out[index] = |M|_2.
+constexpr int kSpecMaxP = 512;
+struct SpecDesc {
+  const void* G;
+  const void* M;
+  int32_t p, ldg, rt, rs, ldm, side;
+  int64_t index;
+};
+
 struct CopyDesc {
   const void* src;
   void* dst;
@@ -115,6 +126,9 @@ void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, h
 void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, hipStream_t st);
 template <typename R>
 void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st);
+// A <- A 2^-e per matrix (FP64 complex, FrobDesc.A is written), 2^(e-1) <= max |a| < 2^e
+void launch_scale_pow2(const FrobDesc* d, int64_t nb, hipStream_t st);
+void launch_spec_final(const SpecDesc* d, int64_t nb, double* out, hipStream_t st);
 template <typename R>
 void launch_copy(const CopyDesc* d, int64_t nb, hipStream_t st);
 // dst (N x M, leading dimension ldd) = transpose of src (M x N, leading dimension lds), per descriptor

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdh2.so")
 DH2_OK = 0
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_GEOMETRY", 3: "ERR_OOM", 4: "ERR_DEVICE", 5: "ERR_NUMERIC"}
 FP64, FP32 = 0, 1
+NORM_FROBENIUS, NORM_SPECTRAL = 0, 1
 INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col": 5,
            "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
            "total_weight_row": 10, "total_weight_col": 11, "coupling": 12}
@@ -38,7 +39,7 @@ class Geometry(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("eta1", ctypes.c_double),
-                ("max_nrhs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_nrhs", ctypes.c_int32), ("norm", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace_gb", ctypes.c_double)]
 
 
@@ -150,7 +151,7 @@ class Handle:
     """A built DH^2 matrix on the current HIP device."""
 
     def __init__(self, V, T, kappa, order, eta, leafsize, tol, eta1=10.0, precision=FP64,
-                 max_nrhs=16, stream=None, workspace_gb=0.0):
+                 max_nrhs=16, stream=None, workspace_gb=0.0, norm=NORM_FROBENIUS):
         lib = load()
         g, keep = _geometry(V, T)
         opt = Options()
@@ -160,6 +161,7 @@ class Handle:
         opt.max_nrhs = max_nrhs
         opt.stream = stream
         opt.workspace_gb = workspace_gb
+        opt.norm = norm
         self.precision = precision
         self.max_nrhs = max_nrhs
         self.n = int(np.asarray(T).shape[0])

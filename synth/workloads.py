@@ -22,6 +22,7 @@ class Workload:
     eta: float = 1.0
     eta1: float = 10.0
     nrhs: int = 1
+    norm: str = "fro"     # error control of the recompression: "fro" | "spectral"
 
     @property
     def n(self):
@@ -45,6 +46,9 @@ WORKLOADS = {
     "sphere32k": Workload("sphere32k", "sphere", 64, 16.0, 5, 64, 1e-6),
     # unit sphere n = 131072, kappa 32, m 5, leaf 64, tol 1e-4, 16 right-hand sides
     "sphere131k": Workload("sphere131k", "sphere", 128, 32.0, 5, 64, 1e-4, nrhs=16),
+    # the spectral-norm experiment on the sphere at doubled wave numbers (Section 5):
+    # n = 32768, kappa 32, m 4, leaf 32, eps 1e-4, spectral block-relative control
+    "sphere32k_spec": Workload("sphere32k_spec", "sphere", 64, 32.0, 4, 32, 1e-4, norm="spectral"),
     # directional stress cases: every admissible block carries a direction c != 0
     # (small eta1 makes every level directional, larger eta admits blocks early)
     "dir512": Workload("dir512", "sphere", 8, 6.0, 3, 8, 1e-6, eta=8.0, eta1=1.0),

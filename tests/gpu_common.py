@@ -15,12 +15,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def oracle_for(name):
-    if name not in _oracles:
+def oracle_for(name, norm="fro"):
+    key = (name, norm)
+    if key not in _oracles:
         w = synth.WORKLOADS[name]
         V, T = synth.make_mesh(w)
-        _oracles[name] = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1)
-    return _oracles[name]
+        _oracles[key] = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, norm=norm)
+    return _oracles[key]
 
 
 def build_handle(name, **kw):

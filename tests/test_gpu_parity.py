@@ -204,3 +204,44 @@ def test_fp32_form_matches_fp64(name):
             assert err <= 1e-4
     finally:
         h.free()
+
+
+SPECTRAL_CASES = ["dir512", "sphere2k", "cube1200dir", "dir2k"]
+
+
+@pytest.mark.parametrize("name", SPECTRAL_CASES)
+def test_spectral_control_matches_oracle(name):
+    """Spectral error control (options.norm = spectral): block weights
+    |R_tc S_b R_sc^*|_2 element by element, ranks and singular values, and the
+    matvec against the oracle built with the same rule."""
+    from paper_1809_04384_amd import dh2
+    o = oracle_for(name, norm="spectral")
+    h, slots = build_handle(name, norm=dh2.NORM_SPECTRAL)
+    try:
+        om = h.inspect("omega")[:, 0].real
+        assert om.shape == o.omega.shape
+        if len(om):
+            err = np.max(np.abs(om - o.omega) / o.omega)
+            say("[gpu] %s spectral block weights: max rel err %.3e" % (name, err))
+            assert err <= 1e-12
+        for kind, ranks_o, sig_o in (("row", o.rank, o.sig), ("col", o.rankW, o.sigW)):
+            ranks = h.inspect("rank_" + kind)[:, 0].real.astype(int)
+            for q, (t, c, flags) in enumerate(slots.tolist()):
+                key = (t, c)
+                if key not in ranks_o:
+                    continue
+                s_o = sig_o[key]
+                s_g = h.inspect("sigma_" + kind, q)[:, 0].real
+                m = min(len(s_o), len(s_g))
+                if m:
+                    assert np.max(np.abs(s_o[:m] - s_g[:m])) <= 1e-12 * s_o[0] + 1e-300
+                if ranks[q] != ranks_o[key]:
+                    # only a singular value at the threshold may change a rank
+                    assert np.any(np.abs(s_o - o.tol) <= 1e-8 * o.tol), (kind, key, ranks[q], ranks_o[key])
+        X = synth.complex_gaussian(o.n, 3, seed=0)
+        Y = _matvec(h, X)
+        err = rel(Y, o.matvec(X.T).T)
+        say("[gpu] %s spectral control matvec rel err %.3e" % (name, err))
+        assert err <= 1e-10
+    finally:
+        h.free()

@@ -22,7 +22,7 @@ def build(name, **over):
         p = dict(kappa=w.kappa, order=w.order, eta=w.eta, leaf=w.leaf, tol=w.tol, eta1=w.eta1)
         p.update(over)
         _cache[key] = OracleDH2(V, T, p["kappa"], p["order"], p["eta"], p["leaf"], p["tol"],
-                                eta1=p["eta1"])
+                                eta1=p["eta1"], norm=p.get("norm", "fro"))
     return _cache[key]
 
 
@@ -59,6 +59,10 @@ def test_block_weights_are_block_norms(o):
 def test_fast_recompression_matches_general_algorithm(o):
     """Singular values and ranks of the fast algorithm (Section 3.2) equal those
     of the dense algorithm of Section 3.1 applied to the expanded G_int."""
+    _fast_vs_general(o)
+
+
+def _fast_vs_general(o):
     if not o.st.adm:
         pytest.skip("no admissible blocks")
     Gi = o.dense_interp()
@@ -107,6 +111,68 @@ def test_recompression_error_within_tolerance(o):
     Gt = o.dense_compressed()
     rel = np.linalg.norm(Gi - Gt, 2) / np.linalg.norm(Gi, 2)
     assert rel <= o.tol
+
+
+SPECTRAL_CASES = ["dir512", "cube768"]
+
+
+@pytest.mark.parametrize("name", SPECTRAL_CASES)
+def test_spectral_block_weights_are_block_norms(name):
+    """Spectral error control (Section 5): omega_b is the spectral norm of the
+    interpolated block V_tc S_b V_sc^*, here from the expanded bases and a dense
+    SVD (the oracle takes it from the basis weights, R_tc S_b R_sc^*)."""
+    o = build(name, norm="spectral")
+    for b in range(0, len(o.st.adm), max(1, len(o.st.adm) // 50)):
+        t, s, c = o.st.adm[b]
+        blk = o.expanded_basis(t, c, o.Vleaf, o.E) @ o.coupling(b) @ H(o.expanded_basis(s, c, o.Vleaf, o.E))
+        ref = np.linalg.svd(blk, compute_uv=False)[0]
+        assert abs(ref - o.omega[b]) <= 1e-12 * ref
+        # the spectral norm lies between |.|_F / sqrt(rank) and |.|_F
+        fro = np.linalg.norm(blk)
+        assert o.omega[b] <= fro * (1 + 1e-14) and o.omega[b] >= fro / math.sqrt(min(blk.shape)) * (1 - 1e-14)
+
+
+def test_rank_rules_by_enumeration():
+    """Both rank rules against their definitions by enumerating k: the smallest
+    k whose discarded singular values sigma_{k+1}, sigma_{k+2}, ... have a sum of
+    squares within eps^2 (Frobenius) or are all within eps (spectral)."""
+    rng = np.random.default_rng(7)
+    for trial in range(300):
+        m = int(rng.integers(0, 14))
+        sig = np.sort(10.0 ** rng.uniform(-9, 0, size=m))[::-1]
+        eps = 10.0 ** rng.uniform(-8, 0)
+        fro = min(k for k in range(m + 1) if np.sum(sig[k:] ** 2) <= eps * eps)
+        spec = min(k for k in range(m + 1) if np.all(sig[k:] <= eps))
+        r = OracleDH2.__new__(OracleDH2)
+        r.tol = eps
+        r.norm = "fro"
+        assert r.rank_rule(sig) == fro
+        r.norm = "spectral"
+        assert r.rank_rule(sig) == spec
+        assert spec <= fro
+
+
+@pytest.mark.parametrize("name", SPECTRAL_CASES)
+def test_spectral_fast_recompression_matches_general_algorithm(name):
+    """The fast algorithm of Section 3.2 against the dense one of Section 3.1,
+    both under the spectral rank rule and spectral block weights."""
+    _fast_vs_general(build(name, norm="spectral"))
+
+
+@pytest.mark.parametrize("name", SPECTRAL_CASES)
+def test_spectral_block_errors_within_tolerance(name):
+    """Spectral control: per admissible block |G_int,b - Gtilde_b|_2 <= 2 eps
+    omega_b (eps omega_b for the row and for the column truncation, whose
+    weighted matrices hold G_int,b / omega_b), and the whole matrix within
+    eps |G_int|_2."""
+    o = build(name, norm="spectral")
+    Gi = o.dense_interp()
+    Gt = o.dense_compressed()
+    st = o.st
+    for b, (t, s, c) in enumerate(st.adm):
+        blk = np.ix_(st.idx(t), st.idx(s))
+        assert np.linalg.norm(Gi[blk] - Gt[blk], 2) <= 2 * o.tol * o.omega[b]
+    assert np.linalg.norm(Gi - Gt, 2) <= o.tol * np.linalg.norm(Gi, 2)
 
 
 def test_power_iteration_matches_dense_norm():
