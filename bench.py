@@ -49,7 +49,17 @@ def parse():
 
 
 PMC_FILE = os.path.join(ROOT, "profiles", "k_mv_rows_mfma_near_sphere131k_pmc.txt")
-MATVEC_SRC = os.path.join(ROOT, "paper_1809_04384_amd", "csrc", "matvec.hip")
+MATVEC_SRCS = [os.path.join(ROOT, "paper_1809_04384_amd", "csrc", f) for f in ("matvec.hip", "api.cpp")]
+
+
+def source_sha256():
+    """Hash of the matvec kernels and of the library source that schedules
+    their launches (row lists and their order)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in MATVEC_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -57,7 +67,6 @@ def measured_traffic():
     counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the
     streaming-kernel calibration), or None when the summary is missing or the
     kernel source changed since the counters were taken."""
-    import hashlib
     if not os.path.exists(PMC_FILE):
         return None
     kv = {}
@@ -65,7 +74,7 @@ def measured_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(MATVEC_SRC, "rb").read()).hexdigest()
+    sha = source_sha256()
     if kv.get("source_sha256") != sha:
         return None
     try:

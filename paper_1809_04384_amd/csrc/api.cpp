@@ -226,6 +226,30 @@ struct dh2_problem {
 
 namespace {
 
+// Order of the rows of a launch with one workgroup per row (k_mv_rows_mfma maps
+// workgroup b to list entry xcd q + min(xcd, rm) + (b >> 3), xcd = b & 7, with
+// n = 8 q + rm): the rows, longest first, are dealt to the 8 XCDs in snake
+// order (the last partial round forward), so the per-XCD totals are balanced,
+// and each XCD's contiguous share starts with its longest rows.  Returns the
+// row indices in list order.
+std::vector<int64_t> xcd_balanced_order(const std::vector<double>& work) {
+  const int64_t n = (int64_t)work.size();
+  std::vector<int64_t> by(n);
+  std::iota(by.begin(), by.end(), (int64_t)0);
+  std::stable_sort(by.begin(), by.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+  std::vector<std::vector<int64_t>> share(8);
+  const int64_t full = n / 8 * 8;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t r = i / 8, pos = i % 8;
+    const int64_t x = (i < full && (r & 1)) ? 7 - pos : pos;
+    share[x].push_back(by[i]);
+  }
+  std::vector<int64_t> out;
+  out.reserve(n);
+  for (int x = 0; x < 8; ++x) out.insert(out.end(), share[x].begin(), share[x].end());
+  return out;
+}
+
 typedef z64 C64;
 
 // slot-level bookkeeping used during the build
@@ -1153,7 +1177,18 @@ struct Builder {
     h.coup_rows_d = h.upload(crows);
     h.coup_blks_d = h.upload(cblks);
     h.n_coup_rows = (int64_t)crows.size();
-    h.coup_mf_rows_d = h.upload(mrows);
+    {
+      std::vector<double> work(mrows.size());
+      for (size_t i = 0; i < mrows.size(); ++i) {
+        double w = 0;
+        for (int32_t e = mrows[i].seg_begin; e < mrows[i].seg_end; ++e) w += (double)msegs[e].lda * msegs[e].ncols;
+        work[i] = w;
+      }
+      std::vector<MfRow> ordered;
+      ordered.reserve(mrows.size());
+      for (int64_t i : xcd_balanced_order(work)) ordered.push_back(mrows[i]);
+      h.coup_mf_rows_d = h.upload(ordered);
+    }
     h.coup_mf_segs_d = h.upload(msegs);
     h.xh_tr_d = h.upload(xtr);
     h.n_xh_tr = (int64_t)xtr.size();
@@ -1217,7 +1252,16 @@ struct Builder {
     {
       std::vector<MfRow> mf;
       mf.reserve(nrows.size());
-      for (const NearRow& r : nrows) mf.push_back({at(Yp, r.row0), (int32_t)n, r.nr, r.seg_begin, r.seg_end});
+      std::vector<double> work(nrows.size());
+      for (size_t i = 0; i < nrows.size(); ++i) {
+        double w = 0;
+        for (int32_t e = nrows[i].seg_begin; e < nrows[i].seg_end; ++e) w += (double)nrows[i].nr * nsegs[e].ncols;
+        work[i] = w;
+      }
+      for (int64_t i : xcd_balanced_order(work)) {
+        const NearRow& r = nrows[i];
+        mf.push_back({at(Yp, r.row0), (int32_t)n, r.nr, r.seg_begin, r.seg_end});
+      }
       h.near_mf_rows_d = h.upload(mf);
     }
     h.near_matvec_bytes = nbytes * es;
