@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--cpu-sample-leaves", type=int, default=3)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-control build")
+    ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming kernel (read MIB MiB, write MIB MiB) and exit; "
                          "its HBM counters calibrate the traffic of the profiled kernels")
@@ -148,16 +149,20 @@ def cpu_baseline(w, V, T, X, nleaves):
     }
 
 
-def fp32_form(args, w, V, T, X, Y64, dh2, torch):
-    """The FP32 form on the same workload: one build, event-timed matvecs on
-    complex64 right-hand sides (the FP64 draw rounded), and the relative
-    Frobenius difference of the full n x nrhs result from the FP64 form."""
+def fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=None):
+    """The FP32 form (or, with precision = BF16X3, its split-BF16x3 variant)
+    on the same workload: one build, event-timed matvecs on complex64
+    right-hand sides (the FP64 draw rounded), and the relative Frobenius
+    difference of the full n x nrhs result from the FP64 form."""
+    if precision is None:
+        precision = dh2.FP32
+    label = "fp32" if precision == dh2.FP32 else "bf16x3"
     nrhs = X.shape[0]
     Xd = torch.from_numpy(X.astype(np.complex64)).to("cuda:0")
     Yd = torch.empty_like(Xd)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=precision,
                    max_nrhs=max(nrhs, 1))
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
@@ -187,10 +192,15 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch):
     torch.cuda.synchronize()
     err = (torch.linalg.vector_norm(Yd.to(torch.complex128) - Y64) / torch.linalg.vector_norm(Y64)).item()
     h.free()
-    log("fp32 form: build %.2f s, matvec %.3f ms (%.1f GB/s), near %.3f ms (%.1f GB/s), rel. diff vs FP64 %.2e"
-        % (tb, mv_ms, mv_bytes / (mv_ms * 1e-3) / 1e9, near_avg, near_alg / (near_avg * 1e-3) / 1e9, err))
+    log("%s form: build %.2f s, matvec %.3f ms (%.1f GB/s), near %.3f ms (%.1f GB/s), rel. diff vs FP64 %.2e"
+        % (label, tb, mv_ms, mv_bytes / (mv_ms * 1e-3) / 1e9, near_avg, near_alg / (near_avg * 1e-3) / 1e9, err))
     return {
-        "dtype": "f32 matvec and near field; FP64 recompression", "build_s": round(tb, 3),
+        "dtype": ("f32 matvec and near field; FP64 recompression" if precision == dh2.FP32 else
+                  "f32 matvec and near field; recompression products split-BF16x3 with f32 accumulation, "
+                  "FP64 QR and SVD"),
+        "build_s": round(tb, 3),
+        "build_gemm": {"flops": st["gemm_flops"], "launches": st["gemm_launches"]},
+        "ranks": {"row_mean": round(st["rank_mean_row"], 2), "row_max": st["rank_max_row"]},
         "matvec_ms": round(mv_ms, 3), "value": round(mv_bytes / (mv_ms * 1e-3) / 1e9, 2), "unit": "GB/s",
         "rel_diff_vs_fp64": err,
         "matvec_phases_ms": {k: round(sum(v) / len(v), 4) for k, v in phases.items()},
@@ -343,6 +353,10 @@ def main():
     if not args.no_fp32:
         fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch)
 
+    bf = None
+    if not args.no_bf16x3:
+        bf = fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=dh2.BF16X3)
+
     spec = None
     if not args.no_spectral:
         spec = spectral_form(args, dh2, torch)
@@ -375,6 +389,7 @@ def main():
         "build_s": round(statistics.median(builds), 3),
         "matvec_ms": round(mv_ms, 3),
         "build_phases_ms": {k[3:]: round(v, 1) for k, v in st.items() if k.startswith("ms_")},
+        "build_gemm": {"flops": st["gemm_flops"], "launches": st["gemm_launches"]},
         "matvec_phases_ms": {k: round(sum(v) / len(v), 4) for k, v in phases.items()},
         "ranks": {"row_max": st["rank_max_row"], "row_mean": round(st["rank_mean_row"], 2),
                   "col_max": st["rank_max_col"], "col_mean": round(st["rank_mean_col"], 2)},
@@ -390,6 +405,7 @@ def main():
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
         "cpu_baseline": base,
         "fp32_form": fp32,
+        "bf16x3_form": bf,
         "spectral_form": spec,
     }
     print(json.dumps(out), flush=True)

@@ -56,8 +56,14 @@ typedef struct {
  *             recompression run in FP64 (the same ranks as the FP64 form); the
  *             recompressed couplings and bases are then rounded to complex64
  *             and the matvec runs in FP32 on complex64 X / Y.
- * Householder QR and SVD of the recompression are FP64 in both forms. */
-typedef enum { DH2_FP64 = 0, DH2_FP32 = 1 } dh2_precision;
+ *   DH2_BF16X3  the FP32 form with the matrix products of the recompression
+ *             (weighted couplings, block weights, total-weight pieces, basis
+ *             changes, projections) on the BF16 matrix cores: each FP64 operand
+ *             is split into two bf16 parts and a product takes three of the four
+ *             part products, accumulated in FP32 (about 2^-16 relative per
+ *             product); ranks may differ from the FP64 form at near-ties.
+ * Householder QR and SVD of the recompression are FP64 in all forms. */
+typedef enum { DH2_FP64 = 0, DH2_FP32 = 1, DH2_BF16X3 = 2 } dh2_precision;
 
 /* Error control of the recompression (Section 5).  Block weights
  * omega_b = |R_tc S_b R_sc^*|, the norm of the interpolated block, and the
@@ -155,6 +161,8 @@ typedef struct {
   double matvec_bytes_per_rhs; /* additional algorithmic bytes per right-hand side */
   double ms_structure, ms_near, ms_interp, ms_basis_weights, ms_block_weights,
       ms_total_weights, ms_truncation, ms_projection, ms_total;
+  double gemm_flops;        /* real flops of the build's complex matrix products, 8 M N K each */
+  int64_t gemm_launches;    /* kernel launches of those products */
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);

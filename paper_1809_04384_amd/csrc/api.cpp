@@ -321,6 +321,7 @@ struct Builder {
       if (g.M > 0 && g.N > 0) v.push_back(g);
     if (v.empty()) return;
     std::stable_sort(v.begin(), v.end(), [&](const GemmDesc& a, const GemmDesc& b) { return key(a) < key(b); });
+    for (const GemmDesc& g : v) h.stats.gemm_flops += 8.0 * g.M * g.N * g.K;
     const GemmDesc* d = upload_tmp(v, tmp);
     size_t i0 = 0;
     while (i0 < v.size()) {
@@ -332,7 +333,11 @@ struct Builder {
         maxN = std::max(maxN, v[i1].N);
         ++i1;
       }
-      launch_gemm<double>(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
+      h.stats.gemm_launches += (int64_t)((i1 - i0 + 65534) / 65535);
+      if (h.precision == DH2_BF16X3)
+        launch_gemm_bf16x3(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
+      else
+        launch_gemm<double>(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
       i0 = i1;
     }
   }
@@ -1077,7 +1082,7 @@ struct Builder {
   void matvec_schedule() {
     const int nr = h.max_nrhs;
     const int64_t n = p.n;
-    const bool f32 = h.precision == DH2_FP32;
+    const bool f32 = h.precision != DH2_FP64;
     const int64_t es = f32 ? (int64_t)sizeof(z32) : (int64_t)sizeof(C64);
     auto at = [es](const void* base, int64_t e) -> char* { return (char*)base + e * es; };
     auto valloc = [&](int64_t elems) -> char* { return h.alloc<char>((size_t)std::max<int64_t>(elems, 1) * es); };
@@ -1394,10 +1399,10 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
       }
       eval.push_back(nd[b]);
     }
-    const int es = h.precision == DH2_FP32 ? (int)sizeof(z32) : (int)sizeof(C64);
+    const int es = h.precision != DH2_FP64 ? (int)sizeof(z32) : (int)sizeof(C64);
     h.near_d = h.alloc<char>((size_t)std::max<int64_t>(off, 1) * es);
     NearDesc* ndd = h.upload(eval);
-    if (h.precision == DH2_FP32)
+    if (h.precision != DH2_FP64)
       launch_near<float>(ndd, (int64_t)eval.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
     else
       launch_near<double>(ndd, (int64_t)eval.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
@@ -1411,7 +1416,7 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
     }
     CopyDesc* cpd = cp.empty() ? nullptr : h.upload(cp);
     if (!cp.empty()) {
-      if (h.precision == DH2_FP32) launch_transpose_blocks<float>(cpd, (int64_t)cp.size(), h.stream);
+      if (h.precision != DH2_FP64) launch_transpose_blocks<float>(cpd, (int64_t)cp.size(), h.stream);
       else launch_transpose_blocks<double>(cpd, (int64_t)cp.size(), h.stream);
       h.check_launch();
     }
@@ -1470,7 +1475,7 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   h.release(selfl);
   h.release(Vd);
   h.release(Td);
-  if (h.precision == DH2_FP32) bd.narrow_to_fp32();
+  if (h.precision != DH2_FP64) bd.narrow_to_fp32();
   bd.matvec_schedule();
   h.sync();
   h.stats.ms_total = now_ms() - t_start;
@@ -1555,7 +1560,7 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     }
     std::memcpy(&opt, options, options->size);
   }
-  if (opt.precision != DH2_FP64 && opt.precision != DH2_FP32) {
+  if (opt.precision != DH2_FP64 && opt.precision != DH2_FP32 && opt.precision != DH2_BF16X3) {
     g_err = "unknown precision";
     return DH2_ERR_ARG;
   }
@@ -1659,7 +1664,7 @@ void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* 
 }
 
 void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
-  if (h->precision == DH2_FP32) run_matvec_t<float>(h, X, Y, nrhs, ev);
+  if (h->precision != DH2_FP64) run_matvec_t<float>(h, X, Y, nrhs, ev);
   else run_matvec_t<double>(h, X, Y, nrhs, ev);
 }
 }  // namespace
@@ -1741,7 +1746,7 @@ dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64
         if (index < 0 || index >= (int64_t)p.near.size()) throw Fail{DH2_ERR_ARG, "index out of range"};
         r = p.cl[p.near[index].t].size;
         c = p.cl[p.near[index].s].size;
-        if (h->precision == DH2_FP32) {
+        if (h->precision != DH2_FP64) {
           // complex64 storage, widened on the host
           if (out && r * c > 0) {
             HIPCHK(hipStreamSynchronize(h->stream));

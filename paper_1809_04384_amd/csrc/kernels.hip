@@ -384,6 +384,133 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
 }
 
 // ---------------------------------------------------------------------------
+// Split-BF16x3 form of k_gemm (same descriptors, FP64 complex data in and
+// out) with the products on the BF16 matrix cores.  Each operand x is taken
+// to FP32 and split as x = hi + lo, hi = x rounded to bf16, lo = (x - hi)
+// rounded to bf16; a product is hi hi' + hi lo' + lo hi' (the dropped lo lo'
+// and the rounding of lo leave about 2^-16 of the product), accumulated in
+// FP32 and written in FP64.  Per 16-deep slice a wave issues 12 MFMAs
+// (16x16x16 bf16): three per real product of Re C += Re A Re B - Im A Im B,
+// Im C += Re A Im B + Im A Re B, kept in four accumulators.
+typedef short gm_bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rn(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
+  const float f = (float)x;
+  hi = bf16_rn(f);
+  lo = bf16_rn(f - __uint_as_float((unsigned)hi << 16));
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(const GemmDesc* __restrict__ dd, int ntm) {
+  const GemmDesc d = dd[blockIdx.y];
+  const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
+  const int m0 = tm * 32, n0 = tn * 32;
+  if (m0 >= d.M || n0 >= d.N) return;
+  const z64* A = (const z64*)d.A;
+  const z64* B = (const z64*)d.B;
+  z64* C = (z64*)d.C;
+  // [part][row of op(A) | column of op(B)][k]; parts: Re hi, Re lo, Im hi, Im lo.
+  // Rows are padded to 20 entries (40 B) so the 8-byte operand reads of a wave
+  // fall in distinct banks.
+  __shared__ __align__(16) unsigned short As[4][32][20];
+  __shared__ __align__(16) unsigned short Bs[4][32][20];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sm = (wave & 1) * 16, sn = (wave >> 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  gm_f32x4 rr, ii, ri, ir;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) rr[e] = ii[e] = ri[e] = ir[e] = 0.f;
+  z64 va[2], vb[2];
+  auto load_slice = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      int i, kk;
+      if (d.opA == 0) { i = e % 32; kk = e / 32; }
+      else { kk = e % 16; i = e / 16; }
+      const int gi = m0 + i, gk = k0 + kk;
+      z64 v{0, 0};
+      if (gi < d.M && gk < d.K) {
+        if (d.opA == 0) v = A[gi + (int64_t)gk * d.lda];
+        else {
+          v = A[gk + (int64_t)gi * d.lda];
+          if (d.opA == 2) v = conj(v);
+        }
+      }
+      va[h] = v;
+      int kb, j;
+      if (d.opB == 0) { kb = e % 16; j = e / 16; }
+      else { j = e % 32; kb = e / 32; }
+      const int gkb = k0 + kb, gj = n0 + j;
+      z64 w{0, 0};
+      if (gkb < d.K && gj < d.N) {
+        if (d.opB == 0) w = B[gkb + (int64_t)gj * d.ldb];
+        else {
+          w = B[gj + (int64_t)gkb * d.ldb];
+          if (d.opB == 2) w = conj(w);
+        }
+      }
+      vb[h] = w;
+    }
+  };
+  auto store_slice = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      int i, kk, j, kb;
+      if (d.opA == 0) { i = e % 32; kk = e / 32; }
+      else { kk = e % 16; i = e / 16; }
+      if (d.opB == 0) { kb = e % 16; j = e / 16; }
+      else { j = e % 32; kb = e / 32; }
+      split_bf16(va[h].x, As[0][i][kk], As[1][i][kk]);
+      split_bf16(va[h].y, As[2][i][kk], As[3][i][kk]);
+      split_bf16(vb[h].x, Bs[0][j][kb], Bs[1][j][kb]);
+      split_bf16(vb[h].y, Bs[2][j][kb], Bs[3][j][kb]);
+    }
+  };
+  load_slice(0);
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    store_slice();
+    __syncthreads();
+    if (k0 + 16 < d.K) load_slice(k0 + 16);
+    gm_bf16x4 a[4], b[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      a[p] = *(const gm_bf16x4*)&As[p][sm + li][4 * lk];
+      b[p] = *(const gm_bf16x4*)&Bs[p][sn + li][4 * lk];
+    }
+    rr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[1], rr, 0, 0, 0);
+    rr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[0], rr, 0, 0, 0);
+    rr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], rr, 0, 0, 0);
+    ii = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[3], ii, 0, 0, 0);
+    ii = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[3], b[2], ii, 0, 0, 0);
+    ii = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[2], ii, 0, 0, 0);
+    ri = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[3], ri, 0, 0, 0);
+    ri = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[2], ri, 0, 0, 0);
+    ri = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[2], ri, 0, 0, 0);
+    ir = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[1], ir, 0, 0, 0);
+    ir = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[3], b[0], ir, 0, 0, 0);
+    ir = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[0], ir, 0, 0, 0);
+    __syncthreads();
+  }
+  const z64 al{d.alpha_re, d.alpha_im};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // f32 16x16 output: element e of lane l is row 4 (l >> 4) + e, column l & 15
+    const int gi = m0 + sm + 4 * lk + e, gj = n0 + sn + li;
+    if (gi < d.M && gj < d.N) {
+      const z64 v = al * z64{(double)rr[e] - (double)ii[e], (double)ri[e] + (double)ir[e]};
+      z64& dst = C[gi + (int64_t)gj * d.ldc];
+      dst = d.accumulate ? dst + v : v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Householder fold (FP64): R <- R factor of [R; P_1; P_2; ...] for an n x n
 // upper triangular R (column-major, leading dimension ldr) and pieces P
 // (rows x n, column-major).  This is the QR step of the basis weights
@@ -1192,6 +1319,15 @@ void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStrea
   }
 }
 template void launch_gemm<double>(const GemmDesc*, int64_t, int, int, hipStream_t);
+
+void launch_gemm_bf16x3(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st) {
+  if (nitems <= 0 || maxM <= 0 || maxN <= 0) return;
+  const int ntm = (maxM + 31) / 32, ntn = (maxN + 31) / 32;
+  for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
+    const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
+    hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(ntm * ntn), (unsigned)cnt), dim3(256), 0, st, d + i0, ntm);
+  }
+}
 template void launch_gemm<float>(const GemmDesc*, int64_t, int, int, hipStream_t);
 
 static size_t g_lds_limit = 65536;   // per-workgroup LDS bytes usable for dynamic buffers

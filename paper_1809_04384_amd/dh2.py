@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdh2.so")
 
 DH2_OK = 0
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_GEOMETRY", 3: "ERR_OOM", 4: "ERR_DEVICE", 5: "ERR_NUMERIC"}
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
 NORM_FROBENIUS, NORM_SPECTRAL = 0, 1
 INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col": 5,
            "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
@@ -57,7 +57,8 @@ class Stats(ctypes.Structure):
                 ("ms_interp", ctypes.c_double), ("ms_basis_weights", ctypes.c_double),
                 ("ms_block_weights", ctypes.c_double), ("ms_total_weights", ctypes.c_double),
                 ("ms_truncation", ctypes.c_double), ("ms_projection", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("gemm_flops", ctypes.c_double),
+                ("gemm_launches", ctypes.c_int64)]
 
 
 class PlanSizes(ctypes.Structure):

@@ -206,6 +206,36 @@ def test_fp32_form_matches_fp64(name):
         h.free()
 
 
+@pytest.mark.parametrize("name", FP32_CASES)
+def test_bf16x3_form_matches_fp64(name):
+    """Split-BF16x3 form: the FP32 form with the recompression's matrix
+    products on the BF16 matrix cores (three bf16 part products per real
+    product, FP32 accumulation; QR and SVD in FP64).  Every right-hand-side
+    path must agree with the FP64 oracle to 1e-4 relative (the products carry
+    about 2^-16 relative error, below the tolerance of the FP32 form)."""
+    import torch
+    from paper_1809_04384_amd import dh2
+    o = oracle_for(name)
+    w = synth.WORKLOADS[name]
+    V, T = synth.make_mesh(w)
+    say("[gpu] dh2_build BF16x3 workload=%s n=%d" % (name, len(T)))
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.BF16X3)
+    try:
+        for nrhs in (1, 2, 5):
+            X = synth.complex_gaussian(o.n, nrhs, seed=20 + nrhs)
+            Xd = torch.from_numpy(X.astype(np.complex64)).to("cuda:0")
+            Yd = torch.empty_like(Xd)
+            say("[gpu] BF16x3 dh2_matvec %s nrhs=%d" % (name, nrhs))
+            h.matvec(Xd, Yd)
+            torch.cuda.synchronize()
+            Y = Yd.cpu().numpy().astype(np.complex128)
+            err = rel(Y, o.matvec(X.T).T)
+            say("[gpu] %s BF16x3 nrhs=%d rel err vs oracle %.3e" % (name, nrhs, err))
+            assert err <= 1e-4
+    finally:
+        h.free()
+
+
 SPECTRAL_CASES = ["dir512", "sphere2k", "cube1200dir", "dir2k"]
 
 
