@@ -32,6 +32,11 @@ def test_build_rejects_bad_arguments_without_gpu():
         with pytest.raises(dh2.Dh2Error) as e:
             dh2.Handle(V, T, p["kappa"], p["order"], p["eta"], p["leafsize"], p["tol"])
         assert e.value.status == 1
+    # unknown precision / norm codes are rejected before any device work
+    for kw in (dict(precision=7), dict(norm=5), dict(norm=-1)):
+        with pytest.raises(dh2.Dh2Error) as e:
+            dh2.Handle(V, T, 1.0, 3, 1.0, 8, 1e-6, **kw)
+        assert e.value.status == 1
     T2 = T.copy()
     T2[3, 1] = len(V) + 5
     with pytest.raises(dh2.Dh2Error) as e:
