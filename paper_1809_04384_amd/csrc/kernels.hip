@@ -557,17 +557,35 @@ __device__ __forceinline__ double group_sum(double v) {
   if (G >= 16) v += dpp_mov<0x140>(v);   // row mirror
   return v;
 }
-// sum over the whole wave (all lanes active), the same value in every lane
-__device__ __forceinline__ double wave_sum(double v) {
-  v = group_sum<16>(v);
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+// The four row values of a wave (every lane of row r holding the value of row
+// r) combined across rows with the gfx950 lane swaps (upper and lower halves,
+// then odd and even rows) instead of readlanes; every lane combines
+// (r0 op r2) op (r1 op r3) in the same order, so all lanes get the same bits.
+template <bool MAX>
+__device__ __forceinline__ double rows_combine(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)(b & 0xffffffffLL), hi = (unsigned)(b >> 32);
+  const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double a0 = __builtin_bit_cast(double, ((long long)sh[0] << 32) | sl[0]);
+  const double a1 = __builtin_bit_cast(double, ((long long)sh[1] << 32) | sl[1]);
+  const double h = MAX ? fmax(a0, a1) : a0 + a1;
+  const long long c = __builtin_bit_cast(long long, h);
+  const unsigned clo = (unsigned)(c & 0xffffffffLL), chi = (unsigned)(c >> 32);
+  const auto tl = __builtin_amdgcn_permlane16_swap(clo, clo, false, false);
+  const auto th = __builtin_amdgcn_permlane16_swap(chi, chi, false, false);
+  const double b0 = __builtin_bit_cast(double, ((long long)th[0] << 32) | tl[0]);
+  const double b1 = __builtin_bit_cast(double, ((long long)th[1] << 32) | tl[1]);
+  return MAX ? fmax(b0, b1) : b0 + b1;
 }
+// sum over the whole wave (all lanes active), the same value in every lane
+__device__ __forceinline__ double wave_sum(double v) { return rows_combine<false>(group_sum<16>(v)); }
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_mov<0xB1>(v));
   v = fmax(v, dpp_mov<0x4E>(v));
   v = fmax(v, dpp_mov<0x141>(v));
   v = fmax(v, dpp_mov<0x140>(v));
-  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+  return rows_combine<true>(v);
 }
 
 // Global-memory accesses through address space 1: the task pointers are
