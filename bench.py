@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-control build")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="also run the batching form with COUNT problems (64 in the recipe)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming kernel (read MIB MiB, write MIB MiB) and exit; "
                          "its HBM counters calibrate the traffic of the profiled kernels")
@@ -267,6 +269,70 @@ def spectral_form(args, dh2, torch):
     }
 
 
+def batch_form(args, dh2, torch, count):
+    """The batching form: count problems of the seeded recipe (sphere, cube and
+    ellipsoid surfaces, n ~ U[2k, 32k], kappa ~ U[4, 24], m 4, leaf 32, tol
+    1e-5), FP32 form, 64 complex64 right-hand sides each.  Builds one by one;
+    all products then run as one graph launch (dh2_batch_run), timed against
+    the same products issued one handle after another, and checked bit for
+    bit against them."""
+    ws = synth.batch_workloads(count=count)
+    nrhs = 64
+    hs, X, Ye, Yb = [], [], [], []
+    bytes_total = 0.0
+    tb = 0.0
+    for i, w in enumerate(ws):
+        V, T = synth.make_mesh(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
+                       max_nrhs=nrhs)
+        torch.cuda.synchronize()
+        tb += time.perf_counter() - t0
+        st = h.stats()
+        bytes_total += st["matvec_bytes"] + nrhs * st["matvec_bytes_per_rhs"]
+        hs.append(h)
+        X.append(torch.from_numpy(synth.complex_gaussian(len(T), nrhs, seed=100 + i).astype(np.complex64))
+                 .to("cuda:0"))
+        Ye.append(torch.empty_like(X[-1]))
+        Yb.append(torch.empty_like(X[-1]))
+    log("batch form: %d problems, n total %d, builds %.1f s" % (count, sum(w.n for w in ws), tb))
+    s = torch.cuda.Stream()
+    b = dh2.Batch(hs, X, Yb, stream=s.cuda_stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    seq, bat = [], []
+    with torch.cuda.stream(s):
+        for rep in range(args.matvec_reps + 1):
+            ev0.record(s)
+            for h, x, y in zip(hs, X, Ye):
+                h.matvec_on(x, y, s.cuda_stream)
+            ev1.record(s)
+            ev1.synchronize()
+            if rep:
+                seq.append(ev0.elapsed_time(ev1))
+            ev0.record(s)
+            b.run()
+            ev1.record(s)
+            ev1.synchronize()
+            if rep:
+                bat.append(ev0.elapsed_time(ev1))
+    same = all(torch.equal(a, c) for a, c in zip(Yb, Ye))
+    b.free()
+    for h in hs:
+        h.free()
+    t_seq, t_bat = statistics.median(seq), statistics.median(bat)
+    log("batch form: one graph launch %.3f ms, one product after another %.3f ms (x%.2f), %.1f GB/s, "
+        "equal bits %s" % (t_bat, t_seq, t_seq / t_bat, bytes_total / (t_bat * 1e-3) / 1e9, same))
+    return {
+        "workload": "%d problems: sphere / side-2 cube / ellipsoid 1:2:3, n ~ U[2048, 32768] (total %d), "
+                    "kappa ~ U[4, 24], m=4, leaf 32, tol 1e-5, FP32 form, %d complex64 right-hand sides each"
+                    % (count, sum(w.n for w in ws), nrhs),
+        "build_s_total": round(tb, 2), "graph_ms": round(t_bat, 3), "one_after_another_ms": round(t_seq, 3),
+        "speedup": round(t_seq / t_bat, 3), "value": round(bytes_total / (t_bat * 1e-3) / 1e9, 1), "unit": "GB/s",
+        "bytes_per_batch": bytes_total, "bitwise_equal_to_single_products": same,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -357,6 +423,10 @@ def main():
     if not args.no_bf16x3:
         bf = fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=dh2.BF16X3)
 
+    batch = None
+    if args.batch > 0:
+        batch = batch_form(args, dh2, torch, args.batch)
+
     spec = None
     if not args.no_spectral:
         spec = spectral_form(args, dh2, torch)
@@ -407,6 +477,7 @@ def main():
         "fp32_form": fp32,
         "bf16x3_form": bf,
         "spectral_form": spec,
+        "batch_form": batch,
     }
     print(json.dumps(out), flush=True)
 

@@ -129,6 +129,11 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
  * range), DH2_ERR_DEVICE (launch failure). */
 dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs);
 
+/* dh2_matvec enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ * instead of the handle's stream.  Calls on one handle must not overlap in
+ * time (they share its work buffers).  Errors as dh2_matvec. */
+dh2_status dh2_matvec_stream(dh2_handle h, const void* X, void* Y, int nrhs, void* stream);
+
 /* dh2_matvec with per-phase timing, for benchmarks: runs the same kernels,
  * records HIP events on the handle's stream between the phases and waits for
  * them (this call synchronises).  phase_ms[7] receives milliseconds of:
@@ -141,6 +146,32 @@ dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, do
 
 /* Releases all device and host memory of the handle.  NULL is a no-op. */
 void dh2_free(dh2_handle h);
+
+/* ---------------------------------------------------------------------------
+ * Many products as one launch: a batch holds Y_i = Gtilde_i X_i for count
+ * distinct handles (problems of any sizes, one precision), recorded once into
+ * a HIP graph whose branches run the problems side by side (up to 8
+ * concurrent branches, problems dealt round-robin), and replayed by one graph
+ * launch.  Small problems, which fill a fraction of the GPU each, then share
+ * it.  Each product is exactly the one dh2_matvec computes.
+ *   handles  count distinct handles (a handle twice would race on its buffers)
+ *   X, Y     count device pointers each, laid out as for dh2_matvec; the
+ *            pointers are recorded: later runs read and write the same memory
+ *   nrhs     1 <= nrhs <= max_nrhs of every handle
+ *   stream   hipStream_t the graph is launched on; NULL = a stream owned by
+ *            the batch, and then dh2_batch_run waits for the products
+ *   out      receives the batch; *out is NULL on failure
+ * The handles must outlive the batch.  Errors: DH2_ERR_ARG (NULL or repeated
+ * handle, mixed precisions, nrhs out of range, count < 1), DH2_ERR_DEVICE
+ * (capture or instantiation failed). */
+typedef struct dh2_batch_s* dh2_batch;
+dh2_status dh2_batch_create(const dh2_handle* handles, const void* const* X, void* const* Y, int nrhs,
+                            int count, void* stream, dh2_batch* out);
+/* One graph launch of all products (returns without synchronising unless the
+ * batch owns its stream).  Errors: DH2_ERR_ARG (NULL), DH2_ERR_DEVICE. */
+dh2_status dh2_batch_run(dh2_batch b);
+/* Releases the graph and the batch's streams and events.  NULL is a no-op. */
+void dh2_batch_free(dh2_batch b);
 
 /* Message of the last failure on this thread ("" if none). */
 const char* dh2_last_error(void);

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -1621,51 +1622,54 @@ namespace {
 // ev[g] before group g (0 gather, 1 forward, 2 coupling, 3 backward, 4 near,
 // 5 leaf output, 6 scatter) and ev[7] at the end.
 template <typename R>
-void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
+void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st) {
   const int64_t n = h->plan.n;
   auto mark = [&](int g) {
-    if (ev) HIPCHK(hipEventRecord(ev[g], h->stream));
+    if (ev) HIPCHK(hipEventRecord(ev[g], st));
   };
   auto terms = [&](int g) {
     for (const auto& ph : h->mv_phases)
       if (ph.group == g && ph.out_end > ph.out_begin)
         launch_mv_terms<R>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
-                                nrhs, h->stream);
+                                nrhs, st);
   };
   // four or more right-hand sides: matrix-core block rows on row-major copies
   const bool mf = nrhs >= 4;
   mark(0);
-  launch_mv_permute<R>(X, h->Xp_d, h->perm_d, n, nrhs, 1, h->stream);
-  if (mf) launch_mv_transpose<R>(h->Xp_d, h->XT_d, n, nrhs, h->stream);
+  launch_mv_permute<R>(X, h->Xp_d, h->perm_d, n, nrhs, 1, st);
+  if (mf) launch_mv_transpose<R>(h->Xp_d, h->XT_d, n, nrhs, st);
   mark(1);
   terms(1);
-  if (mf) launch_mv_slot_transpose<R>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, h->stream);
+  if (mf) launch_mv_slot_transpose<R>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, st);
   mark(2);
   if (mf)
     launch_mv_rows_mfma<R>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d,
-                                nrhs, 1, h->stream);
+                                nrhs, 1, st);
   else
-    launch_mv_coupling<R>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, h->stream);
+    launch_mv_coupling<R>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, st);
   mark(3);
   terms(3);
   mark(4);
   if (mf)
     launch_mv_rows_mfma<R>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d,
-                                nrhs, 0, h->stream);
+                                nrhs, 0, st);
   else
     launch_mv_near<R>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
-                           h->stream, h->XT_d);
+                           st, h->XT_d);
   mark(5);
   terms(5);
   mark(6);
-  launch_mv_permute<R>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, h->stream);
+  launch_mv_permute<R>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, st);
   mark(7);
   HIPCHK(hipGetLastError());
 }
 
+void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st) {
+  if (h->precision != DH2_FP64) run_matvec_t<float>(h, X, Y, nrhs, ev, st);
+  else run_matvec_t<double>(h, X, Y, nrhs, ev, st);
+}
 void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
-  if (h->precision != DH2_FP64) run_matvec_t<float>(h, X, Y, nrhs, ev);
-  else run_matvec_t<double>(h, X, Y, nrhs, ev);
+  run_matvec(h, X, Y, nrhs, ev, h->stream);
 }
 }  // namespace
 }  // extern "C++"
@@ -1686,6 +1690,128 @@ dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs) {
   }
   return DH2_OK;
 }
+
+dh2_status dh2_matvec_stream(dh2_handle h, const void* X, void* Y, int nrhs, void* stream) {
+  if (!h || !X || !Y) {
+    g_err = "NULL handle or vector";
+    return DH2_ERR_ARG;
+  }
+  if (nrhs < 1 || nrhs > h->max_nrhs) {
+    g_err = "nrhs out of range [1, max_nrhs]";
+    return DH2_ERR_ARG;
+  }
+  try {
+    run_matvec(h, X, Y, nrhs, nullptr, (hipStream_t)stream);
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+  return DH2_OK;
+}
+
+struct dh2_batch_s {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~dh2_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipStream_t q : side) (void)hipStreamDestroy(q);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+dh2_status dh2_batch_create(const dh2_handle* handles, const void* const* X, void* const* Y, int nrhs,
+                            int count, void* stream, dh2_batch* out) {
+  g_err.clear();
+  if (!out) {
+    g_err = "out is NULL";
+    return DH2_ERR_ARG;
+  }
+  *out = nullptr;
+  if (!handles || !X || !Y || count < 1) {
+    g_err = "NULL array or count < 1";
+    return DH2_ERR_ARG;
+  }
+  {
+    std::set<const void*> seen;
+    for (int i = 0; i < count; ++i) {
+      const dh2_handle h = handles[i];
+      if (!h || !X[i] || !Y[i]) {
+        g_err = "NULL handle or vector in the batch";
+        return DH2_ERR_ARG;
+      }
+      if (!seen.insert(h).second) {
+        g_err = "a handle appears twice in the batch";
+        return DH2_ERR_ARG;
+      }
+      if (h->precision != handles[0]->precision) {
+        g_err = "mixed precisions in one batch";
+        return DH2_ERR_ARG;
+      }
+      if (nrhs < 1 || nrhs > h->max_nrhs) {
+        g_err = "nrhs out of range [1, max_nrhs] for a handle of the batch";
+        return DH2_ERR_ARG;
+      }
+    }
+  }
+  std::unique_ptr<dh2_batch_s> b(new dh2_batch_s());
+  bool capturing = false;
+  try {
+    b->stream = (hipStream_t)stream;
+    if (!b->stream) {
+      HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+      b->own_stream = true;
+    }
+    const int nside = std::min(count, 8);
+    b->side.resize(nside, nullptr);
+    for (auto& q : b->side) HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    b->events.resize(nside + 1, nullptr);
+    for (auto& e : b->events) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    capturing = true;
+    // fork: every branch waits for the work already on the stream
+    HIPCHK(hipEventRecord(b->events[nside], b->stream));
+    for (int q = 0; q < nside; ++q) HIPCHK(hipStreamWaitEvent(b->side[q], b->events[nside], 0));
+    for (int i = 0; i < count; ++i) run_matvec(handles[i], X[i], Y[i], nrhs, nullptr, b->side[i % nside]);
+    // join
+    for (int q = 0; q < nside; ++q) {
+      HIPCHK(hipEventRecord(b->events[q], b->side[q]));
+      HIPCHK(hipStreamWaitEvent(b->stream, b->events[q], 0));
+    }
+    capturing = false;
+    HIPCHK(hipStreamEndCapture(b->stream, &b->graph));
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  } catch (const Fail& f) {
+    if (capturing) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(b->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    return fail(f);
+  }
+  *out = b.release();
+  return DH2_OK;
+}
+
+dh2_status dh2_batch_run(dh2_batch b) {
+  if (!b) {
+    g_err = "NULL batch";
+    return DH2_ERR_ARG;
+  }
+  try {
+    HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    if (b->own_stream) HIPCHK(hipStreamSynchronize(b->stream));
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+  return DH2_OK;
+}
+
+void dh2_batch_free(dh2_batch b) { delete b; }
 
 dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, double* phase_ms,
                               double* near_bytes) {

@@ -23,7 +23,8 @@ INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col":
 
 EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_free", "dh2_last_error",
             "dh2_get_stats", "dh2_plan_create", "dh2_plan_get_sizes", "dh2_plan_export",
-            "dh2_plan_free", "dh2_inspect"]
+            "dh2_plan_free", "dh2_inspect", "dh2_batch_create", "dh2_batch_run", "dh2_batch_free",
+            "dh2_matvec_stream"]
 
 
 class Dh2Error(RuntimeError):
@@ -96,8 +97,14 @@ def load():
     lib.dh2_plan_free.argtypes = [P]
     lib.dh2_plan_free.restype = None
     lib.dh2_inspect.argtypes = [P, I32, I64, P, P, P]
+    lib.dh2_batch_create.argtypes = [P, P, P, I32, I32, P, P]
+    lib.dh2_matvec_stream.argtypes = [P, P, P, I32, P]
+    lib.dh2_batch_run.argtypes = [P]
+    lib.dh2_batch_free.argtypes = [P]
+    lib.dh2_batch_free.restype = None
     for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_get_stats", "dh2_plan_create",
-                 "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect"):
+                 "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect", "dh2_batch_create", "dh2_batch_run",
+                 "dh2_matvec_stream"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -170,6 +177,12 @@ class Handle:
         _check(lib.dh2_build_ex(ctypes.byref(g), kappa, order, eta, leafsize, tol,
                                 ctypes.byref(opt), ctypes.byref(self._h)))
 
+    def matvec_on(self, X, Y, stream):
+        """Handle.matvec enqueued on another stream than the handle's (the
+        products of a batch issued one after another, for comparison)."""
+        lib = load()
+        _check(lib.dh2_matvec_stream(self._h, X.data_ptr(), Y.data_ptr(), X.shape[0], stream))
+
     def matvec_ptr(self, x_ptr, y_ptr, nrhs):
         """Y = Gtilde X for raw device pointers (column-major n x nrhs complex)."""
         _check(load().dh2_matvec(self._h, x_ptr, y_ptr, nrhs))
@@ -216,6 +229,45 @@ class Handle:
         if getattr(self, "_h", None):
             load().dh2_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Y_i = Gtilde_i X_i for several handles as one graph launch (dh2_batch_*).
+    X and Y are lists of device tensors laid out as for Handle.matvec; their
+    memory is recorded, so later runs read and write the same tensors."""
+
+    def __init__(self, handles, X, Y, stream=None):
+        import torch
+        lib = load()
+        if not (len(handles) == len(X) == len(Y)) or not handles:
+            raise ValueError("handles, X and Y must be non-empty lists of one length")
+        nrhs = X[0].shape[0]
+        for h, x, y in zip(handles, X, Y):
+            want = torch.complex128 if h.precision == FP64 else torch.complex64
+            for A in (x, y):
+                if A.dtype != want or not A.is_contiguous() or A.dim() != 2 or A.shape != (nrhs, h.n):
+                    raise ValueError("X/Y must be contiguous %s tensors of shape (%d, n)" % (want, nrhs))
+        cnt = len(handles)
+        hs = (ctypes.c_void_p * cnt)(*[h._h.value for h in handles])
+        xs = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in X])
+        ys = (ctypes.c_void_p * cnt)(*[y.data_ptr() for y in Y])
+        self._keep = (list(handles), list(X), list(Y))
+        self._b = ctypes.c_void_p()
+        _check(lib.dh2_batch_create(hs, xs, ys, nrhs, cnt, stream, ctypes.byref(self._b)))
+
+    def run(self):
+        _check(load().dh2_batch_run(self._b))
+
+    def free(self):
+        if getattr(self, "_b", None):
+            load().dh2_batch_free(self._b)
+            self._b = None
 
     def __del__(self):
         try:

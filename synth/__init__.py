@@ -6,7 +6,7 @@ workload parameter sets.
 """
 from .meshes import sphere_octahedral, cube_surface, ellipsoid_octahedral
 from .rhs import complex_gaussian
-from .workloads import WORKLOADS, Workload, make_mesh
+from .workloads import WORKLOADS, Workload, make_mesh, batch_workloads
 
-__all__ = ["sphere_octahedral", "cube_surface", "ellipsoid_octahedral",
+__all__ = ["sphere_octahedral", "cube_surface", "ellipsoid_octahedral", "batch_workloads",
            "complex_gaussian", "WORKLOADS", "Workload", "make_mesh"]

@@ -58,3 +58,20 @@ WORKLOADS = {
     "cube768": Workload("cube768", "cube", 8, 4.0, 3, 16, 1e-6, eta=2.0),
     "cube1200dir": Workload("cube1200dir", "cube", 10, 4.0, 3, 16, 1e-6, eta=4.0, eta1=2.0),
 }
+
+
+def batch_workloads(count=64, seed=2024, n_lo=2048, n_hi=32768):
+    """Problems of the batching form: surfaces drawn from sphere, side-2 cube
+    and ellipsoid (axes 1:2:3), sizes n ~ U[n_lo, n_hi] rounded to the mesh
+    family (sphere / ellipsoid n = 8 q^2, cube n = 12 q^2), kappa ~ U[4, 24],
+    m = 4, leaf 32, tol 1e-5, eta 1, eta1 10."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        surface = ("sphere", "cube", "ellipsoid")[int(rng.integers(0, 3))]
+        n = float(rng.uniform(n_lo, n_hi))
+        q = max(1, int(round((n / (12.0 if surface == "cube" else 8.0)) ** 0.5)))
+        kappa = float(rng.uniform(4.0, 24.0))
+        out.append(Workload("batch%02d" % i, surface, q, round(kappa, 3), 4, 32, 1e-5))
+    return out

@@ -23,6 +23,17 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_batch_entry_points_reject_bad_arguments_without_gpu():
+    import ctypes
+    lib = dh2.load()
+    b = ctypes.c_void_p()
+    assert lib.dh2_batch_create(None, None, None, 1, 0, None, ctypes.byref(b)) == 1
+    assert b.value is None
+    assert lib.dh2_batch_create(None, None, None, 1, 1, None, None) == 1
+    assert lib.dh2_batch_run(None) == 1
+    lib.dh2_batch_free(None)
+
+
 def test_build_rejects_bad_arguments_without_gpu():
     V, T = synth.sphere_octahedral(2)
     bad = [dict(kappa=-1.0), dict(order=0), dict(eta=0.0), dict(leafsize=0), dict(tol=-1.0)]

@@ -1,0 +1,92 @@
+"""Batch of products as one graph launch (dh2_batch_*): problems of several
+sizes, surfaces and wave numbers recorded into one HIP graph and replayed.
+Every replay must reproduce the products of dh2_matvec bit for bit (the same
+kernels in the same order per problem), with eager work between replays, and
+one problem is checked against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.dh2 import OracleDH2
+from tests.gpu_common import say, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_batch_graph_replays_match_single_products(prec_name):
+    import torch
+    from paper_1809_04384_amd import dh2
+    prec = dh2.FP64 if prec_name == "fp64" else dh2.FP32
+    cdt = torch.complex128 if prec == dh2.FP64 else torch.complex64
+    # two parity workloads with admissible blocks (at these sizes the batching
+    # recipe's wave numbers leave only near fields) and three of the recipe
+    ws = [synth.WORKLOADS["dir512"], synth.WORKLOADS["cube768"]] + \
+        synth.batch_workloads(count=3, seed=7, n_lo=300, n_hi=2500)
+    nrhs = 6
+    hs, X, Ye, Yb, meshes = [], [], [], [], []
+    try:
+        for i, w in enumerate(ws):
+            V, T = synth.make_mesh(w)
+            meshes.append((V, T))
+            say("[gpu] batch: build %s %s n=%d kappa=%g (%s)" % (w.name, w.surface, len(T), w.kappa, prec_name))
+            hs.append(dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=prec,
+                                 max_nrhs=nrhs))
+            X.append(torch.from_numpy(synth.complex_gaussian(len(T), nrhs, seed=30 + i)).to("cuda:0").to(cdt))
+            Ye.append(torch.empty_like(X[-1]))
+            Yb.append(torch.empty_like(X[-1]))
+        for h, x, y in zip(hs, X, Ye):
+            h.matvec(x, y)
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        say("[gpu] batch: capture %d problems" % len(hs))
+        b = dh2.Batch(hs, X, Yb, stream=s.cuda_stream)
+        try:
+            for rep in range(3):
+                for y in Yb:
+                    y.zero_()
+                torch.cuda.synchronize()
+                with torch.cuda.stream(s):
+                    b.run()
+                s.synchronize()
+                for i in range(len(hs)):
+                    assert torch.equal(Yb[i], Ye[i]), (rep, i)
+                # eager work between replays
+                hs[0].matvec(X[0], Ye[0])
+                torch.cuda.synchronize()
+            say("[gpu] batch: 3 replays equal the single products")
+        finally:
+            b.free()
+        # a problem with a far field against the oracle
+        i0 = 0
+        w = ws[i0]
+        V, T = meshes[i0]
+        o = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1)
+        Xn = X[i0].cpu().numpy().astype(np.complex128)
+        err = rel(Yb[i0].cpu().numpy().astype(np.complex128), o.matvec(Xn.T).T)
+        say("[gpu] batch: %s vs oracle rel err %.3e" % (w.name, err))
+        assert err <= (1e-10 if prec == dh2.FP64 else 1e-4)
+    finally:
+        for h in hs:
+            h.free()
+
+
+def test_batch_rejects_repeated_handle_and_mixed_precision():
+    import torch
+    from paper_1809_04384_amd import dh2
+    V, T = synth.sphere_octahedral(8)
+    h64 = dh2.Handle(V, T, 4.0, 3, 1.0, 32, 1e-6)
+    h32 = dh2.Handle(V, T, 4.0, 3, 1.0, 32, 1e-6, precision=dh2.FP32)
+    try:
+        x = torch.zeros((2, len(T)), dtype=torch.complex128, device="cuda:0")
+        y = torch.empty_like(x)
+        with pytest.raises(dh2.Dh2Error) as e:
+            dh2.Batch([h64, h64], [x, x], [y, y])
+        assert e.value.status == 1
+        x32 = torch.zeros((2, len(T)), dtype=torch.complex64, device="cuda:0")
+        with pytest.raises(dh2.Dh2Error) as e:
+            dh2.Batch([h64, h32], [x, x32], [y, torch.empty_like(x32)])
+        assert e.value.status == 1
+    finally:
+        h64.free()
+        h32.free()
