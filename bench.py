@@ -56,12 +56,20 @@ MATVEC_SRCS = [os.path.join(ROOT, "paper_1809_04384_amd", "csrc", f) for f in ("
 
 
 def source_sha256():
-    """Hash of the matvec kernels and of the library source that schedules
-    their launches (row lists and their order)."""
+    """Hash of the matvec kernels (matvec.hip) and of the parts of api.cpp that
+    build their row lists and issue their launches (the text between the
+    "matvec schedule (begin)" and "(end)" markers)."""
     import hashlib
     h = hashlib.sha256()
-    for f in MATVEC_SRCS:
-        h.update(open(f, "rb").read())
+    h.update(open(MATVEC_SRCS[0], "rb").read())
+    keep = False
+    for line in open(MATVEC_SRCS[1], "rb"):
+        if b"matvec schedule (begin)" in line:
+            keep = True
+        if keep:
+            h.update(line)
+        if b"matvec schedule (end)" in line:
+            keep = False
     return h.hexdigest()
 
 

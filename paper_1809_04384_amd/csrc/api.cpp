@@ -227,6 +227,7 @@ struct dh2_problem {
 
 namespace {
 
+// ---- matvec schedule (begin) ----
 // Order of the rows of a launch with one workgroup per row (k_mv_rows_mfma maps
 // workgroup b to list entry xcd q + min(xcd, rm) + (b >> 3), xcd = b & 7, with
 // n = 8 q + rm): the rows, longest first, are dealt to the 8 XCDs in snake
@@ -250,6 +251,7 @@ std::vector<int64_t> xcd_balanced_order(const std::vector<double>& work) {
   for (int x = 0; x < 8; ++x) out.insert(out.end(), share[x].begin(), share[x].end());
   return out;
 }
+// ---- matvec schedule (end) ----
 
 typedef z64 C64;
 
@@ -1080,6 +1082,7 @@ struct Builder {
   // ------------------------------------------------------------------
   // matvec schedule: phases of MvOut lists (see matvec.hip).  Pointers are
   // formed in elements of the handle's type (complex128 or complex64).
+  // ---- matvec schedule (begin) ----
   void matvec_schedule() {
     const int nr = h.max_nrhs;
     const int64_t n = p.n;
@@ -1290,6 +1293,7 @@ struct Builder {
     h.mv_outs_d = h.upload(outs);
     h.mv_terms_d = h.upload(terms);
   }
+  // ---- matvec schedule (end) ----
 };
 
 void validate(const dh2_geometry* g, double kappa, int order, double eta, int leafsize, double tol,
@@ -1621,6 +1625,7 @@ namespace {
 // Runs the matvec phases on the handle's stream; with ev != NULL records
 // ev[g] before group g (0 gather, 1 forward, 2 coupling, 3 backward, 4 near,
 // 5 leaf output, 6 scatter) and ev[7] at the end.
+// ---- matvec schedule (begin) ----
 template <typename R>
 void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st) {
   const int64_t n = h->plan.n;
@@ -1668,6 +1673,7 @@ void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev
   if (h->precision != DH2_FP64) run_matvec_t<float>(h, X, Y, nrhs, ev, st);
   else run_matvec_t<double>(h, X, Y, nrhs, ev, st);
 }
+// ---- matvec schedule (end) ----
 void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
   run_matvec(h, X, Y, nrhs, ev, h->stream);
 }
