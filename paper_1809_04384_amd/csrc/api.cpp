@@ -168,13 +168,12 @@ struct dh2_problem {
   MvOut* mv_outs_d = nullptr; MvTerm* mv_terms_d = nullptr;
   struct Phase { int64_t out_begin, out_end; int group; };
   std::vector<Phase> mv_phases;     // groups: 1 forward, 2 coupling, 3 backward, 5 leaf output
-  CoupRow* coup_rows_d = nullptr;
-  CoupBlk* coup_blks_d = nullptr;
+
   int64_t n_coup_rows = 0;
-  NearRow* near_rows_d = nullptr;
+
   NearSeg* near_segs_d = nullptr;
   int64_t n_near_rows = 0;
-  // matrix-core forms (four or more right-hand sides)
+  // matrix-core block rows (every right-hand-side count)
   MfRow* near_mf_rows_d = nullptr;      // one per leaf, segments near_segs_d
   MfRow* coup_mf_rows_d = nullptr;      // one per row slot, segments coup_mf_segs_d
   NearSeg* coup_mf_segs_d = nullptr;
@@ -251,6 +250,7 @@ std::vector<int64_t> xcd_balanced_order(const std::vector<double>& work) {
   for (int x = 0; x < 8; ++x) out.insert(out.end(), share[x].begin(), share[x].end());
   return out;
 }
+
 // ---- matvec schedule (end) ----
 
 typedef z64 C64;
@@ -1159,33 +1159,23 @@ struct Builder {
     h.xhT_d = valloc(xrows * nr);
     h.zero16_d = h.alloc<C64>(16);
     HIPCHK(hipMemsetAsync(h.zero16_d, 0, 16 * sizeof(C64), h.stream));
-    std::vector<CoupRow> crows;
-    std::vector<CoupBlk> cblks;
     std::vector<MfRow> mrows;
     std::vector<NearSeg> msegs;
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_row[q] > 0) {
         const int kq = h.rank_row[q];
-        CoupRow r{at(yh, yo[q]), kq, (int32_t)cblks.size(), 0, 0};
         MfRow mr{at(yh, yo[q]), kq, kq, (int32_t)msegs.size(), 0};
         for (int64_t e = p.row_ptr[q]; e < p.row_ptr[q + 1]; ++e) {
           const int64_t b = p.row_blk[e];
           const AdmBlock& a = p.adm[b];
           const int64_t qs = p.slot_of(a.s, a.c);
           const int ks = h.rank_col[qs];
-          if (ks > 0) {
-            cblks.push_back({at(h.St_d, h.St_off[b]), at(xh, xo[qs]), ks, 0});
-            msegs.push_back({at(h.St_d, h.St_off[b]), xro[qs], kq, ks});
-          }
+          if (ks > 0) msegs.push_back({at(h.St_d, h.St_off[b]), xro[qs], kq, ks});
         }
-        r.blk_end = (int32_t)cblks.size();
         mr.seg_end = (int32_t)msegs.size();
-        crows.push_back(r);
         mrows.push_back(mr);
       }
-    h.coup_rows_d = h.upload(crows);
-    h.coup_blks_d = h.upload(cblks);
-    h.n_coup_rows = (int64_t)crows.size();
+    h.n_coup_rows = (int64_t)mrows.size();
     {
       std::vector<double> work(mrows.size());
       for (size_t i = 0; i < mrows.size(); ++i) {
@@ -1255,7 +1245,6 @@ struct Builder {
       r.seg_end = (int32_t)nsegs.size();
       nrows.push_back(r);
     }
-    h.near_rows_d = h.upload(nrows);
     h.near_segs_d = h.upload(nsegs);
     h.n_near_rows = (int64_t)nrows.size();
     {
@@ -1638,29 +1627,21 @@ void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* 
         launch_mv_terms<R>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
                                 nrhs, st);
   };
-  // four or more right-hand sides: matrix-core block rows on row-major copies
-  const bool mf = nrhs >= 4;
+  // every right-hand-side count runs the matrix-core block rows on row-major
+  // copies (columns past nrhs read zeros)
   mark(0);
   launch_mv_permute<R>(X, h->Xp_d, h->perm_d, n, nrhs, 1, st);
-  if (mf) launch_mv_transpose<R>(h->Xp_d, h->XT_d, n, nrhs, st);
+  launch_mv_transpose<R>(h->Xp_d, h->XT_d, n, nrhs, st);
   mark(1);
   terms(1);
-  if (mf) launch_mv_slot_transpose<R>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, st);
+  launch_mv_slot_transpose<R>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, st);
   mark(2);
-  if (mf)
-    launch_mv_rows_mfma<R>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d,
-                                nrhs, 1, st);
-  else
-    launch_mv_coupling<R>(h->coup_rows_d, h->n_coup_rows, h->coup_blks_d, nrhs, st);
+  launch_mv_rows_mfma<R>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d, nrhs, 1,
+                         st);
   mark(3);
   terms(3);
   mark(4);
-  if (mf)
-    launch_mv_rows_mfma<R>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d,
-                                nrhs, 0, st);
-  else
-    launch_mv_near<R>(h->near_rows_d, h->n_near_rows, h->near_segs_d, h->Xp_d, h->Yp_d, n, nrhs,
-                           st, h->XT_d);
+  launch_mv_rows_mfma<R>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d, nrhs, 0, st);
   mark(5);
   terms(5);
   mark(6);

@@ -36,175 +36,7 @@ __global__ void __launch_bounds__(256) k_mv_terms(const MvOut* __restrict__ outs
   }
 }
 
-// Near-field product (the dense inadmissible leaves, Definition of DH^2
-// matrices): a workgroup per leaf row cluster, lane = row, the four waves take
-// interleaved columns; every matrix entry is read once, coalesced along the
-// column, and applied to all right-hand sides held in registers.  The wave
-// partial sums are combined through LDS; Y rows are written (not accumulated).
-template <typename R, int NR>
-__global__ void __launch_bounds__(256) k_mv_near(const NearRow* __restrict__ rows,
-                                                 const NearSeg* __restrict__ segs,
-                                                 const cpx<R>* __restrict__ X, cpx<R>* __restrict__ Y,
-                                                 int64_t n, int nrhs) {
-  const NearRow rw = rows[blockIdx.x];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ cpx<R> red[3][64][NR];
-  for (int r0 = 0; r0 < rw.nr; r0 += 64) {
-    const int i = r0 + lane;
-    const bool act = i < rw.nr;
-    for (int c0 = 0; c0 < nrhs; c0 += NR) {
-      const int nc = min(NR, nrhs - c0);
-      cpx<R> acc[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = cpx<R>{0, 0};
-      for (int sg = rw.seg_begin; sg < rw.seg_end; ++sg) {
-        const NearSeg s = segs[sg];
-        const cpx<R>* A = (const cpx<R>*)s.A + i;
-        const cpx<R>* x = X + s.x0 + (int64_t)c0 * n;
-        int j = wave;
-        for (; j + 12 < s.ncols; j += 16) {
-          cpx<R> a[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            a[u] = act ? A[(int64_t)(j + 4 * u) * s.lda] : cpx<R>{0, 0};
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-              if (r < nc) cfma(acc[r], a[u], x[j + 4 * u + (int64_t)r * n]);
-        }
-        for (; j < s.ncols; j += 4) {
-          const cpx<R> a = act ? A[(int64_t)j * s.lda] : cpx<R>{0, 0};
-#pragma unroll
-          for (int r = 0; r < NR; ++r)
-            if (r < nc) cfma(acc[r], a, x[j + (int64_t)r * n]);
-        }
-      }
-      if (wave > 0)
-#pragma unroll
-        for (int r = 0; r < NR; ++r) red[wave - 1][lane][r] = acc[r];
-      __syncthreads();
-      if (wave == 0 && act) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          if (r >= nc) break;
-          const cpx<R> v = acc[r] + red[0][lane][r] + red[1][lane][r] + red[2][lane][r];
-          Y[rw.row0 + i + (int64_t)(c0 + r) * n] = v;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Multi right-hand-side variant: X is given row-major (all right-hand sides of a
-// row contiguous, XT[j * nrhs + r]); tiles of 64 rows of X are staged in LDS
-// once per workgroup and broadcast to the waves, so each matrix entry costs
-// one coalesced load plus NR complex FMAs from registers.
-template <typename R, int NR>
-__global__ void __launch_bounds__(256) k_mv_near_multi(const NearRow* __restrict__ rows,
-                                                       const NearSeg* __restrict__ segs,
-                                                       const cpx<R>* __restrict__ XT,
-                                                       cpx<R>* __restrict__ Y, int64_t n, int nrhs) {
-  const NearRow rw = rows[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  constexpr int TE = (64 * NR + 255) / 256;      // tile entries per thread
-  __shared__ cpx<R> xs[64][NR];
-  __shared__ cpx<R> red[3][64][NR];
-  // tiles of (segment, 64 columns) are visited in order; the next tile's X rows
-  // are fetched into registers while the current one is consumed from LDS
-  for (int r0 = 0; r0 < rw.nr; r0 += 64) {
-    const int i = r0 + lane;
-    const bool act = i < rw.nr;
-    for (int c0 = 0; c0 < nrhs; c0 += NR) {
-      cpx<R> acc[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = cpx<R>{0, 0};
-      cpx<R> nxt[TE];
-      int sg = rw.seg_begin, jt = 0;
-      {
-        const int fsg = sg, fjt = jt;
-        const bool fok = fsg < rw.seg_end;
-        const NearSeg fs = segs[fok ? fsg : rw.seg_begin];
-        const int ftile = fok ? min(64, fs.ncols - fjt) : 0;
-#pragma unroll
-        for (int u = 0; u < TE; ++u) {
-          const int e = tid + 256 * u;
-          const int j = e / NR, r = e % NR;
-          cpx<R> v{0, 0};
-          if (e < 64 * NR && j < ftile && c0 + r < nrhs) v = XT[(fs.x0 + fjt + j) * nrhs + c0 + r];
-          nxt[u] = v;
-        }
-      }
-      while (sg < rw.seg_end) {
-        const NearSeg s = segs[sg];
-        const int tile = min(64, s.ncols - jt);
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < TE; ++u) {
-          const int e = tid + 256 * u;
-          if (e < 64 * NR) xs[e / NR][e % NR] = nxt[u];
-        }
-        __syncthreads();
-        // advance and prefetch the following tile
-        int sg2 = sg, jt2 = jt + 64;
-        if (jt2 >= s.ncols) {
-          ++sg2;
-          jt2 = 0;
-        }
-        {
-        const int fsg = sg2, fjt = jt2;
-        const bool fok = fsg < rw.seg_end;
-        const NearSeg fs = segs[fok ? fsg : rw.seg_begin];
-        const int ftile = fok ? min(64, fs.ncols - fjt) : 0;
-#pragma unroll
-        for (int u = 0; u < TE; ++u) {
-          const int e = tid + 256 * u;
-          const int j = e / NR, r = e % NR;
-          cpx<R> v{0, 0};
-          if (e < 64 * NR && j < ftile && c0 + r < nrhs) v = XT[(fs.x0 + fjt + j) * nrhs + c0 + r];
-          nxt[u] = v;
-        }
-      }
-        const cpx<R>* A = (const cpx<R>*)s.A + i + (int64_t)jt * s.lda;
-        int jj = wave;
-        for (; jj + 12 < tile; jj += 16) {
-          cpx<R> a[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) a[u] = act ? A[(int64_t)(jj + 4 * u) * s.lda] : cpx<R>{0, 0};
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int r = 0; r < NR; ++r) cfma(acc[r], a[u], xs[jj + 4 * u][r]);
-        }
-        for (; jj < tile; jj += 4) {
-          const cpx<R> a = act ? A[(int64_t)jj * s.lda] : cpx<R>{0, 0};
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[r], a, xs[jj][r]);
-        }
-        sg = sg2;
-        jt = jt2;
-      }
-      if (wave > 0)
-#pragma unroll
-        for (int r = 0; r < NR; ++r) red[wave - 1][lane][r] = acc[r];
-      __syncthreads();
-      if (wave == 0 && act) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          if (c0 + r < nrhs) {
-            const cpx<R> v = acc[r] + red[0][lane][r] + red[1][lane][r] + red[2][lane][r];
-            Y[rw.row0 + i + (int64_t)(c0 + r) * n] = v;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Matrix-core block-row product for four or more right-hand sides, used by the
+// Matrix-core block-row product (any number of right-hand sides), used by the
 // near field (a row = a leaf cluster, its segments = the inadmissible blocks
 // restricted to its rows) and by the coupling phase (a row = a row slot (t, c),
 // its segments = the recompressed couplings Stilde_b of its admissible blocks).
@@ -433,86 +265,6 @@ void launch_mv_slot_transpose(const SlotT* d, int64_t cnt, void* dst, int nrhs, 
 template void launch_mv_slot_transpose<double>(const SlotT*, int64_t, void*, int, hipStream_t);
 template void launch_mv_slot_transpose<float>(const SlotT*, int64_t, void*, int, hipStream_t);
 
-// Coupling phase y_tc = sum_b Stilde_b x_sc (the admissible leaves of eq. (vsw)
-// in the new bases): a workgroup per row slot; its eight half-waves take
-// interleaved blocks, lane = row of Stilde_b (coalesced along the column), all
-// right-hand sides in registers, partial sums combined through LDS.
-template <typename R, int NR, int ROWS>
-__global__ void __launch_bounds__(256) k_mv_coupling(const CoupRow* __restrict__ rows,
-                                                     const CoupBlk* __restrict__ blks, int nrhs) {
-  // lane = (group g of 64 / NR lanes, right-hand side r); the groups of the
-  // workgroup take interleaved blocks; every lane accumulates a whole column of
-  // y_tc (up to ROWS rows per pass) for its right-hand side, the entries of
-  // Stilde_b are shared by the lanes of a group
-  constexpr int G = 256 / NR;                    // groups per workgroup
-  const CoupRow rw = rows[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int r = tid % NR, g = tid / NR;
-  const int lane = tid & 63, wave = tid >> 6;
-  __shared__ cpx<R> red[4][ROWS][NR];
-  cpx<R>* y = (cpx<R>*)rw.y;
-  for (int rc = 0; rc < rw.kq; rc += ROWS) {
-    const int rows_here = min(ROWS, rw.kq - rc);
-    for (int c0 = 0; c0 < nrhs; c0 += NR) {
-      const bool ract = c0 + r < nrhs;
-      cpx<R> acc[ROWS];
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) acc[i] = cpx<R>{0, 0};
-      for (int bb = rw.blk_begin + g; bb < rw.blk_end; bb += G) {
-        const CoupBlk b = blks[bb];
-        const cpx<R>* S = (const cpx<R>*)b.S + rc;
-        const cpx<R>* x = (const cpx<R>*)b.x + (int64_t)(c0 + r) * b.ks;
-        for (int j = 0; j < b.ks; ++j) {
-          const cpx<R> xv = ract ? x[j] : cpx<R>{0, 0};
-          const cpx<R>* Sj = S + (int64_t)j * rw.kq;
-#pragma unroll
-          for (int i = 0; i < ROWS; ++i)
-            if (i < rows_here) cfma(acc[i], Sj[i], xv);
-        }
-      }
-      // reduce over the groups of a wave (lanes with equal r), then over waves
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) {
-        for (int off = NR; off < 64; off <<= 1) {
-          acc[i].x += __shfl_xor(acc[i].x, off);
-          acc[i].y += __shfl_xor(acc[i].y, off);
-        }
-      }
-      if (lane < NR)
-#pragma unroll
-        for (int i = 0; i < ROWS; ++i) red[wave][i][r] = acc[i];
-      __syncthreads();
-      for (int e = tid; e < rows_here * NR; e += 256) {
-        const int i = e / NR, rr = e % NR;
-        if (c0 + rr < nrhs) {
-          const cpx<R> v = red[0][i][rr] + red[1][i][rr] + red[2][i][rr] + red[3][i][rr];
-          y[rc + i + (int64_t)(c0 + rr) * rw.kq] = v;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-template <typename R>
-void launch_mv_coupling(const CoupRow* rows, int64_t nrows, const CoupBlk* blks, int nrhs,
-                        hipStream_t st) {
-  if (nrows <= 0) return;
-  const dim3 g((unsigned)nrows), b(256);
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_mv_coupling<R, 1, sizeof(R) == 8 ? 16 : 32>), g, b, 0, st, rows, blks, nrhs);
-  else if (nrhs == 2)
-    hipLaunchKernelGGL((k_mv_coupling<R, 2, sizeof(R) == 8 ? 16 : 32>), g, b, 0, st, rows, blks, nrhs);
-  else if (nrhs <= 4)
-    hipLaunchKernelGGL((k_mv_coupling<R, 4, sizeof(R) == 8 ? 16 : 32>), g, b, 0, st, rows, blks, nrhs);
-  else if (nrhs <= 8)
-    hipLaunchKernelGGL((k_mv_coupling<R, 8, sizeof(R) == 8 ? 16 : 32>), g, b, 0, st, rows, blks, nrhs);
-  else
-    hipLaunchKernelGGL((k_mv_coupling<R, 16, sizeof(R) == 8 ? 16 : 32>), g, b, 0, st, rows, blks, nrhs);
-}
-template void launch_mv_coupling<double>(const CoupRow*, int64_t, const CoupBlk*, int, hipStream_t);
-template void launch_mv_coupling<float>(const CoupRow*, int64_t, const CoupBlk*, int, hipStream_t);
-
 // row-major copy of the gathered X: XT[p * nrhs + r] = Xp[p + r n]
 template <typename R>
 __global__ void k_mv_transpose(const cpx<R>* __restrict__ Xp, cpx<R>* __restrict__ XT, int64_t n,
@@ -532,32 +284,6 @@ void launch_mv_transpose(const void* X, void* XT, int64_t n, int nrhs, hipStream
 }
 template void launch_mv_transpose<double>(const void*, void*, int64_t, int, hipStream_t);
 template void launch_mv_transpose<float>(const void*, void*, int64_t, int, hipStream_t);
-
-template <typename R>
-void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
-                    int64_t n, int nrhs, hipStream_t st, void* XT) {
-  if (nrows <= 0) return;
-  const dim3 g((unsigned)nrows), b(256);
-  if (nrhs == 1) {
-    hipLaunchKernelGGL((k_mv_near<R, 1>), g, b, 0, st, rows, segs, (const cpx<R>*)X, (cpx<R>*)Y, n, nrhs);
-    return;
-  }
-  const int64_t tot = n * nrhs;
-  hipLaunchKernelGGL(k_mv_transpose<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                     (const cpx<R>*)X, (cpx<R>*)XT, n, nrhs);
-  if (nrhs == 2)
-    hipLaunchKernelGGL((k_mv_near_multi<R, 2>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
-  else if (nrhs <= 4)
-    hipLaunchKernelGGL((k_mv_near_multi<R, 4>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
-  else if (nrhs <= 8)
-    hipLaunchKernelGGL((k_mv_near_multi<R, 8>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
-  else
-    hipLaunchKernelGGL((k_mv_near_multi<R, 16>), g, b, 0, st, rows, segs, (const cpx<R>*)XT, (cpx<R>*)Y, n, nrhs);
-}
-template void launch_mv_near<double>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
-                                     int64_t, int, hipStream_t, void*);
-template void launch_mv_near<float>(const NearRow*, int64_t, const NearSeg*, const void*, void*,
-                                    int64_t, int, hipStream_t, void*);
 
 // gather: dst[p + r n] = src[perm[p] + r n];  scatter: dst[perm[p] + r n] = src[p + r n]
 template <typename R>

@@ -39,29 +39,6 @@ struct NearSeg {
   int32_t lda, ncols;
 };
 
-template <typename R>
-void launch_mv_near(const NearRow* rows, int64_t nrows, const NearSeg* segs, const void* X, void* Y,
-                    int64_t n, int nrhs, hipStream_t st, void* XT);
-
-// Coupling: y_q (kq x nrhs, leading dimension kq) = sum over the admissible
-// blocks of the row slot of Stilde_b (kq x ks) x_s (ks x nrhs, leading dimension ks).
-struct CoupRow {
-  void* y;
-  int32_t kq;
-  int32_t blk_begin, blk_end;
-  int32_t pad;
-};
-struct CoupBlk {
-  const void* S;
-  const void* x;
-  int32_t ks;
-  int32_t pad;
-};
-
-template <typename R>
-void launch_mv_coupling(const CoupRow* rows, int64_t nrows, const CoupBlk* blks, int nrhs,
-                        hipStream_t st);
-
 // Block row of the matrix-core product: y (nr x nrhs, leading dimension ldy) =
 // sum over the segments [seg_begin, seg_end) of A (nr x ncols, leading
 // dimension lda) times rows [x0, x0 + ncols) of a row-major right-hand side

@@ -52,10 +52,9 @@ def test_matvec_fp64_matches_oracle(name):
 
 @pytest.mark.parametrize("name", ["sphere2k", "dir2k"])
 def test_matvec_rhs_counts(name):
-    """Every right-hand-side count takes its own near-field kernel (1: one
-    lane per row; 2: LDS-staged X tile; 4 and more: matrix cores in chunks of
-    16, 20 = one full chunk plus a ragged one); each column must match the
-    oracle."""
+    """Right-hand-side counts below, at and above one 16-wide matrix-core tile
+    (1 and 2: one ragged tile; 16: one full tile; 20: one full tile plus a
+    ragged one); each column must match the oracle."""
     from paper_1809_04384_amd import dh2
     o = oracle_for(name)
     w = synth.WORKLOADS[name]
