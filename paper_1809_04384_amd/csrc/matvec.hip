@@ -88,23 +88,27 @@ __device__ __forceinline__ cpx<R> gload(const cpx<R>* p) {
 // One pass of a block row: rows [r0, r0 + nr) (NT = ceil(nr / 16) row tiles)
 // and right-hand sides [c0, c0 + 16), over the T steps of this wave; the wave
 // partial sums are added into red[rhs][row] (one wave after the other).
-template <typename R, int KU, int S, int NT>
+template <typename R, int KU, int S, int NT, int NC>
 __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restrict__ segs,
                                         const cpx<R>* __restrict__ XT, const cpx<R>* __restrict__ zero16,
                                         int nrhs, int wave, int T, int r0, int nr, int c0,
-                                        cpx<R> (&red)[16][65]) {
+                                        cpx<R> (&red)[NC][16][65]) {
   typedef typename Mfma<R>::acc_t acc_t;
   constexpr int SW = 4 * KU;
   const int lane = threadIdx.x & 63;
   const int kc = lane >> 4, rr = lane & 15;
-  const bool bact = c0 + rr < nrhs;
-  acc_t t1[NT], t2[NT], t3[NT];
+  bool bact[NC];
 #pragma unroll
-  for (int rt = 0; rt < NT; ++rt)
+  for (int ch = 0; ch < NC; ++ch) bact[ch] = c0 + 16 * ch + rr < nrhs;
+  acc_t t1[NC][NT], t2[NC][NT], t3[NC][NT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) t1[rt][e] = t2[rt][e] = t3[rt][e] = R(0);
+  for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t1[ch][rt][e] = t2[ch][rt][e] = t3[ch][rt][e] = R(0);
   if (T > 0) {
-    cpx<R> a[S][KU][NT], x[S][KU];
+    cpx<R> a[S][KU][NT], x[S][KU][NC];
     // fetch position: segment fsg (descriptor fs), first column fj0.  Past the
     // last segment fs keeps a valid address with no columns, so every load
     // stays in bounds and the stage is zero.
@@ -114,7 +118,7 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
     // read row nr - 1 (those outputs are dropped), columns past the segment
     // read its last column, and their right-hand side comes from zero16, so
     // they add nothing.
-    auto fetch = [&](cpx<R> (&fa)[KU][NT], cpx<R> (&fx)[KU]) {
+    auto fetch = [&](cpx<R> (&fa)[KU][NT], cpx<R> (&fx)[KU][NC]) {
       const cpx<R>* A = (const cpx<R>*)fs.A + r0;
       const cpx<R>* xb = XT + fs.x0 * nrhs + c0 + rr;
       const int jl = max(fs.ncols - 1, 0);
@@ -122,8 +126,11 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
       for (int u = 0; u < KU; ++u) {
         const int j = fj0 + 4 * u + kc;
         const int jc = min(j, jl);
-        const cpx<R>* xp = (j < fs.ncols && bact) ? xb + (int64_t)j * nrhs : zero16 + rr;
-        fx[u] = gload(xp);
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) {
+          const cpx<R>* xp = (j < fs.ncols && bact[ch]) ? xb + (int64_t)j * nrhs + 16 * ch : zero16 + rr;
+          fx[u][ch] = gload(xp);
+        }
 #pragma unroll
         for (int rt = 0; rt < NT; ++rt) fa[u][rt] = gload(A + min(rt * 16 + rr, nr - 1) + (int64_t)jc * fs.lda);
       }
@@ -148,32 +155,36 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
         fetch(a[(st + S - 1) % S], x[(st + S - 1) % S]);
         advance();
 #pragma unroll
-        for (int u = 0; u < KU; ++u) {
-          const cpx<R> xv = x[st][u];
-          const R b1 = xv.x, b2 = xv.y - xv.x, b3 = xv.x + xv.y;
+        for (int u = 0; u < KU; ++u)
 #pragma unroll
-          for (int rt = 0; rt < NT; ++rt) {
-            const cpx<R> av = a[st][u][rt];
-            t1[rt] = Mfma<R>::mac(av.x + av.y, b1, t1[rt]);
-            t2[rt] = Mfma<R>::mac(av.x, b2, t2[rt]);
-            t3[rt] = Mfma<R>::mac(av.y, b3, t3[rt]);
+          for (int ch = 0; ch < NC; ++ch) {
+            const cpx<R> xv = x[st][u][ch];
+            const R b1 = xv.x, b2 = xv.y - xv.x, b3 = xv.x + xv.y;
+#pragma unroll
+            for (int rt = 0; rt < NT; ++rt) {
+              const cpx<R> av = a[st][u][rt];
+              t1[ch][rt] = Mfma<R>::mac(av.x + av.y, b1, t1[ch][rt]);
+              t2[ch][rt] = Mfma<R>::mac(av.x, b2, t2[ch][rt]);
+              t3[ch][rt] = Mfma<R>::mac(av.y, b3, t3[ch][rt]);
+            }
           }
-        }
       }
     }
   }
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int rt = 0; rt < NT; ++rt) {
+      for (int ch = 0; ch < NC; ++ch)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = rt * 16 + Mfma<R>::row(lane, e);
-          const cpx<R> v{t1[rt][e] - t3[rt][e], t1[rt][e] + t2[rt][e]};
-          if (w == 0) red[rr][row] = v;
-          else red[rr][row] = red[rr][row] + v;
+        for (int rt = 0; rt < NT; ++rt) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int row = rt * 16 + Mfma<R>::row(lane, e);
+            const cpx<R> v{t1[ch][rt][e] - t3[ch][rt][e], t1[ch][rt][e] + t2[ch][rt][e]};
+            if (w == 0) red[ch][rr][row] = v;
+            else red[ch][rr][row] = red[ch][rr][row] + v;
+          }
         }
-      }
     }
     __syncthreads();
   }
@@ -184,7 +195,7 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
 #endif
 // ROLE only names the instantiation (0 near field, 1 coupling) so that the two
 // uses are told apart in kernel traces.
-template <typename R, int KU, int S, int ROLE>
+template <typename R, int KU, int S, int ROLE, int NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF_WPE))) k_mv_rows_mfma(const MfRow* __restrict__ rows,
                                                       const NearSeg* __restrict__ segs,
                                                       const cpx<R>* __restrict__ XT,
@@ -200,21 +211,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF
   cpx<R>* __restrict__ Y = (cpx<R>*)rw.y;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  __shared__ cpx<R> red[16][65];
+  __shared__ cpx<R> red[NC][16][65];
   // steps of this wave: its segments are seg_begin + wave + 4 i
   int T = 0;
   for (int sg = rw.seg_begin + wave; sg < rw.seg_end; sg += 4) T += (segs[sg].ncols + SW - 1) / SW;
   for (int r0 = 0; r0 < rw.nr; r0 += 64) {
     const int nr = min(64, rw.nr - r0);
     const int ntile = (nr + 15) >> 4;
-    for (int c0 = 0; c0 < nrhs; c0 += 16) {
-      if (ntile == 1) mf_pass<R, KU, S, 1>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
-      else if (ntile == 2) mf_pass<R, KU, S, 2>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
-      else if (ntile == 3) mf_pass<R, KU, S, 3>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
-      else mf_pass<R, KU, S, 4>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
-      for (int e = tid; e < 16 * 64; e += 256) {
-        const int row = e & 63, r = e >> 6;
-        if (row < nr && c0 + r < nrhs) Y[r0 + row + (int64_t)(c0 + r) * rw.ldy] = red[r][row];
+    for (int c0 = 0; c0 < nrhs; c0 += 16 * NC) {
+      if (ntile == 1) mf_pass<R, KU, S, 1, NC>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      else if (ntile == 2) mf_pass<R, KU, S, 2, NC>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      else if (ntile == 3) mf_pass<R, KU, S, 3, NC>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      else mf_pass<R, KU, S, 4, NC>(rw, segs, XT, zero16, nrhs, wave, T, r0, nr, c0, red);
+      for (int e = tid; e < NC * 16 * 64; e += 256) {
+        const int row = e & 63, r = (e >> 6) & 15, ch = e >> 10;
+        const int c = c0 + 16 * ch + r;
+        if (row < nr && c < nrhs) Y[r0 + row + (int64_t)c * rw.ldy] = red[ch][r][row];
       }
       __syncthreads();
     }
@@ -232,12 +244,29 @@ template <typename R>
 void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT,
                          const void* zero16, int nrhs, int role, hipStream_t st) {
   if (nrows <= 0) return;
+  // FP32 with more than 16 right-hand sides: two 16-wide chunks per pass, so
+  // the matrix is streamed once per 32 right-hand sides (FP64 accumulators
+  // for two chunks would not fit the registers of two waves per SIMD)
+  const dim3 g((unsigned)nrows), b(256);
+  const cpx<R>* xt = (const cpx<R>*)XT;
+  const cpx<R>* z = (const cpx<R>*)zero16;
+  if constexpr (sizeof(R) == 4) {
+    if (nrhs > 16) {
+      if (role == 0)
+        hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0, 2>), g, b, 0, st, rows, segs, xt, z, nrhs,
+                           (int)nrows);
+      else
+        hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1, 2>), g, b, 0, st, rows, segs, xt, z, nrhs,
+                           (int)nrows);
+      return;
+    }
+  }
   if (role == 0)
-    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0>), dim3((unsigned)nrows), dim3(256), 0, st,
-                       rows, segs, (const cpx<R>*)XT, (const cpx<R>*)zero16, nrhs, (int)nrows);
+    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0, 1>), g, b, 0, st, rows, segs, xt, z, nrhs,
+                       (int)nrows);
   else
-    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1>), dim3((unsigned)nrows), dim3(256), 0, st,
-                       rows, segs, (const cpx<R>*)XT, (const cpx<R>*)zero16, nrhs, (int)nrows);
+    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1, 1>), g, b, 0, st, rows, segs, xt, z, nrhs,
+                       (int)nrows);
 }
 template void launch_mv_rows_mfma<double>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
                                           int, hipStream_t);
