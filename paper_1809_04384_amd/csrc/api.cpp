@@ -1772,13 +1772,23 @@ dh2_status dh2_batch_create(const dh2_handle* handles, const void* const* X, voi
     capturing = false;
     HIPCHK(hipStreamEndCapture(b->stream, &b->graph));
     HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-  } catch (const Fail& f) {
+  } catch (...) {
     if (capturing) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(b->stream, &g);
       if (g) (void)hipGraphDestroy(g);
     }
-    return fail(f);
+    try {
+      throw;
+    } catch (const Fail& f) {
+      return fail(f);
+    } catch (const std::bad_alloc&) {
+      g_err = "host allocation failed";
+      return DH2_ERR_OOM;
+    } catch (const std::exception& e) {
+      g_err = e.what();
+      return DH2_ERR_DEVICE;
+    }
   }
   *out = b.release();
   return DH2_OK;
