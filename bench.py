@@ -478,7 +478,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(near_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(near_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic() if args.workload == "sphere131k" else None,
-                     "kernel": "k_mv_rows_mfma<double,1,4,0> (near-field block rows on matrix cores)",
+                     "kernel": "k_mv_rows_mfma<double,1,4,0,1> (near-field block rows on matrix cores)",
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
         "cpu_baseline": base,
         "fp32_form": fp32,
