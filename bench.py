@@ -94,6 +94,30 @@ def measured_traffic():
         return None
 
 
+def measured_peaks(torch):
+    """Achievable rates on this GPU for context: HBM read bandwidth of a plain
+    streaming reduction (torch sum over 16 GiB) and the FP64 matrix-core rate of
+    a large library GEMM (torch.matmul, 8192^3)."""
+    x = torch.ones(2 * 1024 ** 3, dtype=torch.float64, device="cuda:0")
+    a = torch.randn(8192, 8192, dtype=torch.float64, device="cuda:0")
+    out = {}
+    for name, f, work in (("hbm_read_gbs", lambda: x.sum(), 16 * 2 ** 30 / 1e9),
+                          ("fp64_gemm_tflops", lambda: a @ a, 2 * 8192 ** 3 / 1e12)):
+        f()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[name] = round(work / (statistics.median(ts) * 1e-3), 1)
+    del x, a
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_probe(mib):
     import torch
     a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
@@ -439,6 +463,9 @@ def main():
     if not args.no_spectral:
         spec = spectral_form(args, dh2, torch)
 
+    peaks = measured_peaks(torch)
+    log("measured peaks: %s" % peaks)
+
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -479,7 +506,9 @@ def main():
                      "frac": round(near_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic() if args.workload == "sphere131k" else None,
                      "kernel": "k_mv_rows_mfma<double,1,4,0,1> (near-field block rows on matrix cores)",
-                     "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4)},
+                     "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4),
+                     "measured_peaks": peaks,
+                     "frac_of_measured_read": round(near_gbs / peaks["hbm_read_gbs"], 4) if peaks else None},
         "cpu_baseline": base,
         "fp32_form": fp32,
         "bf16x3_form": bf,
