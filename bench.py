@@ -328,7 +328,27 @@ def batch_form(args, dh2, torch, count):
                  .to("cuda:0"))
         Ye.append(torch.empty_like(X[-1]))
         Yb.append(torch.empty_like(X[-1]))
-    log("batch form: %d problems, n total %d, builds %.1f s" % (count, sum(w.n for w in ws), tb))
+    log("batch form: %d problems, n total %d, builds one after another %.1f s" % (count, sum(w.n for w in ws), tb))
+    # the same builds side by side (dh2_build_many): 8 host threads, a stream per problem
+    probs = []
+    for w in ws:
+        V, T = synth.make_mesh(w)
+        probs.append((V, T, w.kappa, w.order, w.eta, w.leaf, w.tol))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hm = dh2.build_many(probs, precision=dh2.FP32, max_nrhs=nrhs, threads=8)
+    torch.cuda.synchronize()
+    tbm = time.perf_counter() - t0
+    same_build = True
+    for h1, h2, x in zip(hs, hm, X):
+        y1, y2 = torch.empty_like(x), torch.empty_like(x)
+        h1.matvec(x, y1)
+        h2.matvec(x, y2)
+        torch.cuda.synchronize()
+        same_build = same_build and torch.equal(y1, y2)
+    for h in hm:
+        h.free()
+    log("batch form: builds side by side %.1f s (x%.2f), products equal %s" % (tbm, tb / tbm, same_build))
     s = torch.cuda.Stream()
     b = dh2.Batch(hs, X, Yb, stream=s.cuda_stream)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -359,7 +379,9 @@ def batch_form(args, dh2, torch, count):
         "workload": "%d problems: sphere / side-2 cube / ellipsoid 1:2:3, n ~ U[2048, 32768] (total %d), "
                     "kappa ~ U[4, 24], m=4, leaf 32, tol 1e-5, FP32 form, %d complex64 right-hand sides each"
                     % (count, sum(w.n for w in ws), nrhs),
-        "build_s_total": round(tb, 2), "graph_ms": round(t_bat, 3), "one_after_another_ms": round(t_seq, 3),
+        "build_s_total": round(tb, 2), "build_s_side_by_side": round(tbm, 2),
+        "side_by_side_builds_equal": same_build,
+        "graph_ms": round(t_bat, 3), "one_after_another_ms": round(t_seq, 3),
         "speedup": round(t_seq / t_bat, 3), "value": round(bytes_total / (t_bat * 1e-3) / 1e9, 1), "unit": "GB/s",
         "bytes_per_batch": bytes_total, "bitwise_equal_to_single_products": same,
     }

@@ -147,6 +147,19 @@ dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, do
 /* Releases all device and host memory of the handle.  NULL is a no-op. */
 void dh2_free(dh2_handle h);
 
+/* Builds of many problems side by side: problem i is what dh2_build_ex returns
+ * for (geometries[i], kappa[i], order[i], eta[i], leafsize[i], tol[i], options),
+ * built by one of up to `threads` host threads (0 = 8) on a stream of its own, so
+ * the GPU runs the phases of several builds at once (small problems fill a
+ * fraction of it each).  options->stream is ignored: every handle owns its
+ * stream, which dh2_free destroys.  out receives count handles; on failure all
+ * entries are NULL, every partial build is freed and the message names the
+ * first failing problem.  Errors: as dh2_build_ex; DH2_ERR_ARG for NULL arrays
+ * or count < 1. */
+dh2_status dh2_build_many(int count, const dh2_geometry* geometries, const double* kappa, const int* order,
+                          const double* eta, const int* leafsize, const double* tol,
+                          const dh2_options* options, int threads, dh2_handle* out);
+
 /* ---------------------------------------------------------------------------
  * Many products as one launch: a batch holds Y_i = Gtilde_i X_i for count
  * distinct handles (problems of any sizes, one precision), recorded once into

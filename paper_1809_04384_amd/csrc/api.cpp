@@ -23,6 +23,8 @@
 #include <memory>
 #include <numeric>
 #include <set>
+#include <atomic>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -212,10 +214,12 @@ struct dh2_problem {
     }
     return p;
   }
+  bool own_stream = false;               // created by dh2_build_many, destroyed with the handle
   ~dh2_problem() {
     if (stream) hipStreamSynchronize(stream);
     else hipDeviceSynchronize();
     for (void* p : allocs) hipFree(p);
+    if (own_stream && stream) hipStreamDestroy(stream);
   }
   void sync() {
     HIPCHK(hipStreamSynchronize(stream));
@@ -1841,6 +1845,65 @@ dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, do
 }
 
 void dh2_free(dh2_handle h) { delete h; }
+
+dh2_status dh2_build_many(int count, const dh2_geometry* geometries, const double* kappa, const int* order,
+                          const double* eta, const int* leafsize, const double* tol, const dh2_options* options,
+                          int threads, dh2_handle* out) {
+  g_err.clear();
+  if (!out || count < 1 || !geometries || !kappa || !order || !eta || !leafsize || !tol) {
+    g_err = "NULL array or count < 1";
+    return DH2_ERR_ARG;
+  }
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  dh2_options base{};
+  base.size = sizeof(base);
+  if (options) {
+    if (options->size < sizeof(uint32_t) || options->size > sizeof(dh2_options)) {
+      g_err = "options.size must be sizeof(dh2_options)";
+      return DH2_ERR_ARG;
+    }
+    std::memcpy(&base, options, options->size);
+  }
+  const int nthr = std::max(1, std::min(count, threads > 0 ? threads : 8));
+  std::vector<hipStream_t> streams(count, nullptr);
+  std::vector<dh2_status> st(count, DH2_OK);
+  std::vector<std::string> msg(count);
+  for (int i = 0; i < count; ++i) {
+    if (hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(streams[j]);
+      g_err = "stream creation failed";
+      return DH2_ERR_DEVICE;
+    }
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    (void)hipSetDevice(dev);
+    for (int i = next++; i < count; i = next++) {
+      dh2_options o = base;
+      o.stream = streams[i];
+      st[i] = dh2_build_ex(&geometries[i], kappa[i], order[i], eta[i], leafsize[i], tol[i], &o, &out[i]);
+      if (st[i] == DH2_OK) out[i]->own_stream = true;
+      else msg[i] = g_err;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthr; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < count; ++i) {
+    if (st[i] == DH2_OK) continue;
+    for (int j = 0; j < count; ++j) {
+      if (out[j]) dh2_free(out[j]);   // destroys its own stream
+      else (void)hipStreamDestroy(streams[j]);
+      out[j] = nullptr;
+    }
+    g_err = "problem " + std::to_string(i) + ": " + msg[i];
+    return st[i];
+  }
+  return DH2_OK;
+}
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s) {
   if (!h || !s || s->size != sizeof(dh2_stats)) {

@@ -3,6 +3,8 @@
 // interleaved (re, im); matrices are column-major unless stated.
 #include "kernels.hpp"
 
+#include <atomic>
+
 #include <type_traits>
 
 #include <hip/hip_runtime.h>
@@ -1348,8 +1350,11 @@ void launch_gemm_bf16x3(const GemmDesc* d, int64_t nitems, int maxM, int maxN, h
 }
 template void launch_gemm<float>(const GemmDesc*, int64_t, int, int, hipStream_t);
 
-static size_t g_lds_limit = 65536;   // per-workgroup LDS bytes usable for dynamic buffers
-static size_t g_lds_total = 65536;   // per-workgroup LDS bytes of the device
+// per-workgroup LDS bytes usable for dynamic buffers, and of the device; set by
+// every build (the same values for one device), read by the launchers, so
+// atomic: builds may run in several host threads
+static std::atomic<size_t> g_lds_limit{65536};
+static std::atomic<size_t> g_lds_total{65536};
 
 void set_lds_limit(size_t bytes) {
   g_lds_total = bytes;

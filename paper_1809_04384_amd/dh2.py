@@ -24,7 +24,7 @@ INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col":
 EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_free", "dh2_last_error",
             "dh2_get_stats", "dh2_plan_create", "dh2_plan_get_sizes", "dh2_plan_export",
             "dh2_plan_free", "dh2_inspect", "dh2_batch_create", "dh2_batch_run", "dh2_batch_free",
-            "dh2_matvec_stream"]
+            "dh2_matvec_stream", "dh2_build_many"]
 
 
 class Dh2Error(RuntimeError):
@@ -99,12 +99,13 @@ def load():
     lib.dh2_inspect.argtypes = [P, I32, I64, P, P, P]
     lib.dh2_batch_create.argtypes = [P, P, P, I32, I32, P, P]
     lib.dh2_matvec_stream.argtypes = [P, P, P, I32, P]
+    lib.dh2_build_many.argtypes = [I32, P, P, P, P, P, P, P, I32, P]
     lib.dh2_batch_run.argtypes = [P]
     lib.dh2_batch_free.argtypes = [P]
     lib.dh2_batch_free.restype = None
     for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_get_stats", "dh2_plan_create",
                  "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect", "dh2_batch_create", "dh2_batch_run",
-                 "dh2_matvec_stream"):
+                 "dh2_matvec_stream", "dh2_build_many"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -274,3 +275,43 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+def build_many(problems, precision=FP64, max_nrhs=16, eta1=10.0, norm=NORM_FROBENIUS, threads=0,
+               workspace_gb=0.0):
+    """Handles for many problems built side by side (dh2_build_many): problems is
+    a list of (V, T, kappa, order, eta, leafsize, tol); every handle owns a
+    stream of its own."""
+    lib = load()
+    cnt = len(problems)
+    if cnt < 1:
+        raise ValueError("no problems")
+    geoms = (Geometry * cnt)()
+    keep = []
+    for i, (V, T, *_rest) in enumerate(problems):
+        g, k = _geometry(V, T)
+        geoms[i] = g
+        keep.append(k)
+    kap = (ctypes.c_double * cnt)(*[float(p[2]) for p in problems])
+    order = (ctypes.c_int * cnt)(*[int(p[3]) for p in problems])
+    eta = (ctypes.c_double * cnt)(*[float(p[4]) for p in problems])
+    leaf = (ctypes.c_int * cnt)(*[int(p[5]) for p in problems])
+    tol = (ctypes.c_double * cnt)(*[float(p[6]) for p in problems])
+    opt = Options()
+    opt.size = ctypes.sizeof(Options)
+    opt.precision = precision
+    opt.eta1 = eta1
+    opt.max_nrhs = max_nrhs
+    opt.workspace_gb = workspace_gb
+    opt.norm = norm
+    out = (ctypes.c_void_p * cnt)()
+    _check(lib.dh2_build_many(cnt, geoms, kap, order, eta, leaf, tol, ctypes.byref(opt), threads, out))
+    hs = []
+    for i in range(cnt):
+        h = Handle.__new__(Handle)
+        h._h = ctypes.c_void_p(out[i])
+        h.precision = precision
+        h.max_nrhs = max_nrhs
+        h.n = int(np.asarray(problems[i][1]).shape[0])
+        hs.append(h)
+    return hs

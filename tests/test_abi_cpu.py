@@ -34,6 +34,15 @@ def test_batch_entry_points_reject_bad_arguments_without_gpu():
     lib.dh2_batch_free(None)
 
 
+def test_build_many_rejects_bad_arguments_without_gpu():
+    import ctypes
+    lib = dh2.load()
+    out = (ctypes.c_void_p * 2)()
+    assert lib.dh2_build_many(0, None, None, None, None, None, None, None, 0, out) == 1
+    assert lib.dh2_build_many(2, None, None, None, None, None, None, None, 0, out) == 1
+    assert out[0] is None and out[1] is None
+
+
 def test_build_rejects_bad_arguments_without_gpu():
     V, T = synth.sphere_octahedral(2)
     bad = [dict(kappa=-1.0), dict(order=0), dict(eta=0.0), dict(leafsize=0), dict(tol=-1.0)]
