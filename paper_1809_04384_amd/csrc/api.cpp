@@ -185,11 +185,13 @@ struct dh2_problem {
   int64_t n_xh_tr = 0;
   int64_t near_matvec_bytes = 0;    // matrix bytes streamed by the near-field kernel
 
+  // Stream-ordered allocations on the handle's stream: a release does not wait
+  // for the whole device (builds of other handles on other streams go on)
   template <class T>
   T* alloc(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
-    HIPCHK(hipMalloc(&p, count * sizeof(T)));
+    HIPCHK(hipMallocAsync(&p, count * sizeof(T), stream));
     allocs.push_back(p);
     return (T*)p;
   }
@@ -197,7 +199,7 @@ struct dh2_problem {
     if (!p) return;
     auto it = std::find(allocs.begin(), allocs.end(), p);
     if (it != allocs.end()) {
-      hipFree(p);
+      (void)hipFreeAsync(p, stream);
       allocs.erase(it);
     }
   }
@@ -218,7 +220,9 @@ struct dh2_problem {
   ~dh2_problem() {
     if (stream) hipStreamSynchronize(stream);
     else hipDeviceSynchronize();
-    for (void* p : allocs) hipFree(p);
+    for (void* p : allocs) (void)hipFreeAsync(p, stream);
+    if (stream) hipStreamSynchronize(stream);
+    else hipDeviceSynchronize();
     if (own_stream && stream) hipStreamDestroy(stream);
   }
   void sync() {

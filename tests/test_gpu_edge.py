@@ -2,8 +2,9 @@
 one leaf (no admissible block: the matvec is the dense near field), the
 Laplace case kappa = 0 (one direction per level), tol = 0 (every nonzero
 singular value kept), the largest right-hand-side count a handle reserves and
-one beyond it, a handle on a non-default stream, and bitwise repeatability
-(the matvec adds partial sums in a fixed order, without atomics)."""
+one beyond it, a handle on a non-default stream and a product on a per-call
+stream, and bitwise repeatability (the matvec adds partial sums in a fixed
+order, without atomics)."""
 import numpy as np
 import pytest
 
@@ -131,6 +132,12 @@ def test_side_stream_and_bitwise_repeatability():
         torch.cuda.synchronize()
         assert torch.equal(Ya, Yb)
         assert torch.equal(Ya, Yc)
+        # the per-call stream of dh2_matvec_stream
+        Yd = torch.empty_like(X)
+        with torch.cuda.stream(s):
+            h0.matvec_on(X, Yd, s.cuda_stream)
+        s.synchronize()
+        assert torch.equal(Ya, Yd)
     finally:
         h0.free()
         h1.free()
