@@ -121,3 +121,18 @@ def test_build_many_equals_single_builds():
     finally:
         for h in many + single:
             h.free()
+
+
+def test_build_many_reports_the_failing_problem():
+    """A problem that fails its build (a triangle index out of range, caught on
+    the host) fails the whole call: the status is the problem's, the message
+    names it, and no handle is returned."""
+    from paper_1809_04384_amd import dh2
+    V, T = synth.sphere_octahedral(4)
+    bad = T.copy()
+    bad[5, 2] = len(V) + 3
+    probs = [(V, T, 4.0, 3, 1.0, 16, 1e-6), (V, bad, 4.0, 3, 1.0, 16, 1e-6), (V, T, 2.0, 3, 1.0, 16, 1e-6)]
+    with pytest.raises(dh2.Dh2Error) as e:
+        dh2.build_many(probs, threads=3)
+    assert e.value.status == 2
+    assert "problem 1" in str(e.value)
