@@ -229,7 +229,8 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=None):
     log("%s form: build %.2f s, matvec %.3f ms (%.1f GB/s), near %.3f ms (%.1f GB/s), rel. diff vs FP64 %.2e"
         % (label, tb, mv_ms, mv_bytes / (mv_ms * 1e-3) / 1e9, near_avg, near_alg / (near_avg * 1e-3) / 1e9, err))
     return {
-        "dtype": ("f32 matvec and near field; FP64 recompression" if precision == dh2.FP32 else
+        "dtype": ("f32 matvec and near field; recompression products f32 on matrix cores with f32 "
+                  "accumulation, FP64 QR and SVD" if precision == dh2.FP32 else
                   "f32 matvec and near field; recompression products split-BF16x3 with f32 accumulation, "
                   "FP64 QR and SVD"),
         "build_s": round(tb, 3),

@@ -52,13 +52,14 @@ typedef struct {
 
 /* Precision of a handle.
  *   DH2_FP64  everything in FP64; X / Y are complex128.
- *   DH2_FP32  the near field is evaluated and stored in FP32; interpolation and
- *             recompression run in FP64 (the same ranks as the FP64 form); the
- *             recompressed couplings and bases are then rounded to complex64
- *             and the matvec runs in FP32 on complex64 X / Y.
+ *   DH2_FP32  the near field is evaluated and stored in FP32; the matrix
+ *             products of the recompression (weighted couplings, block weights,
+ *             total-weight pieces, basis changes, projections) run on the FP32
+ *             matrix cores with FP32 accumulation on FP64 data; the recompressed
+ *             couplings and bases are then rounded to complex64 and the matvec
+ *             runs in FP32 on complex64 X / Y.
  *   DH2_BF16X3  the FP32 form with the matrix products of the recompression
- *             (weighted couplings, block weights, total-weight pieces, basis
- *             changes, projections) on the BF16 matrix cores: each FP64 operand
+ *             on the BF16 matrix cores instead: each FP64 operand
  *             is split into two bf16 parts and a product takes three of the four
  *             part products, accumulated in FP32 (about 2^-16 relative per
  *             product); ranks may differ from the FP64 form at near-ties.

@@ -347,6 +347,8 @@ struct Builder {
       h.stats.gemm_launches += (int64_t)((i1 - i0 + 65534) / 65535);
       if (h.precision == DH2_BF16X3)
         launch_gemm_bf16x3(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
+      else if (h.precision == DH2_FP32)
+        launch_gemm_f32(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
       else
         launch_gemm<double>(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
       i0 = i1;

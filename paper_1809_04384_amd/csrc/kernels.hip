@@ -292,16 +292,19 @@ struct GMfma<float> {
 // happen there), and each wave multiplies a 16 x 16 sub-tile on the matrix
 // cores, four real products per complex product:
 //   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
-template <typename R>
+// S: storage type of A, B and C; R: the matrix-core type of the products
+// (S = double, R = float: FP64 data multiplied on the FP32 matrix cores with
+// FP32 accumulation).
+template <typename S, typename R>
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, int ntm) {
   typedef typename GMfma<R>::acc_t acc_t;
   const GemmDesc d = dd[blockIdx.y];
   const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
   const int m0 = tm * 32, n0 = tn * 32;
   if (m0 >= d.M || n0 >= d.N) return;
-  const cpx<R>* A = (const cpx<R>*)d.A;
-  const cpx<R>* B = (const cpx<R>*)d.B;
-  cpx<R>* C = (cpx<R>*)d.C;
+  const cpx<S>* A = (const cpx<S>*)d.A;
+  const cpx<S>* B = (const cpx<S>*)d.B;
+  cpx<S>* C = (cpx<S>*)d.C;
   __shared__ cpx<R> As[16][33];
   __shared__ cpx<R> Bs[16][33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -323,7 +326,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
       if (d.opA == 0) { i = e % 32; kk = e / 32; }
       else { kk = e % 16; i = e / 16; }
       const int gi = m0 + i, gk = k0 + kk;
-      cpx<R> v{0, 0};
+      cpx<S> v{0, 0};
       if (gi < d.M && gk < d.K) {
         if (d.opA == 0) v = A[gi + (int64_t)gk * d.lda];
         else {
@@ -331,12 +334,12 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
           if (d.opA == 2) v = conj(v);
         }
       }
-      va[h] = v;
+      va[h] = cpx<R>{(R)v.x, (R)v.y};
       int kb, j;
       if (d.opB == 0) { kb = e % 16; j = e / 16; }
       else { j = e % 32; kb = e / 32; }
       const int gkb = k0 + kb, gj = n0 + j;
-      cpx<R> w{0, 0};
+      cpx<S> w{0, 0};
       if (gkb < d.K && gj < d.N) {
         if (d.opB == 0) w = B[gkb + (int64_t)gj * d.ldb];
         else {
@@ -344,7 +347,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
           if (d.opB == 2) w = conj(w);
         }
       }
-      vb[h] = w;
+      vb[h] = cpx<R>{(R)w.x, (R)w.y};
     }
   };
   auto store_slice = [&]() {
@@ -373,13 +376,13 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
     }
     __syncthreads();
   }
-  const cpx<R> al{(R)d.alpha_re, (R)d.alpha_im};
+  const cpx<S> al{(S)d.alpha_re, (S)d.alpha_im};
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int gi = m0 + sm + GMfma<R>::row(lane, e), gj = n0 + sn + li;
     if (gi < d.M && gj < d.N) {
-      const cpx<R> v = al * cpx<R>{cre[e], cim[e]};
-      cpx<R>& dst = C[gi + (int64_t)gj * d.ldc];
+      const cpx<S> v = al * cpx<S>{(S)cre[e], (S)cim[e]};
+      cpx<S>& dst = C[gi + (int64_t)gj * d.ldc];
       dst = d.accumulate ? dst + v : v;
     }
   }
@@ -1334,7 +1337,7 @@ void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStrea
   const int ntm = (maxM + 31) / 32, ntn = (maxN + 31) / 32;
   for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
     const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
-    hipLaunchKernelGGL(k_gemm<R>, dim3((unsigned)(ntm * ntn), (unsigned)cnt), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_gemm<R, R>), dim3((unsigned)(ntm * ntn), (unsigned)cnt), dim3(256), 0, st,
                        d + i0, ntm);
   }
 }
@@ -1348,7 +1351,16 @@ void launch_gemm_bf16x3(const GemmDesc* d, int64_t nitems, int maxM, int maxN, h
     hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(ntm * ntn), (unsigned)cnt), dim3(256), 0, st, d + i0, ntm);
   }
 }
-template void launch_gemm<float>(const GemmDesc*, int64_t, int, int, hipStream_t);
+
+void launch_gemm_f32(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st) {
+  if (nitems <= 0 || maxM <= 0 || maxN <= 0) return;
+  const int ntm = (maxM + 31) / 32, ntn = (maxN + 31) / 32;
+  for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
+    const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
+    hipLaunchKernelGGL((k_gemm<double, float>), dim3((unsigned)(ntm * ntn), (unsigned)cnt), dim3(256), 0, st,
+                       d + i0, ntm);
+  }
+}
 
 // per-workgroup LDS bytes usable for dynamic buffers, and of the device; set by
 // every build (the same values for one device), read by the launchers, so

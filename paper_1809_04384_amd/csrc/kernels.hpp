@@ -121,6 +121,8 @@ template <typename R>
 void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st);
 // The same products on FP64 data with split-BF16x3 MFMA products and FP32 accumulation
 void launch_gemm_bf16x3(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st);
+// The same products on FP64 data on the FP32 matrix cores (operands rounded to FP32, FP32 accumulation)
+void launch_gemm_f32(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st);
 void set_lds_limit(size_t bytes);
 int fold_rows_per_chunk(int n);
 template <typename PT>

@@ -168,9 +168,9 @@ FP32_CASES = ["dir512", "sphere2k", "cube1200dir", "dir2k"]
 
 @pytest.mark.parametrize("name", FP32_CASES)
 def test_fp32_form_matches_fp64(name):
-    """FP32 form: near field evaluated in FP32, recompression in FP64 (same
-    ranks as the FP64 form), couplings and bases rounded to complex64, matvec
-    in FP32.  Every right-hand-side count (1, 2, 5, 20, 37) must agree with the
+    """FP32 form: near field evaluated in FP32, the recompression's matrix
+    products on the FP32 matrix cores (QR and SVD in FP64), couplings and
+    bases rounded to complex64, matvec in FP32.  Every right-hand-side count (1, 2, 5, 20, 37) must agree with the
     FP64 oracle to 1e-4 relative, the near field entry by entry to 1e-5 of its
     largest entry."""
     import torch
@@ -182,8 +182,13 @@ def test_fp32_form_matches_fp64(name):
     h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32, max_nrhs=40)
     h64, _ = handle(name)
     try:
-        assert np.array_equal(h.inspect("rank_row"), h64.inspect("rank_row"))
-        assert np.array_equal(h.inspect("rank_col"), h64.inspect("rank_col"))
+        # the recompression products run in FP32: ranks may move at singular
+        # values within FP32 rounding of the threshold, so they are reported,
+        # and the products below carry the bound
+        for kind in ("row", "col"):
+            r32, r64 = h.inspect("rank_" + kind), h64.inspect("rank_" + kind)
+            say("[gpu] %s FP32 %s ranks differing from FP64: %d of %d"
+                % (name, kind, int(np.sum(r32 != r64)), r32.size))
         nb = len(o.st.near)
         for b in list(range(0, nb, max(1, nb // 20))) + [nb - 1]:
             N = h.inspect("near", b)
