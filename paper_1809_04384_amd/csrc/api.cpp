@@ -1895,7 +1895,13 @@ dh2_status dh2_build_many(int count, const dh2_geometry* geometries, const doubl
     }
   };
   std::vector<std::thread> pool;
-  for (int t = 1; t < nthr; ++t) pool.emplace_back(worker);
+  for (int t = 1; t < nthr; ++t) {
+    try {
+      pool.emplace_back(worker);
+    } catch (...) {
+      break;   // fewer threads: the calling thread takes the remaining problems
+    }
+  }
   worker();
   for (auto& t : pool) t.join();
   for (int i = 0; i < count; ++i) {
