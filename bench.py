@@ -29,6 +29,7 @@ import synth  # noqa: E402
 
 METRIC = "DH² build s + matvec GB/s, n=131k κ=32 at rel.err 1e-4, FP32 vs FP64"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -40,11 +41,15 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=3)
+    ap.add_argument("--cpu-build-workloads", default="sphere2k,dir2k",
+                    help="workloads whose whole oracle build is timed beside the GPU build ('' = none)")
+    ap.add_argument("--err-sample-leaves", type=int, default=4,
+                    help="leaf row clusters of the error check against the interpolated matrix (0 = skip)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-control build")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
-    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
-                    help="also run the batching form with COUNT problems (64 in the recipe)")
+    ap.add_argument("--batch", type=int, default=64, metavar="COUNT",
+                    help="problems of the batching form (the recipe's 64; 0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming kernel (read MIB MiB, write MIB MiB) and exit; "
                          "its HBM counters calibrate the traffic of the profiled kernels")
@@ -132,16 +137,20 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, V, T, X, nleaves):
+def cpu_baseline(w, V, T, X, nleaves, pre=None):
     """Oracle near-field matvec on the rows of a few leaf clusters (seeded
-    choice), timed on the host.  Returns the baseline object."""
+    choice), timed on the host.  pre = (structure, triangle data, seconds) of
+    an oracle already built for this workload.  Returns the baseline object."""
     from oracle.structure import build_structure
     from oracle.quadrature import triangle_data
     from oracle import cquad
-    t0 = time.time()
-    st = build_structure(V, T, w.kappa, w.eta, w.leaf, w.eta1)
-    tri = triangle_data(V, T)
-    t_struct = time.time() - t0
+    if pre is None:
+        t0 = time.time()
+        st = build_structure(V, T, w.kappa, w.eta, w.leaf, w.eta1)
+        tri = triangle_data(V, T)
+        t_struct = time.time() - t0
+    else:
+        st, tri, t_struct = pre
     leaves = [t for t in range(len(st.first)) if st.is_leaf(t)]
     rng = np.random.default_rng(2)
     pick = sorted(rng.choice(len(leaves), size=min(nleaves, len(leaves)), replace=False).tolist())
@@ -183,7 +192,86 @@ def cpu_baseline(w, V, T, X, nleaves):
     }
 
 
-def fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=None):
+def oracle_matvec_bytes(o, nrhs):
+    """Algorithmic bytes of one compressed matvec of the oracle's result, by the
+    library's formula: every stored entry (near field, recompressed couplings,
+    leaf bases and transfers of both bases) read once, 16 bytes each, plus per
+    right-hand side X and Y and the coefficient vectors read and written."""
+    st = o.st
+    near = sum(int(st.size[t]) * int(st.size[s]) for (t, s) in st.near)
+    coup = sum(S.size for S in o.St)
+    basis = sum(Q.size for Q in o.Q.values()) + sum(F.size for F in o.F.values())
+    basis += sum(Q.size for Q in o.QW.values()) + sum(F.size for F in o.FW.values())
+    coef = sum(o.rank.values()) + sum(o.rankW.values())
+    return 16.0 * (near + coup + basis) + nrhs * 16.0 * (2.0 * o.n + 2.0 * coef)
+
+
+def cpu_build_baseline(names, dh2, torch):
+    """The FP64 oracle's whole build and one matvec on small workloads, per
+    phase, on the host cores, beside the FP64 GPU build of the same problem."""
+    from oracle.dh2 import OracleDH2
+    out = {}
+    for name in names:
+        w = synth.WORKLOADS[name]
+        V, T = synth.make_mesh(w)
+        t0 = time.perf_counter()
+        o = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1)
+        tb = time.perf_counter() - t0
+        X = synth.complex_gaussian(len(T), 1, seed=0)
+        t0 = time.perf_counter()
+        o.matvec(X.T)
+        tm = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=1)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        h.free()
+        out[name] = {
+            "workload": "%s: %s n=%d, kappa=%g, m=%d, leaf %d, eta=%g, eta1=%g, tol=%g, FP64"
+                        % (name, w.surface, len(T), w.kappa, w.order, w.leaf, w.eta, w.eta1, w.tol),
+            "build_s": round(tb, 2),
+            "build_phases_s": dict({"structure": round(o.structure_s, 2)},
+                                   **{k: round(v, 2) for k, v in o.phase_s.items()}),
+            "matvec_s": round(tm, 3),
+            "matvec_gbs": round(oracle_matvec_bytes(o, 1) / tm / 1e9, 3),
+            "gpu_build_s": round(tg, 3),
+        }
+        log("cpu baseline build %s: oracle %.1f s, GPU %.3f s" % (name, tb, tg))
+    return out
+
+
+def interp_error(w, V, T, X, results, nleaves):
+    """Relative error of the compressed matvec against the interpolated matrix
+    G_int (the error the recompression tolerance bounds, Section 5) on the rows
+    of a seeded sample of leaf clusters, for every form, beside the error
+    against the reference Galerkin matrix G on the same rows (interpolation
+    plus recompression).  G_int X and G X on those rows come from the oracle."""
+    from oracle.dh2 import OracleDH2
+    t0 = time.perf_counter()
+    o = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, lazy=True)
+    st = o.st
+    leaves = [t for t in range(len(st.first)) if st.is_leaf(t)]
+    rng = np.random.default_rng(2)
+    pick = [leaves[i] for i in sorted(rng.choice(len(leaves), size=nleaves, replace=False).tolist())]
+    rows, Yi = o.interp_rows(pick, X.T)
+    t_int = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    G = o.galerkin_rows(rows)
+    Yg = G @ X.T
+    t_gal = time.perf_counter() - t0
+    out = {"sample": "%d leaf row clusters (default_rng(2)), %d rows x %d right-hand sides; oracle G_int rows "
+                     "%.1f s, Galerkin rows %.1f s" % (nleaves, len(rows), X.shape[0], t_int, t_gal)}
+    for label, Y in results.items():
+        Yr = Y[:, rows].T
+        out[label] = {"vs_interp": float(np.linalg.norm(Yr - Yi) / np.linalg.norm(Yi)),
+                      "vs_galerkin": float(np.linalg.norm(Yr - Yg) / np.linalg.norm(Yg))}
+    out["interp_vs_galerkin"] = float(np.linalg.norm(Yi - Yg) / np.linalg.norm(Yg))
+    log("errors on sampled rows: %s" % json.dumps(out))
+    return out, (st, o.tri, o.structure_s)
+
+
+def fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=None):
     """The FP32 form (or, with precision = BF16X3, its split-BF16x3 variant)
     on the same workload: one build, event-timed matvecs on complex64
     right-hand sides (the FP64 draw rounded), and the relative Frobenius
@@ -225,6 +313,7 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=None):
     h.matvec(Xd, Yd)
     torch.cuda.synchronize()
     err = (torch.linalg.vector_norm(Yd.to(torch.complex128) - Y64) / torch.linalg.vector_norm(Y64)).item()
+    results[label] = Yd.cpu().numpy().astype(np.complex128)
     h.free()
     log("%s form: build %.2f s, matvec %.3f ms (%.1f GB/s), near %.3f ms (%.1f GB/s), rel. diff vs FP64 %.2e"
         % (label, tb, mv_ms, mv_bytes / (mv_ms * 1e-3) / 1e9, near_avg, near_alg / (near_avg * 1e-3) / 1e9, err))
@@ -451,7 +540,7 @@ def main():
     mv_ms = statistics.median(times)
     mv_bytes = st["matvec_bytes"] + nrhs * st["matvec_bytes_per_rhs"]
     mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
-    # dominant kernel: near field, timed with events around its launch
+    # near field (the dominant kernel) and coupling, timed with events around their launches
     phases = {}
     near_ms = []
     near_bytes = 0.0
@@ -466,17 +555,25 @@ def main():
     near_gbs = near_alg / (near_avg * 1e-3) / 1e9
     log("matvec %.3f ms (%.1f GB/s); near field %.3f ms, %.2f GB -> %.1f GB/s"
         % (mv_ms, mv_gbs, near_avg, near_alg / 1e9, near_gbs))
+    # coupling kernel: every recompressed coupling read once, x_sc read and y_tc written once
+    coup_avg = sum(phases["coupling"]) / len(phases["coupling"])
+    coup_alg = e * st["coupling_entries"] + e * nrhs * (st["rank_mean_row"] * st["n_row_slots"]
+                                                        + st["rank_mean_col"] * st["n_col_slots"])
+    coup_gbs = coup_alg / (coup_avg * 1e-3) / 1e9
+    # build: complex products and Householder steps of the recompression against the FP64 peak
+    build_tflops = (st["gemm_flops"] + st["qr_flops"]) / statistics.median(builds) / 1e12
     h.matvec(Xd, Yd)
     Y64 = Yd.clone()
     h.free()
 
+    results = {"fp64": Y64.cpu().numpy()}
     fp32 = None
     if not args.no_fp32:
-        fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch)
+        fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch, results)
 
     bf = None
     if not args.no_bf16x3:
-        bf = fp32_form(args, w, V, T, X, Y64, dh2, torch, precision=dh2.BF16X3)
+        bf = fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=dh2.BF16X3)
 
     batch = None
     if args.batch > 0:
@@ -489,11 +586,18 @@ def main():
     peaks = measured_peaks(torch)
     log("measured peaks: %s" % peaks)
 
+    errs, pre = None, None
+    if args.err_sample_leaves > 0:
+        log("errors against the interpolated matrix on sampled rows (oracle) ...")
+        errs, pre = interp_error(w, V, T, X, results, args.err_sample_leaves)
+
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        base = cpu_baseline(w, V, T, X, args.cpu_sample_leaves)
+        base = cpu_baseline(w, V, T, X, args.cpu_sample_leaves, pre)
         log("cpu baseline %.3f GB/s" % base["value"])
+        if args.cpu_build_workloads:
+            base["build"] = cpu_build_baseline(args.cpu_build_workloads.split(","), dh2, torch)
 
     out = {
         "metric": METRIC,
@@ -531,7 +635,19 @@ def main():
                      "kernel": "k_mv_rows_mfma<double,1,4,0,1> (near-field block rows on matrix cores)",
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4),
                      "measured_peaks": peaks,
-                     "frac_of_measured_read": round(near_gbs / peaks["hbm_read_gbs"], 4) if peaks else None},
+                     "frac_of_measured_read": round(near_gbs / peaks["hbm_read_gbs"], 4) if peaks else None,
+                     "whole_matvec": {"achieved": round(mv_gbs, 1), "unit": "GB/s",
+                                      "frac": round(mv_gbs / HBM_PEAK_GBS, 4), "bytes": mv_bytes,
+                                      "ms": round(mv_ms, 4)},
+                     "coupling_kernel": {"kernel": "k_mv_rows_mfma<double,1,4,1,1>", "achieved": round(coup_gbs, 1),
+                                         "unit": "GB/s", "frac": round(coup_gbs / HBM_PEAK_GBS, 4),
+                                         "bytes_per_launch": coup_alg, "avg_launch_ms": round(coup_avg, 4)},
+                     "build": {"bound": "fp64", "achieved": round(build_tflops, 2), "unit": "TFLOP/s",
+                               "peak": FP64_PEAK_TFLOPS, "frac": round(build_tflops / FP64_PEAK_TFLOPS, 4),
+                               "flops": st["gemm_flops"] + st["qr_flops"],
+                               "note": "complex products (8 MNK) and Householder QR steps (8 M n^2) of "
+                                       "the recompression over the whole build time"}},
+        "rel_err": errs,
         "cpu_baseline": base,
         "fp32_form": fp32,
         "bf16x3_form": bf,

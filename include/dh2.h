@@ -145,7 +145,11 @@ dh2_status dh2_matvec_stream(dh2_handle h, const void* X, void* Y, int nrhs, voi
 dh2_status dh2_matvec_profile(dh2_handle h, const void* X, void* Y, int nrhs, double* phase_ms,
                               double* near_bytes);
 
-/* Releases all device and host memory of the handle.  NULL is a no-op. */
+/* Releases all device and host memory of the handle.  It first waits for all
+ * work on the device (products enqueued on other streams by
+ * dh2_matvec_stream or a batch may still read the handle's buffers), so it
+ * must not be called while a stream of this device is being captured into a
+ * graph.  NULL is a no-op. */
 void dh2_free(dh2_handle h);
 
 /* Builds of many problems side by side: problem i is what dh2_build_ex returns
@@ -184,7 +188,9 @@ dh2_status dh2_batch_create(const dh2_handle* handles, const void* const* X, voi
 /* One graph launch of all products (returns without synchronising unless the
  * batch owns its stream).  Errors: DH2_ERR_ARG (NULL), DH2_ERR_DEVICE. */
 dh2_status dh2_batch_run(dh2_batch b);
-/* Releases the graph and the batch's streams and events.  NULL is a no-op. */
+/* Releases the graph and the batch's streams and events after waiting for the
+ * batch's stream (a launch may still run).  The handles stay valid.  NULL is a
+ * no-op. */
 void dh2_batch_free(dh2_batch b);
 
 /* Message of the last failure on this thread ("" if none). */
@@ -208,6 +214,20 @@ typedef struct {
       ms_total_weights, ms_truncation, ms_projection, ms_total;
   double gemm_flops;        /* real flops of the build's complex matrix products, 8 M N K each */
   int64_t gemm_launches;    /* kernel launches of those products */
+  double qr_flops;          /* real flops of the Householder QR steps of the recompression:
+                               folding M rows into an n x n triangular factor counts 8 M n^2,
+                               a factor started from zero subtracts (8/3) min(M, n)^3 */
+  /* Workspace batches of the recompression phases (the interpolated couplings
+   * S_b are generated per batch and never stored) and the (cluster, direction)
+   * pairs of the two total-weight passes whose stacked rows were folded over
+   * more than one batch. */
+  int64_t batches_basis_weights, batches_block_weights, batches_total_weights_row,
+      batches_total_weights_col, batches_truncation, batches_projection;
+  int64_t slots_straddled;
+  /* Regeneration factor: interpolated couplings S_b generated during the build,
+   * divided by the number of admissible blocks (each phase that needs S_b
+   * generates it again). */
+  double coupling_regeneration;
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);

@@ -164,10 +164,24 @@ struct dh2_problem {
   void* St_d = nullptr;  std::vector<int64_t> St_off;   // Stilde_b (element type of the handle)
   int64_t St_total = 0;
   std::vector<void*> Qr32, Qc32;      // FP32 handles: complex64 copies of Qhat used by the matvec
-  // matvec schedule
-  void* Xp_d = nullptr; void* Yp_d = nullptr; void* xh_d = nullptr; void* yh_d = nullptr;
-  void* XT_d = nullptr;   // row-major copy of the gathered X (multi right-hand-side near field)
-  MvOut* mv_outs_d = nullptr; MvTerm* mv_terms_d = nullptr;
+  // matvec schedule.  A view holds the device addresses one product uses: the
+  // descriptor lists and the staging buffers they point into (gathered X Xp,
+  // its row-major copy XT, Y in cluster order Yp, the row-major slot vectors
+  // xhT), here in the handle's staging arena.
+  struct MvView {
+    MvOut* outs = nullptr;
+    MvTerm* terms = nullptr;
+    MfRow* near_rows = nullptr;
+    MfRow* coup_rows = nullptr;
+    SlotT* xh_tr = nullptr;
+    void* Xp = nullptr;
+    void* XT = nullptr;
+    void* Yp = nullptr;
+    void* xhT = nullptr;
+  };
+  MvView mv_own;
+  char* stage_d = nullptr;               // staging arena of the handle's own products
+  size_t stage_bytes = 0;
   struct Phase { int64_t out_begin, out_end; int group; };
   std::vector<Phase> mv_phases;     // groups: 1 forward, 2 coupling, 3 backward, 5 leaf output
 
@@ -175,12 +189,10 @@ struct dh2_problem {
 
   NearSeg* near_segs_d = nullptr;
   int64_t n_near_rows = 0;
-  // matrix-core block rows (every right-hand-side count)
-  MfRow* near_mf_rows_d = nullptr;      // one per leaf, segments near_segs_d
-  MfRow* coup_mf_rows_d = nullptr;      // one per row slot, segments coup_mf_segs_d
+  // matrix-core block rows (every right-hand-side count): one per leaf
+  // (segments near_segs_d) and one per row slot (segments coup_mf_segs_d)
+  XcdSplit near_split{}, coup_split{};  // per-XCD ranges of the two row lists
   NearSeg* coup_mf_segs_d = nullptr;
-  SlotT* xh_tr_d = nullptr;             // row-major copies of x_sc into xhT_d
-  void* xhT_d = nullptr;
   void* zero16_d = nullptr;             // 16 zero elements, never written after the build
   int64_t n_xh_tr = 0;
   int64_t near_matvec_bytes = 0;    // matrix bytes streamed by the near-field kernel
@@ -218,12 +230,14 @@ struct dh2_problem {
   }
   bool own_stream = false;               // created by dh2_build_many, destroyed with the handle
   ~dh2_problem() {
-    if (stream) hipStreamSynchronize(stream);
-    else hipDeviceSynchronize();
+    // Products may still run on streams other than the handle's (per-call
+    // streams of dh2_matvec_stream, branches of a batch graph): wait for the
+    // whole device before the memory goes back to the pool.
+    (void)hipDeviceSynchronize();
     for (void* p : allocs) (void)hipFreeAsync(p, stream);
-    if (stream) hipStreamSynchronize(stream);
-    else hipDeviceSynchronize();
-    if (own_stream && stream) hipStreamDestroy(stream);
+    if (stream) (void)hipStreamSynchronize(stream);
+    else (void)hipDeviceSynchronize();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
   void sync() {
     HIPCHK(hipStreamSynchronize(stream));
@@ -235,13 +249,15 @@ struct dh2_problem {
 namespace {
 
 // ---- matvec schedule (begin) ----
-// Order of the rows of a launch with one workgroup per row (k_mv_rows_mfma maps
-// workgroup b to list entry xcd q + min(xcd, rm) + (b >> 3), xcd = b & 7, with
-// n = 8 q + rm): the rows, longest first, are dealt to the 8 XCDs in snake
-// order (the last partial round forward), so the per-XCD totals are balanced,
-// and each XCD's contiguous share starts with its longest rows.  Returns the
-// row indices in list order.
-std::vector<int64_t> xcd_balanced_order(const std::vector<double>& work) {
+// Order of the rows of a block-row launch (k_mv_rows_mfma: XCD x runs the
+// list entries [off[x], off[x + 1]) in order): the rows, longest first, are
+// dealt to the 8 XCDs in snake order (the last partial round forward), so the
+// per-XCD counts and totals are balanced and each XCD starts with its longest
+// rows.  Returns the row indices in list order and fills the split.  (Rows in
+// cluster order cut into 8 equal-work ranges, so that neighbouring clusters
+// share right-hand-side rows in one XCD's L2, ran the near field at n = 131k
+// in 10.8 ms against 9.3 ms.)
+std::vector<int64_t> xcd_balanced_order(const std::vector<double>& work, XcdSplit& split) {
   const int64_t n = (int64_t)work.size();
   std::vector<int64_t> by(n);
   std::iota(by.begin(), by.end(), (int64_t)0);
@@ -255,7 +271,13 @@ std::vector<int64_t> xcd_balanced_order(const std::vector<double>& work) {
   }
   std::vector<int64_t> out;
   out.reserve(n);
-  for (int x = 0; x < 8; ++x) out.insert(out.end(), share[x].begin(), share[x].end());
+  split.width = 0;
+  for (int x = 0; x < 8; ++x) {
+    split.off[x] = (int32_t)out.size();
+    split.width = std::max(split.width, (int32_t)share[x].size());
+    out.insert(out.end(), share[x].begin(), share[x].end());
+  }
+  split.off[8] = (int32_t)out.size();
   return out;
 }
 
@@ -354,6 +376,21 @@ struct Builder {
       i0 = i1;
     }
   }
+  // QR flops of fold tasks (see dh2_stats.qr_flops); pieces indexed by the tasks
+  void count_folds(const std::vector<FoldTask>& ts, const std::vector<FoldPiece>& ps) {
+    for (const FoldTask& t : ts) {
+      double M = 0;
+      for (int32_t e = t.piece_begin; e < t.piece_end; ++e) M += ps[e].rows;
+      const double n = t.n;
+      double f = 8.0 * M * n * n;
+      if (t.init_zero) {
+        const double r = std::min(M, n);
+        f -= 8.0 / 3.0 * r * r * r;
+      }
+      h.stats.qr_flops += f;
+    }
+  }
+  int64_t n_coupling_gen = 0;   // S_b generated during the build
   void free_tmp(std::vector<void*>& tmp) {
     h.sync();
     for (void* x : tmp) h.release(x);
@@ -488,6 +525,8 @@ struct Builder {
         }
         std::vector<void*> tmp;
         gemm(gd, tmp);
+        count_folds(tasks, pieces);
+        ++h.stats.batches_basis_weights;
         launch_fold<double>(upload_tmp(tasks, tmp), (int64_t)tasks.size(), upload_tmp(pieces, tmp), k,
                             h.stream);
         h.check_launch();
@@ -505,6 +544,7 @@ struct Builder {
       const AdmBlock& b = p.adm[blocks[i]];
       cd[i] = {(int32_t)b.t, (int32_t)b.s, gdir(b.t, b.c)};
     }
+    n_coupling_gen += (int64_t)cd.size();
     launch_coupling<double>(upload_tmp(cd, tmp), (int64_t)cd.size(), ct, p.kappa, h.box_d, h.dirs_d,
                             dst, h.stream);
     h.check_launch();
@@ -525,6 +565,7 @@ struct Builder {
       C64* T1 = S + (size_t)(b1 - b0) * k * k;
       C64* T2 = T1 + (size_t)(b1 - b0) * k * k;
       std::vector<void*> tmp;
+      ++h.stats.batches_block_weights;
       gen_couplings(blocks, S, tmp);
       std::vector<GemmDesc> g1, g2;
       std::vector<FrobDesc> fd;
@@ -663,7 +704,7 @@ struct Builder {
       }
       // batches over (slot, piece) in order
       size_t a0 = 0, e0 = 0;
-      std::vector<uint8_t> started(qs.size(), 0);
+      std::vector<uint8_t> started(qs.size(), 0), straddled(qs.size(), 0);
       while (a0 < qs.size()) {
         if (e0 >= srcs[a0].size()) {  // slot without pieces: rank 0, Zhat never read
           ++a0;
@@ -695,6 +736,14 @@ struct Builder {
           e = 0;
         }
         if (items.empty()) throw Fail{DH2_ERR_OOM, "workspace too small for one coupling piece"};
+        ++(row ? h.stats.batches_total_weights_row : h.stats.batches_total_weights_col);
+        // a slot whose rows are folded over more than one batch
+        for (const Item& it : items)
+          if (it.e0 > 0 || it.e1 < srcs[it.a].size())
+            if (!straddled[it.a]) {
+              straddled[it.a] = 1;
+              ++h.stats.slots_straddled;
+            }
         std::vector<void*> tmp;
         gen_couplings(sblocks, Sbuf, tmp);
         std::vector<GemmDesc> gd;
@@ -802,6 +851,9 @@ struct Builder {
           started[it.a] = 1;
         }
         pieces.insert(pieces.end(), p2.begin(), p2.end());
+        count_folds(t1, pieces);
+        for (const auto& tier : tiers) count_folds(tier, pieces);
+        count_folds(t2, pieces);
         FoldPiece* pd = upload_tmp(pieces, tmp);
         if (!t1.empty()) launch_fold<double>(upload_tmp(t1, tmp), (int64_t)t1.size(), pd, k, h.stream);
         for (const auto& tier : tiers)
@@ -933,6 +985,8 @@ struct Builder {
           sv.push_back(st);
         }
         if (maxm > 256) throw Fail{DH2_ERR_ARG, "truncation matrix with more than 256 rows"};
+        ++h.stats.batches_truncation;
+        count_folds(ft, fp);
         gemm(g1, tmp);
         gemm(g2, tmp);
         if (!ft.empty()) {
@@ -1016,6 +1070,7 @@ struct Builder {
       C64* S = (C64*)ws;
       C64* T = S + (size_t)(b1 - b0) * k * k;
       std::vector<void*> tmp;
+      ++h.stats.batches_projection;
       gen_couplings(blocks, S, tmp);
       std::vector<GemmDesc> g1, g2;
       for (int64_t b = b0; b < b1; ++b) {
@@ -1099,24 +1154,35 @@ struct Builder {
     const bool f32 = h.precision != DH2_FP64;
     const int64_t es = f32 ? (int64_t)sizeof(z32) : (int64_t)sizeof(C64);
     auto at = [es](const void* base, int64_t e) -> char* { return (char*)base + e * es; };
-    auto valloc = [&](int64_t elems) -> char* { return h.alloc<char>((size_t)std::max<int64_t>(elems, 1) * es); };
     auto Qr = [&](int64_t q) -> const void* { return f32 ? h.Qr32[q] : (const void*)h.Qr_ptr[q]; };
     auto Qc = [&](int64_t q) -> const void* { return f32 ? h.Qc32[q] : (const void*)h.Qc_ptr[q]; };
-    h.Xp_d = valloc(n * nr);
-    h.XT_d = valloc(n * nr);
-    h.Yp_d = valloc(n * nr);
-    std::vector<int64_t> xo(ns, -1), yo(ns, -1);
-    int64_t xt = 0, yt = 0;
+    std::vector<int64_t> xo(ns, -1), yo(ns, -1), xro(ns, -1);
+    int64_t xt = 0, yt = 0, xrows = 0;
     for (int64_t q = 0; q < ns; ++q) {
       if (h.rank_col[q] > 0) { xo[q] = xt; xt += (int64_t)h.rank_col[q] * nr; }
       if (h.rank_row[q] > 0) { yo[q] = yt; yt += (int64_t)h.rank_row[q] * nr; }
+      if (h.rank_col[q] > 0) { xro[q] = xrows; xrows += h.rank_col[q]; }
     }
-    char* xh = valloc(xt);
-    char* yh = valloc(yt);
-    h.xh_d = xh;
-    h.yh_d = yh;
-    char* Xp = (char*)h.Xp_d;
-    char* Yp = (char*)h.Yp_d;
+    // staging arena: Xp, XT, Yp (n x nr), slot vectors x_sc, y_tc and the
+    // row-major slot vectors xhT, each 256-byte aligned
+    const int64_t sizes[6] = {n * nr, n * nr, n * nr, xt, yt, xrows * nr};
+    size_t offs[6], total = 0;
+    for (int i = 0; i < 6; ++i) {
+      offs[i] = total;
+      total += ((size_t)std::max<int64_t>(sizes[i], 1) * es + 255) / 256 * 256;
+    }
+    h.stage_bytes = total;
+    h.stage_d = h.alloc<char>(total);
+    char* Xp = h.stage_d + offs[0];
+    char* XT = h.stage_d + offs[1];
+    char* Yp = h.stage_d + offs[2];
+    char* xh = h.stage_d + offs[3];
+    char* yh = h.stage_d + offs[4];
+    char* xhT = h.stage_d + offs[5];
+    h.mv_own.Xp = Xp;
+    h.mv_own.XT = XT;
+    h.mv_own.Yp = Yp;
+    h.mv_own.xhT = xhT;
     std::vector<MvOut> outs;
     std::vector<MvTerm> terms;
     h.mv_phases.clear();
@@ -1157,19 +1223,12 @@ struct Builder {
     // coupling: its own kernel, one entry per row slot.  The matrix-core form
     // reads x_sc from a row-major copy: column slot q occupies rows
     // [xro[q], xro[q] + k_q) of xhT.
-    std::vector<int64_t> xro(ns, -1);
     std::vector<SlotT> xtr;
-    int64_t xrows = 0;
     for (int64_t q = 0; q < ns; ++q)
-      if (h.rank_col[q] > 0) {
-        xro[q] = xrows;
-        xtr.push_back({at(xh, xo[q]), xrows, h.rank_col[q], 0});
-        xrows += h.rank_col[q];
-      }
-    h.xhT_d = valloc(xrows * nr);
+      if (h.rank_col[q] > 0) xtr.push_back({at(xh, xo[q]), xro[q], h.rank_col[q], 0});
     h.zero16_d = h.alloc<C64>(16);
     HIPCHK(hipMemsetAsync(h.zero16_d, 0, 16 * sizeof(C64), h.stream));
-    std::vector<MfRow> mrows;
+    std::vector<MfRow> mrows, coup_rows, near_rows;
     std::vector<NearSeg> msegs;
     for (int64_t q = 0; q < ns; ++q)
       if (h.rank_row[q] > 0) {
@@ -1193,13 +1252,10 @@ struct Builder {
         for (int32_t e = mrows[i].seg_begin; e < mrows[i].seg_end; ++e) w += (double)msegs[e].lda * msegs[e].ncols;
         work[i] = w;
       }
-      std::vector<MfRow> ordered;
-      ordered.reserve(mrows.size());
-      for (int64_t i : xcd_balanced_order(work)) ordered.push_back(mrows[i]);
-      h.coup_mf_rows_d = h.upload(ordered);
+      coup_rows.reserve(mrows.size());
+      for (int64_t i : xcd_balanced_order(work, h.coup_split)) coup_rows.push_back(mrows[i]);
     }
     h.coup_mf_segs_d = h.upload(msegs);
-    h.xh_tr_d = h.upload(xtr);
     h.n_xh_tr = (int64_t)xtr.size();
     // backward, top-down: y_{t'c'} += F_{t'c} y_tc
     group = 3;
@@ -1258,7 +1314,7 @@ struct Builder {
     h.near_segs_d = h.upload(nsegs);
     h.n_near_rows = (int64_t)nrows.size();
     {
-      std::vector<MfRow> mf;
+      std::vector<MfRow>& mf = near_rows;
       mf.reserve(nrows.size());
       std::vector<double> work(nrows.size());
       for (size_t i = 0; i < nrows.size(); ++i) {
@@ -1266,11 +1322,10 @@ struct Builder {
         for (int32_t e = nrows[i].seg_begin; e < nrows[i].seg_end; ++e) w += (double)nrows[i].nr * nsegs[e].ncols;
         work[i] = w;
       }
-      for (int64_t i : xcd_balanced_order(work)) {
+      for (int64_t i : xcd_balanced_order(work, h.near_split)) {
         const NearRow& r = nrows[i];
         mf.push_back({at(Yp, r.row0), (int32_t)n, r.nr, r.seg_begin, r.seg_end});
       }
-      h.near_mf_rows_d = h.upload(mf);
     }
     h.near_matvec_bytes = nbytes * es;
     // leaf output: Y_t += Q_tc y_tc (after the near field)
@@ -1289,8 +1344,11 @@ struct Builder {
       if (o.term_end > o.term_begin) outs.push_back(o);
     }
     end_phase();
-    h.mv_outs_d = h.upload(outs);
-    h.mv_terms_d = h.upload(terms);
+    h.mv_own.outs = h.upload(outs);
+    h.mv_own.terms = h.upload(terms);
+    h.mv_own.near_rows = h.upload(near_rows);
+    h.mv_own.coup_rows = h.upload(coup_rows);
+    h.mv_own.xh_tr = h.upload(xtr);
   }
   // ---- matvec schedule (end) ----
 };
@@ -1461,6 +1519,7 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   bd.projection();
   h.sync();
   h.stats.ms_projection = now_ms() - t0;
+  h.stats.coupling_regeneration = p.adm.empty() ? 0.0 : (double)bd.n_coupling_gen / (double)p.adm.size();
   // release build-only buffers
   h.R_d = bd.R_d;
   h.Zr_d = bd.Zr_d;
@@ -1626,7 +1685,8 @@ namespace {
 // 5 leaf output, 6 scatter) and ev[7] at the end.
 // ---- matvec schedule (begin) ----
 template <typename R>
-void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st) {
+void run_matvec_t(dh2_problem* h, const dh2_problem::MvView& v, const void* X, void* Y, int nrhs, hipEvent_t* ev,
+                  hipStream_t st) {
   const int64_t n = h->plan.n;
   auto mark = [&](int g) {
     if (ev) HIPCHK(hipEventRecord(ev[g], st));
@@ -1634,35 +1694,34 @@ void run_matvec_t(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* 
   auto terms = [&](int g) {
     for (const auto& ph : h->mv_phases)
       if (ph.group == g && ph.out_end > ph.out_begin)
-        launch_mv_terms<R>(h->mv_outs_d + ph.out_begin, ph.out_end - ph.out_begin, h->mv_terms_d,
-                                nrhs, st);
+        launch_mv_terms<R>(v.outs + ph.out_begin, ph.out_end - ph.out_begin, v.terms, nrhs, st);
   };
   // every right-hand-side count runs the matrix-core block rows on row-major
   // copies (columns past nrhs read zeros)
   mark(0);
-  launch_mv_permute<R>(X, h->Xp_d, h->perm_d, n, nrhs, 1, st);
-  launch_mv_transpose<R>(h->Xp_d, h->XT_d, n, nrhs, st);
+  launch_mv_permute<R>(X, v.Xp, h->perm_d, n, nrhs, 1, st);
+  launch_mv_transpose<R>(v.Xp, v.XT, n, nrhs, st);
   mark(1);
   terms(1);
-  launch_mv_slot_transpose<R>(h->xh_tr_d, h->n_xh_tr, h->xhT_d, nrhs, st);
+  launch_mv_slot_transpose<R>(v.xh_tr, h->n_xh_tr, v.xhT, nrhs, st);
   mark(2);
-  launch_mv_rows_mfma<R>(h->coup_mf_rows_d, h->n_coup_rows, h->coup_mf_segs_d, h->xhT_d, h->zero16_d, nrhs, 1,
-                         st);
+  launch_mv_rows_mfma<R>(v.coup_rows, h->coup_split, h->coup_mf_segs_d, v.xhT, h->zero16_d, nrhs, 1, st);
   mark(3);
   terms(3);
   mark(4);
-  launch_mv_rows_mfma<R>(h->near_mf_rows_d, h->n_near_rows, h->near_segs_d, h->XT_d, h->zero16_d, nrhs, 0, st);
+  launch_mv_rows_mfma<R>(v.near_rows, h->near_split, h->near_segs_d, v.XT, h->zero16_d, nrhs, 0, st);
   mark(5);
   terms(5);
   mark(6);
-  launch_mv_permute<R>(h->Yp_d, Y, h->perm_d, n, nrhs, 0, st);
+  launch_mv_permute<R>(v.Yp, Y, h->perm_d, n, nrhs, 0, st);
   mark(7);
   HIPCHK(hipGetLastError());
 }
 
 void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st) {
-  if (h->precision != DH2_FP64) run_matvec_t<float>(h, X, Y, nrhs, ev, st);
-  else run_matvec_t<double>(h, X, Y, nrhs, ev, st);
+  const dh2_problem::MvView& v = h->mv_own;
+  if (h->precision != DH2_FP64) run_matvec_t<float>(h, v, X, Y, nrhs, ev, st);
+  else run_matvec_t<double>(h, v, X, Y, nrhs, ev, st);
 }
 // ---- matvec schedule (end) ----
 void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev) {
@@ -1713,6 +1772,8 @@ struct dh2_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~dh2_batch_s() {
+    // a launch of the graph may still run on the batch's stream
+    if (stream) (void)hipStreamSynchronize(stream);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);

@@ -200,14 +200,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF
                                                       const NearSeg* __restrict__ segs,
                                                       const cpx<R>* __restrict__ XT,
                                                       const cpx<R>* __restrict__ zero16, int nrhs,
-                                                      int nrow_total) {
+                                                      XcdSplit split) {
   // KU 4-column slices per step; S register stages (S - 1 steps in flight)
   constexpr int SW = 4 * KU;
-  // XCD-aware order: workgroup b runs on XCD b % 8; XCD x takes the x-th
-  // contiguous share of the rows
+  // XCD-aware order: workgroup b runs on XCD b % 8; XCD x takes its share of
+  // the row list in order
   const int b = blockIdx.x;
-  const int q = nrow_total >> 3, rm = nrow_total & 7, xcd = b & 7;
-  const MfRow rw = rows[xcd * q + min(xcd, rm) + (b >> 3)];
+  const int xcd = b & 7, i = b >> 3;
+  if (i >= split.off[xcd + 1] - split.off[xcd]) return;
+  const MfRow rw = rows[split.off[xcd] + i];
   cpx<R>* __restrict__ Y = (cpx<R>*)rw.y;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -241,37 +242,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF
 #endif
 
 template <typename R>
-void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT,
+void launch_mv_rows_mfma(const MfRow* rows, const XcdSplit& split, const NearSeg* segs, const void* XT,
                          const void* zero16, int nrhs, int role, hipStream_t st) {
-  if (nrows <= 0) return;
+  if (split.width <= 0) return;
   // FP32 with more than 16 right-hand sides: two 16-wide chunks per pass, so
   // the matrix is streamed once per 32 right-hand sides (FP64 accumulators
   // for two chunks would not fit the registers of two waves per SIMD)
-  const dim3 g((unsigned)nrows), b(256);
+  const dim3 g((unsigned)(8 * split.width)), b(256);
   const cpx<R>* xt = (const cpx<R>*)XT;
   const cpx<R>* z = (const cpx<R>*)zero16;
   if constexpr (sizeof(R) == 4) {
     if (nrhs > 16) {
       if (role == 0)
         hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0, 2>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                           (int)nrows);
+                           split);
       else
         hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1, 2>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                           (int)nrows);
+                           split);
       return;
     }
   }
   if (role == 0)
     hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0, 1>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                       (int)nrows);
+                       split);
   else
     hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1, 1>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                       (int)nrows);
+                       split);
 }
-template void launch_mv_rows_mfma<double>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
-                                          int, hipStream_t);
-template void launch_mv_rows_mfma<float>(const MfRow*, int64_t, const NearSeg*, const void*, const void*, int,
-                                         int, hipStream_t);
+template void launch_mv_rows_mfma<double>(const MfRow*, const XcdSplit&, const NearSeg*, const void*, const void*,
+                                          int, int, hipStream_t);
+template void launch_mv_rows_mfma<float>(const MfRow*, const XcdSplit&, const NearSeg*, const void*, const void*,
+                                         int, int, hipStream_t);
 
 // row-major copies of the slot vectors x_sc (k x nrhs, leading dimension k):
 // dst[(row0 + j) * nrhs + r] = src[j + r k]; a workgroup per slot

@@ -49,10 +49,17 @@ struct MfRow {
   int32_t ldy, nr;
   int32_t seg_begin, seg_end;
 };
+// Rows of a block-row launch per XCD: workgroup b runs on XCD b % 8, and XCD
+// x takes the list entries [off[x], off[x + 1]) in order.  The grid has
+// 8 * width workgroups, width = the largest share.
+struct XcdSplit {
+  int32_t off[9];
+  int32_t width;
+};
 // zero16: 16 zero elements (device), read in place of right-hand-side entries
 // outside a segment.  role: 0 near field, 1 coupling (names the kernel only).
 template <typename R>
-void launch_mv_rows_mfma(const MfRow* rows, int64_t nrows, const NearSeg* segs, const void* XT,
+void launch_mv_rows_mfma(const MfRow* rows, const XcdSplit& split, const NearSeg* segs, const void* XT,
                          const void* zero16, int nrhs, int role, hipStream_t st);
 
 // Row-major copy of one slot vector: dst[(row0 + j) * nrhs + r] = src[j + r k].

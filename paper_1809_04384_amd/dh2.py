@@ -59,7 +59,12 @@ class Stats(ctypes.Structure):
                 ("ms_block_weights", ctypes.c_double), ("ms_total_weights", ctypes.c_double),
                 ("ms_truncation", ctypes.c_double), ("ms_projection", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("gemm_flops", ctypes.c_double),
-                ("gemm_launches", ctypes.c_int64)]
+                ("gemm_launches", ctypes.c_int64), ("qr_flops", ctypes.c_double),
+                ("batches_basis_weights", ctypes.c_int64), ("batches_block_weights", ctypes.c_int64),
+                ("batches_total_weights_row", ctypes.c_int64), ("batches_total_weights_col", ctypes.c_int64),
+                ("batches_truncation", ctypes.c_int64),
+                ("batches_projection", ctypes.c_int64), ("slots_straddled", ctypes.c_int64),
+                ("coupling_regeneration", ctypes.c_double)]
 
 
 class PlanSizes(ctypes.Structure):

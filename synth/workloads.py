@@ -54,6 +54,8 @@ WORKLOADS = {
     "dir512": Workload("dir512", "sphere", 8, 6.0, 3, 8, 1e-6, eta=8.0, eta1=1.0),
     "dir2k": Workload("dir2k", "sphere", 16, 8.0, 3, 16, 1e-6, eta=4.0, eta1=1.0),
     "dir8k": Workload("dir8k", "sphere", 32, 16.0, 4, 32, 1e-6, eta=4.0, eta1=2.0),
+    # dir2k at the benchmark's tolerance 1e-4 (rank decisions far from FP32 rounding)
+    "dir2k_t4": Workload("dir2k_t4", "sphere", 16, 8.0, 3, 16, 1e-4, eta=4.0, eta1=1.0),
     # cube [-1,1]^3 (flat cluster boxes on the faces), low frequency and directional
     "cube768": Workload("cube768", "cube", 8, 4.0, 3, 16, 1e-6, eta=2.0),
     "cube1200dir": Workload("cube1200dir", "cube", 10, 4.0, 3, 16, 1e-6, eta=4.0, eta1=2.0),

@@ -38,3 +38,65 @@ def build_handle(name, **kw):
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+H = lambda a: a.conj().T
+
+
+def check_ranks_and_sigma(h, slots, o, label):
+    """Ranks and singular values of both truncation passes against the oracle:
+    singular values to 1e-12 of the largest, ranks equal except at a near-tie
+    of the rank rule (a tail sum within 1e-8 of eps^2)."""
+    for kind, ranks_o, sig_o in (("row", o.rank, o.sig), ("col", o.rankW, o.sigW)):
+        ranks = h.inspect("rank_" + kind)[:, 0].real.astype(int)
+        mism = 0
+        for q, (t, c, flags) in enumerate(slots.tolist()):
+            key = (t, c)
+            if key not in ranks_o:
+                assert ranks[q] == -1
+                continue
+            s_o = sig_o[key]
+            s_g = h.inspect("sigma_" + kind, q)[:, 0].real
+            m = min(len(s_o), len(s_g))
+            if m:
+                assert np.max(np.abs(s_o[:m] - s_g[:m])) <= 1e-12 * s_o[0] + 1e-300, (label, kind, key)
+            if ranks[q] != ranks_o[key]:
+                tail = np.cumsum((s_o ** 2)[::-1])[::-1]
+                eps2 = o.tol ** 2
+                near = np.any(np.abs(tail - eps2) <= 1e-8 * eps2)
+                assert near, (label, kind, key, ranks[q], ranks_o[key])
+                mism += 1
+        say("[gpu] %s %s ranks: %d near-tie mismatches" % (label, kind, mism))
+
+
+def check_weight_invariants(h, slots, o, label):
+    """R^* R and Zhat^* Zhat of every slot (unique although R and Zhat are
+    defined up to a unitary factor) against the oracle."""
+    for q, (t, c, flags) in enumerate(slots.tolist()):
+        R = h.inspect("basis_weight", q)
+        Ro = o.R[(t, c)]
+        G, Go = H(R) @ R, H(Ro) @ Ro
+        assert R.shape[0] <= o.k
+        assert np.linalg.norm(G - Go) <= 1e-12 * np.linalg.norm(Go), (label, "R", q, t, c)
+        for kind, Zo in (("row", o.Zrow), ("col", o.Zcol)):
+            if (t, c) not in Zo:
+                continue
+            Z = h.inspect("total_weight_" + kind, q)
+            G, Go = H(Z) @ Z, H(Zo[(t, c)]) @ Zo[(t, c)]
+            assert Z.shape[0] <= o.k, (label, kind, q)
+            assert np.linalg.norm(G - Go) <= 1e-11 * max(np.linalg.norm(Go), 1e-300), (label, kind, q, t, c)
+
+
+def fp32_rank_shift(sig, r_a, r_b, eps, m=None):
+    """Smallest perturbation Delta (absolute, in the units of sig) of every
+    singular value that moves the Frobenius rank rule from r_a to r_b or back.
+    With T_j = sum_{i >= j} sigma_i^2 (0-based) and j = min(r_a, r_b), Weyl's
+    bound |sigma_i' - sigma_i| <= Delta changes T_j by at most
+    2 Delta sqrt(m) sqrt(T_j) + m Delta^2, so a rank change needs
+    |T_j - eps^2| <= that; the root of the quadratic is returned."""
+    sig = np.asarray(sig, dtype=np.float64)
+    m = len(sig) if m is None else m
+    j = min(r_a, r_b)
+    T = float(np.sum(sig[j:] ** 2))
+    s = np.sqrt(max(T, eps * eps))
+    return (-s + np.sqrt(s * s + abs(T - eps * eps))) / np.sqrt(max(m, 1))

@@ -103,3 +103,32 @@ def test_structure_parity_sphere32k():
     assert np.array_equal(ex["perm"], st.perm)
     assert [tuple(r) for r in ex["adm"].tolist()] == [tuple(map(int, a)) for a in st.adm]
     assert [tuple(r) for r in ex["near"].tolist()] == [tuple(map(int, a)) for a in st.near]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of dh2_options and dh2_stats have the sizes and field
+    offsets of the C declarations (compiled here with the host compiler)."""
+    import subprocess
+    fields_s = [f for f, _ in dh2.Stats._fields_]
+    fields_o = [f for f, _ in dh2.Options._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "dh2.h"', "int main(void) {",
+           'printf("%zu %zu\\n", sizeof(dh2_stats), sizeof(dh2_options));']
+    for f in fields_s:
+        src.append('printf("s %s %%zu\\n", offsetof(dh2_stats, %s));' % (f, f))
+    for f in fields_o:
+        src.append('printf("o %s %%zu\\n", offsetof(dh2_options, %s));' % (f, f))
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, stdout=subprocess.PIPE, text=True).stdout.split("\n")
+    size_s, size_o = map(int, out[0].split())
+    assert size_s == ctypes.sizeof(dh2.Stats)
+    assert size_o == ctypes.sizeof(dh2.Options)
+    for line in out[1:]:
+        if not line:
+            continue
+        kind, name, off = line.split()
+        cls = dh2.Stats if kind == "s" else dh2.Options
+        assert getattr(cls, name).offset == int(off), (kind, name)

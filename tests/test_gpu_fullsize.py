@@ -9,6 +9,9 @@ computes one by one is compared directly:
     matrix G (Q7 x Q7 far, Q16 near, singular self term), within the
     interpolation + recompression error (1e-2 relative, a consistency bound:
     the tight FP64 parity is checked element by element at n <= 2048);
+  - the rows of a seeded sample of leaf clusters against the interpolated
+    matrix G_int (the error the recompression tolerance controls, Section 5),
+    formed by the oracle on demand: within tol for the FP64 and FP32 forms;
 and properties that hold at any size:
   - linearity of the matvec (1e-12);
   - the FP32 form within 1e-4 of the FP64 form over the full n x nrhs result.
@@ -77,8 +80,11 @@ def test_full_size(name):
     n = len(T)
     nrhs = w.nrhs
     say("[gpu] full-size %s: n=%d nrhs=%d, oracle structure" % (name, n, nrhs))
-    st = _structure(w, V, T)
-    tri = triangle_data(V, T)
+    from oracle.dh2 import OracleDH2
+    o = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, lazy=True)
+    st, tri = o.st, o.tri
+    leaves = [t for t in range(len(st.first)) if st.is_leaf(t)]
+    pick = [leaves[i] for i in sorted(np.random.default_rng(2).choice(len(leaves), size=3, replace=False).tolist())]
     say("[gpu] dh2_build FP64 %s" % name)
     h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 2))
     try:
@@ -104,6 +110,11 @@ def test_full_size(name):
         err = rel(Y[:, rows].T, Yref)
         say("[gpu] %s sampled rows vs Galerkin matrix: rel err %.3e" % (name, err))
         assert err <= 1e-2
+        say("[gpu] %s oracle rows of the interpolated matrix" % name)
+        irows, Yint = o.interp_rows(pick, X.T)
+        err_int = rel(Y[:, irows].T, Yint)
+        say("[gpu] %s sampled rows vs interpolated matrix: rel err %.3e (tol %g)" % (name, err_int, w.tol))
+        assert err_int <= w.tol
         # linearity (two right-hand sides, or the first two of the batch)
         X1 = synth.complex_gaussian(n, 2, seed=5)
         Y1 = _matvec(h, X1, np.complex128)
@@ -122,6 +133,9 @@ def test_full_size(name):
             err32 = rel(Y32, Y)
             say("[gpu] %s FP32 vs FP64: rel diff %.3e" % (name, err32))
             assert err32 <= 1e-4
+            err32_int = rel(Y32[:, irows].T, Yint)
+            say("[gpu] %s FP32 sampled rows vs interpolated matrix: rel err %.3e" % (name, err32_int))
+            assert err32_int <= w.tol
         finally:
             h32.free()
 

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_common import say, oracle_for, build_handle, rel
+from tests.gpu_common import (say, oracle_for, build_handle, rel, check_ranks_and_sigma,
+                               check_weight_invariants, fp32_rank_shift)
 
 pytestmark = pytest.mark.gpu
 
@@ -112,27 +113,7 @@ def test_bases_transfers_weights_elementwise(name):
 def test_ranks_and_singular_values(name):
     o = oracle_for(name)
     h, slots = handle(name)
-    for kind, ranks_o, sig_o in (("row", o.rank, o.sig), ("col", o.rankW, o.sigW)):
-        ranks = h.inspect("rank_" + kind)[:, 0].real.astype(int)
-        mism = 0
-        for q, (t, c, flags) in enumerate(slots.tolist()):
-            key = (t, c)
-            if key not in ranks_o:
-                assert ranks[q] == -1
-                continue
-            s_o = sig_o[key]
-            s_g = h.inspect("sigma_" + kind, q)[:, 0].real
-            m = min(len(s_o), len(s_g))
-            if m:
-                assert np.max(np.abs(s_o[:m] - s_g[:m])) <= 1e-12 * s_o[0] + 1e-300
-            if ranks[q] != ranks_o[key]:
-                # only a near-tie at the threshold may change a rank
-                tail = np.cumsum((s_o ** 2)[::-1])[::-1]
-                eps2 = o.tol ** 2
-                near = np.any(np.abs(tail - eps2) <= 1e-8 * eps2)
-                assert near, (kind, key, ranks[q], ranks_o[key])
-                mism += 1
-        say("[gpu] %s %s ranks: %d near-tie mismatches" % (name, kind, mism))
+    check_ranks_and_sigma(h, slots, o, name)
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -146,24 +127,10 @@ def test_couplings_and_weight_invariants(name):
         S = h.inspect("coupling", b)
         ref = o.coupling(b)
         assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(ref))
-    H = lambda a: a.conj().T
-    for q, (t, c, flags) in enumerate(slots.tolist()):
-        R = h.inspect("basis_weight", q)
-        Ro = o.R[(t, c)]
-        G, Go = H(R) @ R, H(Ro) @ Ro
-        # rows: the numerical rank, at most k (the oracle keeps min(rows, k))
-        assert R.shape[0] <= o.k
-        assert np.linalg.norm(G - Go) <= 1e-12 * np.linalg.norm(Go), ("R", q, t, c)
-        for kind, Zo in (("row", o.Zrow), ("col", o.Zcol)):
-            if (t, c) not in Zo:
-                continue
-            Z = h.inspect("total_weight_" + kind, q)
-            G, Go = H(Z) @ Z, H(Zo[(t, c)]) @ Zo[(t, c)]
-            assert Z.shape[0] <= o.k, (kind, q)
-            assert np.linalg.norm(G - Go) <= 1e-11 * max(np.linalg.norm(Go), 1e-300), (kind, q, t, c)
+    check_weight_invariants(h, slots, o, name)
 
 
-FP32_CASES = ["dir512", "sphere2k", "cube1200dir", "dir2k"]
+FP32_CASES = ["dir512", "sphere2k", "cube1200dir", "dir2k", "dir2k_t4"]
 
 
 @pytest.mark.parametrize("name", FP32_CASES)
@@ -180,15 +147,29 @@ def test_fp32_form_matches_fp64(name):
     V, T = synth.make_mesh(w)
     say("[gpu] dh2_build FP32 workload=%s n=%d" % (name, len(T)))
     h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32, max_nrhs=40)
-    h64, _ = handle(name)
+    h64, h64_slots = handle(name)
     try:
-        # the recompression products run in FP32: ranks may move at singular
-        # values within FP32 rounding of the threshold, so they are reported,
-        # and the products below carry the bound
-        for kind in ("row", "col"):
-            r32, r64 = h.inspect("rank_" + kind), h64.inspect("rank_" + kind)
-            say("[gpu] %s FP32 %s ranks differing from FP64: %d of %d"
-                % (name, kind, int(np.sum(r32 != r64)), r32.size))
+        # the recompression products run in FP32: a rank may move only where
+        # the FP64 singular values put the rank rule within an FP32-sized
+        # perturbation of its threshold (fp32_rank_shift: the smallest uniform
+        # change of the singular values that moves the rank, bounded by 1e-5
+        # of the largest, about 170 units of FP32 rounding), and only in a few
+        # slots
+        plan_slots = h64_slots
+        for kind, sig_o in (("row", o.sig), ("col", o.sigW)):
+            r32 = h.inspect("rank_" + kind)[:, 0].real.astype(int)
+            r64 = h64.inspect("rank_" + kind)[:, 0].real.astype(int)
+            diff = np.nonzero(r32 != r64)[0]
+            worst = 0.0
+            for q in diff.tolist():
+                t, c, _ = plan_slots[q].tolist()
+                s_o = sig_o[(t, c)]
+                shift = fp32_rank_shift(s_o, r32[q], r64[q], o.tol) / max(s_o[0], 1e-300)
+                worst = max(worst, shift)
+                assert shift <= 1e-5, (name, kind, q, r32[q], r64[q], shift)
+            say("[gpu] %s FP32 %s ranks differing from FP64: %d of %d, largest needed shift %.2e"
+                % (name, kind, len(diff), r32.size, worst))
+            assert len(diff) <= max(3, r32.size // 50)
         nb = len(o.st.near)
         for b in list(range(0, nb, max(1, nb // 20))) + [nb - 1]:
             N = h.inspect("near", b)
