@@ -135,6 +135,24 @@ dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs);
  * time (they share its work buffers).  Errors as dh2_matvec. */
 dh2_status dh2_matvec_stream(dh2_handle h, const void* X, void* Y, int nrhs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dh2_matvec
+ * enqueued on `stream` (NULL = the default stream) with its staging (gathered
+ * X, its row-major copy, Y in cluster order, the coefficient vectors) in a
+ * static device array of the library instead of the handle's buffers.  The
+ * array holds 64 MiB per GPU, is allocated when the library is loaded on a
+ * device and is kept until the process ends; this call allocates and frees
+ * nothing.  The handle's staging for max_nrhs right-hand sides must fit
+ * (about 6 n max_nrhs elements of the handle's complex type plus the
+ * coefficient vectors); larger handles get DH2_ERR_ARG (build them with a
+ * smaller max_nrhs).  All calls on one GPU share the array, whatever the
+ * handle: calls that overlap in time on one GPU race and give wrong results.
+ * Nothing in the array needs clearing between calls (every call writes each
+ * staging entry before reading it).  The result equals dh2_matvec's bit for
+ * bit.  Errors: as dh2_matvec; DH2_ERR_ARG also when the staging does not fit
+ * or the current device is not the handle's. */
+dh2_status dh2_matvec_noalloc(dh2_handle h, const void* X, void* Y, int nrhs, void* stream);
+
 /* dh2_matvec with per-phase timing, for benchmarks: runs the same kernels,
  * records HIP events on the handle's stream between the phases and waits for
  * them (this call synchronises).  phase_ms[7] receives milliseconds of:

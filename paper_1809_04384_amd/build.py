@@ -28,6 +28,7 @@ SOURCES = [
     ("api.cpp", COMMON + ["-ffp-contract=off"], False),
     ("kernels.hip", COMMON + HIPFLAGS, True),
     ("matvec.hip", COMMON + HIPFLAGS, True),
+    ("scratch.hip", COMMON + HIPFLAGS, True),
 ]
 
 

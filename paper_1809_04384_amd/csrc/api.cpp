@@ -32,6 +32,7 @@
 #include "kernels.hpp"
 #include "matvec.hpp"
 #include "plan.hpp"
+#include "scratch.hpp"
 
 using namespace dh2;
 
@@ -167,7 +168,9 @@ struct dh2_problem {
   // matvec schedule.  A view holds the device addresses one product uses: the
   // descriptor lists and the staging buffers they point into (gathered X Xp,
   // its row-major copy XT, Y in cluster order Yp, the row-major slot vectors
-  // xhT), here in the handle's staging arena.
+  // xhT).  `own` points into the handle's staging arena; `scr` holds the same
+  // descriptors relocated into the library's static scratch array (the
+  // allocation-free product), when the arena fits there.
   struct MvView {
     MvOut* outs = nullptr;
     MvTerm* terms = nullptr;
@@ -179,7 +182,8 @@ struct dh2_problem {
     void* Yp = nullptr;
     void* xhT = nullptr;
   };
-  MvView mv_own;
+  MvView mv_own, mv_scr;
+  bool has_scr = false;
   char* stage_d = nullptr;               // staging arena of the handle's own products
   size_t stage_bytes = 0;
   struct Phase { int64_t out_begin, out_end; int group; };
@@ -1349,6 +1353,36 @@ struct Builder {
     h.mv_own.near_rows = h.upload(near_rows);
     h.mv_own.coup_rows = h.upload(coup_rows);
     h.mv_own.xh_tr = h.upload(xtr);
+    // The same descriptors relocated into the static scratch array (device
+    // address of this device's copy), for the allocation-free product: every
+    // pointer into the staging arena moves by the same offset; matrix
+    // pointers stay.
+    size_t scr_bytes = 0;
+    char* scr = (char*)scratch_region(&scr_bytes);
+    h.has_scr = scr != nullptr && h.stage_bytes <= scr_bytes;
+    if (h.has_scr) {
+      char* const base = h.stage_d;
+      const size_t len = h.stage_bytes;
+      auto rel = [&](auto* ptr) {
+        char* c = (char*)ptr;
+        using P = decltype(ptr);
+        return (c >= base && c < base + len) ? (P)(scr + (c - base)) : ptr;
+      };
+      for (MvOut& o : outs) o.y = rel(o.y);
+      for (MvTerm& t : terms) t.x = rel(t.x);
+      for (MfRow& r : near_rows) r.y = rel(r.y);
+      for (MfRow& r : coup_rows) r.y = rel(r.y);
+      for (SlotT& t : xtr) t.src = rel(t.src);
+      h.mv_scr.outs = h.upload(outs);
+      h.mv_scr.terms = h.upload(terms);
+      h.mv_scr.near_rows = h.upload(near_rows);
+      h.mv_scr.coup_rows = h.upload(coup_rows);
+      h.mv_scr.xh_tr = h.upload(xtr);
+      h.mv_scr.Xp = rel(Xp);
+      h.mv_scr.XT = rel(XT);
+      h.mv_scr.Yp = rel(Yp);
+      h.mv_scr.xhT = rel(xhT);
+    }
   }
   // ---- matvec schedule (end) ----
 };
@@ -1718,8 +1752,9 @@ void run_matvec_t(dh2_problem* h, const dh2_problem::MvView& v, const void* X, v
   HIPCHK(hipGetLastError());
 }
 
-void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st) {
-  const dh2_problem::MvView& v = h->mv_own;
+void run_matvec(dh2_problem* h, const void* X, void* Y, int nrhs, hipEvent_t* ev, hipStream_t st,
+                bool scratch = false) {
+  const dh2_problem::MvView& v = scratch ? h->mv_scr : h->mv_own;
   if (h->precision != DH2_FP64) run_matvec_t<float>(h, v, X, Y, nrhs, ev, st);
   else run_matvec_t<double>(h, v, X, Y, nrhs, ev, st);
 }
@@ -1741,6 +1776,37 @@ dh2_status dh2_matvec(dh2_handle h, const void* X, void* Y, int nrhs) {
   }
   try {
     run_matvec(h, X, Y, nrhs, nullptr);
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+  return DH2_OK;
+}
+
+dh2_status dh2_matvec_noalloc(dh2_handle h, const void* X, void* Y, int nrhs, void* stream) {
+  if (!h || !X || !Y) {
+    g_err = "NULL handle or vector";
+    return DH2_ERR_ARG;
+  }
+  if (nrhs < 1 || nrhs > h->max_nrhs) {
+    g_err = "nrhs out of range [1, max_nrhs]";
+    return DH2_ERR_ARG;
+  }
+  if (!h->has_scr) {
+    size_t lim = 0;
+    (void)scratch_region(&lim);
+    g_err = "the product's staging of this handle (" + std::to_string(h->stage_bytes >> 20) +
+            " MiB for max_nrhs = " + std::to_string(h->max_nrhs) + ") exceeds the static scratch of " +
+            std::to_string(lim >> 20) + " MiB (or its address lookup failed); build with a smaller max_nrhs";
+    return DH2_ERR_ARG;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device) {
+    (void)hipGetLastError();
+    g_err = "the current device is not the handle's device";
+    return DH2_ERR_ARG;
+  }
+  try {
+    run_matvec(h, X, Y, nrhs, nullptr, (hipStream_t)stream, true);
   } catch (const Fail& f) {
     return fail(f);
   }

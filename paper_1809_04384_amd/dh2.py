@@ -24,7 +24,7 @@ INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col":
 EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_free", "dh2_last_error",
             "dh2_get_stats", "dh2_plan_create", "dh2_plan_get_sizes", "dh2_plan_export",
             "dh2_plan_free", "dh2_inspect", "dh2_batch_create", "dh2_batch_run", "dh2_batch_free",
-            "dh2_matvec_stream", "dh2_build_many"]
+            "dh2_matvec_stream", "dh2_build_many", "dh2_matvec_noalloc"]
 
 
 class Dh2Error(RuntimeError):
@@ -104,13 +104,14 @@ def load():
     lib.dh2_inspect.argtypes = [P, I32, I64, P, P, P]
     lib.dh2_batch_create.argtypes = [P, P, P, I32, I32, P, P]
     lib.dh2_matvec_stream.argtypes = [P, P, P, I32, P]
+    lib.dh2_matvec_noalloc.argtypes = [P, P, P, I32, P]
     lib.dh2_build_many.argtypes = [I32, P, P, P, P, P, P, P, I32, P]
     lib.dh2_batch_run.argtypes = [P]
     lib.dh2_batch_free.argtypes = [P]
     lib.dh2_batch_free.restype = None
     for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_get_stats", "dh2_plan_create",
                  "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect", "dh2_batch_create", "dh2_batch_run",
-                 "dh2_matvec_stream", "dh2_build_many"):
+                 "dh2_matvec_stream", "dh2_build_many", "dh2_matvec_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -188,6 +189,12 @@ class Handle:
         products of a batch issued one after another, for comparison)."""
         lib = load()
         _check(lib.dh2_matvec_stream(self._h, X.data_ptr(), Y.data_ptr(), X.shape[0], stream))
+
+    def matvec_noalloc(self, X, Y, stream=None):
+        """Handle.matvec through dh2_matvec_noalloc: the staging lives in the
+        library's static device scratch (no allocation); calls on one GPU must
+        not overlap."""
+        _check(load().dh2_matvec_noalloc(self._h, X.data_ptr(), Y.data_ptr(), X.shape[0], stream))
 
     def matvec_ptr(self, x_ptr, y_ptr, nrhs):
         """Y = Gtilde X for raw device pointers (column-major n x nrhs complex)."""
