@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 form")
     ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-control build")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank form")
+    ap.add_argument("--learned-cube", default="cube7k_m6", help="cube workload of the learned-rank family")
     ap.add_argument("--batch", type=int, default=64, metavar="COUNT",
                     help="problems of the batching form (the recipe's 64; 0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -391,6 +393,64 @@ def spectral_form(args, dh2, torch):
     }
 
 
+def learned_form(args, w, V, T, X, Y64, dh2, torch, results, st_exact, build_exact):
+    """The learned-rank form on the benchmark workload (FP64): one build with
+    the predictor sizing randomized truncations, its truncation time and build
+    time against the exact FP64 form's, sketch and fallback counts, ranks, and
+    the difference of its n x nrhs product from the exact form's; then the
+    same comparison on a side-2 cube of the learned-rank family (k = 216)."""
+    nrhs = X.shape[0]
+    Xd = torch.from_numpy(X).to("cuda:0")
+    Yd = torch.empty_like(Xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1),
+                   rank_mode=dh2.RANKS_LEARNED)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    st = h.stats()
+    h.matvec(Xd, Yd)
+    torch.cuda.synchronize()
+    err = (torch.linalg.vector_norm(Yd - Y64) / torch.linalg.vector_norm(Y64)).item()
+    results["learned"] = Yd.cpu().numpy()
+    h.free()
+    out = {"workload": w.name, "build_s": round(tb, 3), "build_s_exact": round(build_exact, 3),
+           "truncation_ms": round(st["ms_truncation"], 1), "truncation_ms_exact": round(st_exact["ms_truncation"], 1),
+           "predict_ms": round(st["ms_rank_predict"], 2), "sketch_slots": st["sketch_slots"],
+           "fallbacks": st["sketch_fallbacks"], "rank_mean_row": round(st["rank_mean_row"], 3),
+           "rank_mean_row_exact": round(st_exact["rank_mean_row"], 3), "rel_diff_vs_exact": err}
+    log("learned form: build %.2f s (exact %.2f s), truncation %.0f ms (exact %.0f ms), %d sketches, %d fallbacks, "
+        "rel. diff vs exact %.2e" % (tb, build_exact, st["ms_truncation"], st_exact["ms_truncation"],
+                                    st["sketch_slots"], st["sketch_fallbacks"], err))
+    wc = synth.WORKLOADS[args.learned_cube]
+    Vc, Tc = synth.make_mesh(wc)
+    Xc = torch.from_numpy(synth.complex_gaussian(len(Tc), 4, seed=0)).to("cuda:0")
+    cube = {"workload": "%s: side-2 cube n=%d, kappa=%g, m=%d (k=%d), leaf %d, tol %g"
+                        % (wc.name, len(Tc), wc.kappa, wc.order, wc.order ** 3, wc.leaf, wc.tol)}
+    ys = {}
+    for label, mode in (("exact", dh2.RANKS_EXACT), ("learned", dh2.RANKS_LEARNED)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hc = dh2.Handle(Vc, Tc, wc.kappa, wc.order, wc.eta, wc.leaf, wc.tol, eta1=wc.eta1, max_nrhs=4,
+                        rank_mode=mode)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        sc = hc.stats()
+        Yc = torch.empty_like(Xc)
+        hc.matvec(Xc, Yc)
+        torch.cuda.synchronize()
+        ys[label] = Yc
+        hc.free()
+        cube[label] = {"build_s": round(tc, 3), "truncation_ms": round(sc["ms_truncation"], 1),
+                       "total_weights_ms": round(sc["ms_total_weights"], 1), "sketch_slots": sc["sketch_slots"],
+                       "fallbacks": sc["sketch_fallbacks"], "rank_mean_row": round(sc["rank_mean_row"], 3)}
+    cube["rel_diff_learned_vs_exact"] = (torch.linalg.vector_norm(ys["learned"] - ys["exact"])
+                                         / torch.linalg.vector_norm(ys["exact"])).item()
+    log("learned form, %s: %s" % (wc.name, json.dumps(cube)))
+    out["cube_family"] = cube
+    return out
+
+
 def batch_form(args, dh2, torch, count):
     """The batching form: count problems of the seeded recipe (sphere, cube and
     ellipsoid surfaces, n ~ U[2k, 32k], kappa ~ U[4, 24], m 4, leaf 32, tol
@@ -575,6 +635,10 @@ def main():
     if not args.no_bf16x3:
         bf = fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=dh2.BF16X3)
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_form(args, w, V, T, X, Y64, dh2, torch, results, st, statistics.median(builds))
+
     batch = None
     if args.batch > 0:
         batch = batch_form(args, dh2, torch, args.batch)
@@ -653,6 +717,7 @@ def main():
         "bf16x3_form": bf,
         "spectral_form": spec,
         "batch_form": batch,
+        "learned_form": learned,
     }
     print(json.dumps(out), flush=True)
 

@@ -78,6 +78,20 @@ typedef enum { DH2_FP64 = 0, DH2_FP32 = 1, DH2_BF16X3 = 2 } dh2_precision;
  *                       numbers, Section 5) */
 typedef enum { DH2_NORM_FROBENIUS = 0, DH2_NORM_SPECTRAL = 1 } dh2_norm;
 
+/* Truncation of the recompression (Section 3.2):
+ *   DH2_RANKS_EXACT    the SVD of every truncation matrix (default);
+ *   DH2_RANKS_LEARNED  the learned-rank form: a small multilayer perceptron
+ *                      (12 features of geometry, direction, kappa and tol per
+ *                      cluster and direction; three hidden layers of 128; BF16
+ *                      weights, FP32 accumulation) predicts the rank, which sizes
+ *                      a randomized range finder (Gaussian sketch with 8 extra
+ *                      columns); the rank is then chosen by the same rule with the
+ *                      norm the sketch discards added, and a slot whose discarded
+ *                      norm alone exceeds the tolerance is truncated exactly
+ *                      (FP64) instead.  Ranks are never below the exact ones and
+ *                      each truncation meets the same block-relative bound. */
+typedef enum { DH2_RANKS_EXACT = 0, DH2_RANKS_LEARNED = 1 } dh2_rank_mode;
+
 /* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then
  * override fields; zero fields take the defaults given here. */
 typedef struct {
@@ -90,6 +104,9 @@ typedef struct {
   int32_t norm;       /* dh2_norm, default DH2_NORM_FROBENIUS                        */
   void* stream;       /* hipStream_t for all work of this handle; NULL = default stream */
   double workspace_gb;/* device workspace for the recompression batches; default 8 */
+  int32_t rank_mode;  /* dh2_rank_mode, default DH2_RANKS_EXACT */
+  int32_t sketch_rank;/* learned-rank form only: when > 0, every slot's predicted rank is
+                         this value and no columns are added (a test hook) */
 } dh2_options;
 
 typedef struct dh2_problem* dh2_handle;
@@ -246,6 +263,10 @@ typedef struct {
    * divided by the number of admissible blocks (each phase that needs S_b
    * generates it again). */
   double coupling_regeneration;
+  /* Learned-rank form: slots truncated through a sketch, sketches that missed the
+   * tolerance and were truncated exactly, and the time of the rank prediction. */
+  int64_t sketch_slots, sketch_fallbacks;
+  double ms_rank_predict;
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);
@@ -278,6 +299,15 @@ dh2_status dh2_plan_export(dh2_plan p, int64_t* perm, int64_t* cl_first, int64_t
                            int32_t* cl_level, int64_t* cl_parent, double* cl_box,
                            int32_t* level_ndirs, double* dirs, int32_t* sd, int64_t* adm,
                            int64_t* near, int64_t* slots);
+/* Features of the learned rank predictor (see DH2_RANKS_LEARNED) of every slot,
+ * n_slots x 12 floats row-major into caller-owned host memory: kind 0 for the
+ * row bases (blocks in which the cluster is the row cluster), 1 for the column
+ * bases.  Features: log2 #t, level / depth, kappa diam(B_t), log10 tol (at
+ * least -16), m, directional (|c| > 0), log2(1 + blocks of the slot's list),
+ * log2(1 + blocks of its ancestors' lists), leaf, shortest / longest side of
+ * B_t, log2(1 + triangles of the other clusters of its list), eta.
+ * Errors: DH2_ERR_ARG (NULL, kind, tol < 0). */
+dh2_status dh2_plan_rank_features(dh2_plan p, double tol, int kind, float* out);
 void dh2_plan_free(dh2_plan p);
 
 /* ---------------------------------------------------------------------------
@@ -296,6 +326,9 @@ void dh2_plan_free(dh2_plan p);
  *          DH2_INSPECT_TOTAL_WEIGHT_ROW  index = slot: Zhat_tc of the row pass (eq. (recomp_weight_full))
  *          DH2_INSPECT_TOTAL_WEIGHT_COL  index = slot: Zhat of the column pass (adjoint matrix)
  *          DH2_INSPECT_COUPLING    index = admissible leaf: S_b = (g_c(xi_t,nu, xi_s,mu)), k x k
+ *          DH2_INSPECT_RANK_PRED_ROW  index ignored: learned-rank form, predicted rank of every
+ *                                  slot's row basis, n_slots x 1 (DH2_ERR_ARG otherwise)
+ *          DH2_INSPECT_RANK_PRED_COL  same for the column bases
  * Real-valued results are returned in the real parts. */
 enum {
   DH2_INSPECT_NEAR = 1,
@@ -309,7 +342,9 @@ enum {
   DH2_INSPECT_BASIS_WEIGHT = 9,
   DH2_INSPECT_TOTAL_WEIGHT_ROW = 10,
   DH2_INSPECT_TOTAL_WEIGHT_COL = 11,
-  DH2_INSPECT_COUPLING = 12
+  DH2_INSPECT_COUPLING = 12,
+  DH2_INSPECT_RANK_PRED_ROW = 13,
+  DH2_INSPECT_RANK_PRED_COL = 14
 };
 dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64_t* rows,
                        int64_t* cols);

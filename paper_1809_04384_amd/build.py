@@ -26,9 +26,11 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "
 SOURCES = [
     ("plan.cpp", COMMON + ["-ffp-contract=off"], False),
     ("api.cpp", COMMON + ["-ffp-contract=off"], False),
+    ("rank_model.cpp", COMMON, False),
     ("kernels.hip", COMMON + HIPFLAGS, True),
     ("matvec.hip", COMMON + HIPFLAGS, True),
     ("scratch.hip", COMMON + HIPFLAGS, True),
+    ("rank_mlp.hip", COMMON + HIPFLAGS, True),
 ]
 
 

@@ -32,6 +32,7 @@
 #include "kernels.hpp"
 #include "matvec.hpp"
 #include "plan.hpp"
+#include "rank_model.hpp"
 #include "scratch.hpp"
 
 using namespace dh2;
@@ -135,6 +136,8 @@ struct dh2_problem {
   int max_nrhs = 16;
   double tol = 0;
   int norm_mode = 0;
+  int rank_mode = 0;       // DH2_RANKS_EXACT / DH2_RANKS_LEARNED
+  int sketch_rank = 0;     // fixed predicted rank of every slot (0 = the predictor's)
   int device = 0;
   size_t ws_bytes = 0;
   std::vector<void*> allocs;
@@ -152,6 +155,7 @@ struct dh2_problem {
   void* E_d = nullptr;                 // transfers (FP64), per slot 2 k x k
   std::vector<int64_t> E_off;
   std::vector<int32_t> rank_row, rank_col;  // -1 if not in the set
+  std::vector<int32_t> pred_row, pred_col;  // learned-rank form: predicted ranks
   std::vector<std::vector<double>> sig_row, sig_col;
   std::vector<double> omega;
   z64* R_d = nullptr;                  // basis weights, per slot k x k (rows rR)
@@ -882,9 +886,46 @@ struct Builder {
   }
 
   // ------------------------------------------------------------------
+  // Learned-rank form: predicted ranks of every slot (row or column basis),
+  // from the hierarchy's features and the compiled-in predictor, or the
+  // handle's fixed rank when one is set (a test hook).
+  std::vector<int32_t> predict_ranks(bool row) {
+    std::vector<int32_t> pr(ns, 0);
+    if (h.sketch_rank > 0) {
+      std::fill(pr.begin(), pr.end(), h.sketch_rank);
+      return pr;
+    }
+    const double t0 = now_ms();
+    std::vector<float> f;
+    rank_features(p, h.tol, row, f);
+    std::vector<void*> tmp;
+    float* fd = upload_tmp(f, tmp);
+    int32_t* rd = h.alloc<int32_t>(ns);
+    tmp.push_back(rd);
+    launch_rank_mlp(fd, ns, rd, h.stream);
+    h.check_launch();
+    h.sync();
+    HIPCHK(hipMemcpy(pr.data(), rd, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+    free_tmp(tmp);
+    h.stats.ms_rank_predict += now_ms() - t0;
+    return pr;
+  }
+
+  // ------------------------------------------------------------------
   // truncation, bottom-up (Section 3.2): SVD of V Zhat^* (leaf) or Vhat Zhat^*
   // with Vhat = [C_{t1c1} E_{t1c}; C_{t2c2} E_{t2c}], rank by the tolerance rule,
   // Qhat = leading left singular vectors, C_tc = Qhat^* Vhat.
+  //   exact path: B = Zhat Vhat^H (rZ x m), its R factor by the fold, Jacobi SVD;
+  //   sketch path (learned-rank form, when the predicted rank plus the
+  //   oversampling, l, is below m and rZ): A = Vhat Zhat^H (m x rZ), Y = A Omega
+  //   with a Gaussian rZ x l Omega, Q = an orthonormal basis of range(Y) (Jacobi
+  //   on the columns of Y), C^H = A^H Q, the discarded part A - Q C and its norm,
+  //   Jacobi on the columns of C^H (left singular vectors U_C of C and sigma),
+  //   the rank by the rule with the discarded norm added, Qhat = Q U_C[:, :rank].
+  //   A slot whose discarded norm alone exceeds the tolerance (the predicted
+  //   rank was too small) is truncated again by the exact path.
+  static constexpr int kSketchOversample = 8;
+  static constexpr int kSigStride = 512;
   void truncation(bool row) {
     const std::vector<uint8_t>& flag = row ? p.slot_row : p.slot_col;
     std::vector<int32_t>& rZ = row ? rZr : rZc;
@@ -898,52 +939,87 @@ struct Builder {
     Cptr.assign(ns, nullptr);
     Qptr.assign(ns, nullptr);
     Qm.assign(ns, 0);
+    std::vector<int32_t> pred;
+    if (h.rank_mode == DH2_RANKS_LEARNED) pred = predict_ranks(row);
+    (row ? h.pred_row : h.pred_col) = pred;
+    const size_t zs = sizeof(C64);
     for (int l = p.depth; l >= 0; --l) {
       std::vector<int64_t> qs;
       for (int64_t q = 0; q < ns; ++q)
         if (si[q].level == l && flag[q]) qs.push_back(q);
       size_t i0 = 0;
       while (i0 < qs.size()) {
-        // per slot: m, Vhat (m x k), B (rZ x m), RB (m x m), U (m x m), scratch 2 m^2
-        std::vector<int64_t> batch;
-        std::vector<size_t> off_vh, off_b, off_rb, off_u, off_sc;
-        std::vector<int32_t> mm;
+        // per slot: Vhat (m x k) and the exact path's B (rZ x m), RB, U (m x m),
+        // scratch 2 m^2; a sketch slot also A (m x rZ), Omega (rZ x l), Y, Q
+        // (m x l), C^H (rZ x l), U_C (l x l), the Jacobi scratch of Y and C^H
+        // and its discarded norm (the exact areas serve its fallback)
+        struct Job {
+          int64_t q;
+          int m, ell;
+          size_t vh, b, rb, u, sc;            // exact path
+          size_t a, om, y, qq, ch, vj, sy, scc;   // sketch path
+        };
+        std::vector<Job> jobs;
         size_t used = 0;
         size_t i1 = i0;
+        auto take = [&](size_t bytes) {
+          const size_t o = used;
+          used += (bytes + 255) / 256 * 256;
+          return o;
+        };
         for (; i1 < qs.size(); ++i1) {
           const int64_t q = qs[i1];
-          int m;
-          if (si[q].leaf) m = si[q].nrows;
-          else m = rank[si[q].child_slot[0]] + rank[si[q].child_slot[1]];
-          const size_t need = ((size_t)m * k + (size_t)rZ[q] * m + 4 * (size_t)m * m + 8) * sizeof(C64);
+          Job j{};
+          j.q = q;
+          j.m = si[q].leaf ? si[q].nrows : rank[si[q].child_slot[0]] + rank[si[q].child_slot[1]];
+          const int m = j.m, rz = rZ[q];
+          j.ell = 0;
+          if (!pred.empty() && m > 0 && rz > 0) {
+            const int want = h.sketch_rank > 0 ? pred[q] : pred[q] + kSketchOversample;
+            if (want < m && want < rz) j.ell = std::max(want, 1);
+          }
+          const int e = j.ell;
+          size_t need = ((size_t)m * k + (size_t)rz * m + 4 * (size_t)m * m + 8) * zs + 5 * 256;
+          if (e > 0)
+            need += ((size_t)m * rz + (size_t)rz * e + 2 * (size_t)m * e + (size_t)rz * e + (size_t)e * e +
+                     (size_t)(m + e) * e + (size_t)(rz + e) * e) * zs + 8 * 256;
           if (used + need > ws_bytes && i1 > i0) break;
-          batch.push_back(q);
-          mm.push_back(m);
-          off_vh.push_back(used); used += (size_t)m * k * sizeof(C64);
-          off_b.push_back(used); used += (size_t)rZ[q] * m * sizeof(C64);
-          off_rb.push_back(used); used += (size_t)m * m * sizeof(C64);
-          off_u.push_back(used); used += (size_t)m * m * sizeof(C64);
-          off_sc.push_back(used); used += (size_t)2 * m * m * sizeof(C64) + 8 * sizeof(C64);
+          j.vh = take((size_t)m * k * zs);
+          j.b = take((size_t)rz * m * zs);
+          j.rb = take((size_t)m * m * zs);
+          j.u = take((size_t)m * m * zs);
+          j.sc = take(((size_t)2 * m * m + 8) * zs);
+          if (e > 0) {
+            j.a = take((size_t)m * rz * zs);
+            j.om = take((size_t)rz * e * zs);
+            j.y = take((size_t)m * e * zs);
+            j.qq = take((size_t)m * e * zs);
+            j.ch = take((size_t)rz * e * zs);
+            j.vj = take((size_t)e * e * zs);
+            j.sy = take((size_t)(m + e) * e * zs);
+            j.scc = take((size_t)(rz + e) * e * zs);
+          }
           if (used > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for a truncation step"};
+          jobs.push_back(j);
         }
         std::vector<void*> tmp;
-        std::vector<GemmDesc> g1, g2;
-        std::vector<FoldTask> ft;
-        std::vector<FoldPiece> fp;
-        std::vector<SvdTask> sv;
-        const size_t nb = batch.size();
-        double* sig_d = (double*)h.alloc<double>(nb * 256 + 1);
+        const size_t nb = jobs.size();
+        double* sig_d = (double*)h.alloc<double>(nb * kSigStride + 1);
+        double* sigy_d = (double*)h.alloc<double>(nb * kSigStride + 1);
         int32_t* rk_d = h.alloc<int32_t>(nb + 1);
         tmp.push_back(sig_d);
+        tmp.push_back(sigy_d);
         tmp.push_back(rk_d);
-        int maxm = 0;
         std::vector<const C64*> vh_ptr(nb);
         std::vector<int> vh_ld(nb);
+        std::vector<GemmDesc> g1;
+        int maxm = 0;
         for (size_t b = 0; b < nb; ++b) {
-          const int64_t q = batch[b];
-          const int m = mm[b];
+          const Job& j = jobs[b];
+          const int64_t q = j.q;
+          const int m = j.m;
           maxm = std::max(maxm, m);
-          C64* vh = (C64*)(ws + off_vh[b]);
+          C64* vh = (C64*)(ws + j.vh);
           if (si[q].leaf) {
             vh_ptr[b] = (C64*)h.V_d + h.V_off[q];
             vh_ld[b] = si[q].nrows;
@@ -965,54 +1041,159 @@ struct Builder {
             vh_ptr[b] = vh;
             vh_ld[b] = m;
           }
-          if (m == 0 || rZ[q] == 0) continue;
-          // B = Zhat Vhat^* (rZ x m)
-          C64* B = (C64*)(ws + off_b[b]);
-          GemmDesc g{};
-          g.A = Zp(row, q); g.lda = k; g.M = rZ[q]; g.K = k;
-          g.B = vh_ptr[b]; g.ldb = vh_ld[b]; g.N = m; g.opB = 2;
-          g.C = B; g.ldc = rZ[q];
-          g.alpha_re = 1.0;
-          g2.push_back(g);
-          ft.push_back(FoldTask{(C64*)(ws + off_rb[b]), m, m, (int32_t)fp.size(),
-                                (int32_t)fp.size() + 1, 1, 0, nullptr});
-          fp.push_back({B, rZ[q], rZ[q]});
-          SvdTask st{};
-          st.B = ws + off_rb[b]; st.ldb = m;
-          st.U = ws + off_u[b]; st.ldu = m;
-          st.sig = sig_d + b * 256;
-          st.rank = rk_d + b;
-          st.scratch = ws + off_sc[b];
-          st.m = m;
-          st.norm_mode = h.norm_mode;
-          st.eps = h.tol;
-          sv.push_back(st);
         }
-        if (maxm > 256) throw Fail{DH2_ERR_ARG, "truncation matrix with more than 256 rows"};
+        if (maxm > kSigStride) throw Fail{DH2_ERR_ARG, "truncation matrix with more than 512 rows"};
         ++h.stats.batches_truncation;
-        count_folds(ft, fp);
         gemm(g1, tmp);
-        gemm(g2, tmp);
-        if (!ft.empty()) {
-          // fold per m: n differs per task, LDS sized for the largest
-          launch_fold<double>(upload_tmp(ft, tmp), (int64_t)ft.size(), upload_tmp(fp, tmp), maxm, h.stream);
-          launch_jacobi(upload_tmp(sv, tmp), (int64_t)sv.size(), maxm, h.stream);
+        // exact path for the given jobs: B = Zhat Vhat^H, fold, Jacobi
+        auto exact = [&](const std::vector<size_t>& which) {
+          std::vector<GemmDesc> g2;
+          std::vector<FoldTask> ft;
+          std::vector<FoldPiece> fp;
+          std::vector<SvdTask> sv;
+          int mm = 0;
+          for (size_t b : which) {
+            const Job& j = jobs[b];
+            const int m = j.m, rz = rZ[j.q];
+            if (m == 0 || rz == 0) continue;
+            mm = std::max(mm, m);
+            C64* B = (C64*)(ws + j.b);
+            GemmDesc g{};
+            g.A = Zp(row, j.q); g.lda = k; g.M = rz; g.K = k;
+            g.B = vh_ptr[b]; g.ldb = vh_ld[b]; g.N = m; g.opB = 2;
+            g.C = B; g.ldc = rz;
+            g.alpha_re = 1.0;
+            g2.push_back(g);
+            ft.push_back(FoldTask{(C64*)(ws + j.rb), m, m, (int32_t)fp.size(), (int32_t)fp.size() + 1, 1, 0, nullptr});
+            fp.push_back({B, rz, rz});
+            SvdTask st{};
+            st.B = ws + j.rb; st.ldb = m;
+            st.U = ws + j.u; st.ldu = m;
+            st.sig = sig_d + b * kSigStride;
+            st.rank = rk_d + b;
+            st.scratch = ws + j.sc;
+            st.m = m;
+            st.norm_mode = h.norm_mode;
+            st.eps = h.tol;
+            sv.push_back(st);
+          }
+          if (ft.empty()) return;
+          count_folds(ft, fp);
+          gemm(g2, tmp);
+          launch_fold<double>(upload_tmp(ft, tmp), (int64_t)ft.size(), upload_tmp(fp, tmp), mm, h.stream);
+          launch_jacobi(upload_tmp(sv, tmp), (int64_t)sv.size(), mm, mm, h.stream);
+        };
+        std::vector<size_t> ex, sk;
+        for (size_t b = 0; b < nb; ++b) (jobs[b].ell > 0 ? sk : ex).push_back(b);
+        exact(ex);
+        if (!sk.empty()) {
+          std::vector<GemmDesc> gA, gY, gC, gR;
+          std::vector<SketchDesc> om;
+          std::vector<FrobDesc> fr;
+          std::vector<SvdTask> svY, svC;
+          int mm = 0, mr = 0, me = 0;
+          for (size_t b : sk) {
+            const Job& j = jobs[b];
+            const int m = j.m, rz = rZ[j.q], e = j.ell;
+            mm = std::max(mm, m);
+            mr = std::max(mr, rz);
+            me = std::max(me, e);
+            C64* A = (C64*)(ws + j.a);
+            C64* Om = (C64*)(ws + j.om);
+            C64* Y = (C64*)(ws + j.y);
+            C64* Q = (C64*)(ws + j.qq);
+            C64* CH = (C64*)(ws + j.ch);
+            GemmDesc g{};
+            g.A = vh_ptr[b]; g.lda = vh_ld[b]; g.M = m; g.K = k;           // A = Vhat Zhat^H
+            g.B = Zp(row, j.q); g.ldb = k; g.N = rz; g.opB = 2;
+            g.C = A; g.ldc = m;
+            g.alpha_re = 1.0;
+            gA.push_back(g);
+            om.push_back({Om, rz, e, rz, 0, (int64_t)j.q * 2 + (row ? 0 : 1)});
+            g = GemmDesc{};
+            g.A = A; g.lda = m; g.M = m; g.K = rz;                          // Y = A Omega
+            g.B = Om; g.ldb = rz; g.N = e;
+            g.C = Y; g.ldc = m;
+            g.alpha_re = 1.0;
+            gY.push_back(g);
+            SvdTask t{};
+            t.B = Y; t.ldb = m; t.rows = m; t.m = e;                       // Q: basis of range(Y)
+            t.W = Q; t.ldw = m;
+            t.sig = sigy_d + b * kSigStride;
+            t.scratch = ws + j.sy;
+            t.eps = 0.0;
+            svY.push_back(t);
+            g = GemmDesc{};
+            g.A = A; g.lda = m; g.M = rz; g.K = m; g.opA = 2;               // C^H = A^H Q
+            g.B = Q; g.ldb = m; g.N = e;
+            g.C = CH; g.ldc = rz;
+            g.alpha_re = 1.0;
+            gC.push_back(g);
+            g = GemmDesc{};
+            g.A = Q; g.lda = m; g.M = m; g.K = e;                           // A -= Q C
+            g.B = CH; g.ldb = rz; g.N = rz; g.opB = 2;
+            g.C = A; g.ldc = m;
+            g.accumulate = 1;
+            g.alpha_re = -1.0;
+            gR.push_back(g);
+            fr.push_back({A, m, rz, m, 0, (int64_t)b});
+            t = SvdTask{};
+            t.B = CH; t.ldb = rz; t.rows = rz; t.m = e;                    // U_C, sigma, rank
+            t.U = ws + j.vj; t.ldu = e;
+            t.sig = sig_d + b * kSigStride;
+            t.rank = rk_d + b;
+            t.scratch = ws + j.scc;
+            t.norm_mode = h.norm_mode;
+            t.eps = h.tol;
+            t.resid = nullptr;   // set below: the discarded norm of job b
+            svC.push_back(t);
+          }
+          h.stats.sketch_slots += (int64_t)sk.size();
+          // the discarded norms, one per job (FrobDesc.index = batch position)
+          double* res_d = h.alloc<double>(nb + 1);
+          tmp.push_back(res_d);
+          gemm(gA, tmp);
+          launch_sketch_omega(upload_tmp(om, tmp), (int64_t)om.size(), 0x5EED1u, h.stream);
+          gemm(gY, tmp);
+          launch_jacobi(upload_tmp(svY, tmp), (int64_t)svY.size(), me, mm, h.stream);
+          gemm(gC, tmp);
+          gemm(gR, tmp);
+          launch_frob<double>(upload_tmp(fr, tmp), (int64_t)fr.size(), res_d, h.stream);
+          for (SvdTask& t : svC) {
+            const size_t b = (size_t)(t.rank - rk_d);
+            t.resid = res_d + b;
+          }
+          launch_jacobi(upload_tmp(svC, tmp), (int64_t)svC.size(), me, mr, h.stream);
         }
         h.check_launch();
         h.sync();
         std::vector<int32_t> rk(nb, 0);
-        std::vector<double> sg(nb * 256);
+        std::vector<double> sg(nb * kSigStride);
         HIPCHK(hipMemcpy(rk.data(), rk_d, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(sg.data(), sig_d, nb * 256 * sizeof(double), hipMemcpyDeviceToHost));
-        // store Qhat (m x kk) and C = Qhat^* Vhat (kk x k); SVD results are indexed by batch position
+        HIPCHK(hipMemcpy(sg.data(), sig_d, nb * kSigStride * sizeof(double), hipMemcpyDeviceToHost));
+        // sketches that missed the tolerance: exact path
+        std::vector<size_t> fb;
+        for (size_t b : sk)
+          if (rk[b] < 0) fb.push_back(b);
+        if (!fb.empty()) {
+          h.stats.sketch_fallbacks += (int64_t)fb.size();
+          for (size_t b : fb) jobs[b].ell = 0;
+          exact(fb);
+          h.check_launch();
+          h.sync();
+          HIPCHK(hipMemcpy(rk.data(), rk_d, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(sg.data(), sig_d, nb * kSigStride * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        // store Qhat (m x kk) and C = Qhat^* Vhat (kk x k); results are indexed by batch position
         std::vector<int> kkb(nb, 0);
         size_t qtot = 0, ctot = 0;
         for (size_t b = 0; b < nb; ++b) {
-          const int64_t q = batch[b];
-          const int m = mm[b];
-          if (m > 0 && rZ[q] > 0) {
+          const Job& j = jobs[b];
+          const int m = j.m;
+          if (m > 0 && rZ[j.q] > 0) {
             kkb[b] = rk[b];
-            sig[q].assign(sg.begin() + b * 256, sg.begin() + b * 256 + m);
+            const int ns_sig = j.ell > 0 ? j.ell : m;
+            sig[j.q].assign(sg.begin() + b * kSigStride, sg.begin() + b * kSigStride + ns_sig);
           }
           qtot += (size_t)m * kkb[b];
           ctot += (size_t)kkb[b] * k;
@@ -1021,11 +1202,12 @@ struct Builder {
         C64* Cb = h.alloc<C64>(std::max<size_t>(ctot, 1));
         keep_rc.push_back(Cb);
         std::vector<CopyDesc> cp;
-        std::vector<GemmDesc> g3;
+        std::vector<GemmDesc> gq, g3;
         size_t qo = 0, co = 0;
         for (size_t b = 0; b < nb; ++b) {
-          const int64_t q = batch[b];
-          const int m = mm[b];
+          const Job& j = jobs[b];
+          const int64_t q = j.q;
+          const int m = j.m;
           const int kk = kkb[b];
           rank[q] = kk;
           Qm[q] = m;
@@ -1034,7 +1216,16 @@ struct Builder {
           qo += (size_t)m * kk;
           co += (size_t)kk * k;
           if (kk > 0) {
-            cp.push_back({ws + off_u[b], Qptr[q], m, kk, m, m});
+            if (j.ell > 0) {
+              GemmDesc g{};                                                 // Qhat = Q U_C[:, :kk]
+              g.A = ws + j.qq; g.lda = m; g.M = m; g.K = j.ell;
+              g.B = ws + j.vj; g.ldb = j.ell; g.N = kk;
+              g.C = Qptr[q]; g.ldc = m;
+              g.alpha_re = 1.0;
+              gq.push_back(g);
+            } else {
+              cp.push_back({ws + j.u, Qptr[q], m, kk, m, m});
+            }
             GemmDesc g{};
             g.A = Qptr[q]; g.lda = m; g.M = kk; g.K = m; g.opA = 2;
             g.B = vh_ptr[b]; g.ldb = vh_ld[b]; g.N = k;
@@ -1044,6 +1235,7 @@ struct Builder {
           }
         }
         if (!cp.empty()) launch_copy<double>(upload_tmp(cp, tmp), (int64_t)cp.size(), h.stream);
+        gemm(gq, tmp);
         gemm(g3, tmp);
         h.check_launch();
         free_tmp(tmp);
@@ -1665,6 +1857,14 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     g_err = "unknown norm";
     return DH2_ERR_ARG;
   }
+  if (opt.rank_mode != DH2_RANKS_EXACT && opt.rank_mode != DH2_RANKS_LEARNED) {
+    g_err = "unknown rank mode";
+    return DH2_ERR_ARG;
+  }
+  if (opt.sketch_rank < 0) {
+    g_err = "sketch_rank must be >= 0";
+    return DH2_ERR_ARG;
+  }
   const double eta1 = opt.eta1 > 0 ? opt.eta1 : 10.0;
   const int max_nrhs = opt.max_nrhs > 0 ? opt.max_nrhs : 16;
   const double wsgb = opt.workspace_gb > 0 ? opt.workspace_gb : 8.0;
@@ -1687,6 +1887,8 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     h->max_nrhs = max_nrhs;
     h->tol = tol;
     h->norm_mode = opt.norm;
+    h->rank_mode = opt.rank_mode;
+    h->sketch_rank = opt.sketch_rank;
     h->plan.kappa = kappa;
     h->plan.order = order;
     h->plan.eta = eta;
@@ -2104,9 +2306,14 @@ dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64
         src = (const z64*)h->E_d + h->E_off[q] + (index % 2) * (int64_t)k * k;
         break;
       }
+      case DH2_INSPECT_RANK_PRED_ROW:
+      case DH2_INSPECT_RANK_PRED_COL:
       case DH2_INSPECT_RANK_ROW:
       case DH2_INSPECT_RANK_COL: {
-        const auto& rk = what == DH2_INSPECT_RANK_ROW ? h->rank_row : h->rank_col;
+        const auto& rk = what == DH2_INSPECT_RANK_ROW ? h->rank_row
+                         : what == DH2_INSPECT_RANK_COL ? h->rank_col
+                         : what == DH2_INSPECT_RANK_PRED_ROW ? h->pred_row : h->pred_col;
+        if ((int64_t)rk.size() != ns) throw Fail{DH2_ERR_ARG, "no predicted ranks (exact truncation)"};
         r = ns;
         c = 1;
         host.resize(2 * ns);
@@ -2296,6 +2503,22 @@ dh2_status dh2_plan_export(dh2_plan pl, int64_t* perm, int64_t* cl_first, int64_
       slots[3 * q + 1] = p.slots[q].c;
       slots[3 * q + 2] = (p.slot_row[q] ? 1 : 0) | (p.slot_col[q] ? 2 : 0);
     }
+  return DH2_OK;
+}
+
+dh2_status dh2_plan_rank_features(dh2_plan pl, double tol, int kind, float* out) {
+  if (!pl || !out || (kind != 0 && kind != 1) || !(tol >= 0.0)) {
+    g_err = "NULL plan or output, kind not 0 / 1, or tol < 0";
+    return DH2_ERR_ARG;
+  }
+  try {
+    std::vector<float> f;
+    rank_features(pl->plan, tol, kind == 0, f);
+    std::copy(f.begin(), f.end(), out);
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return DH2_ERR_OOM;
+  }
   return DH2_OK;
 }
 

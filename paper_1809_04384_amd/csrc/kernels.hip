@@ -938,35 +938,41 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Truncation SVD (FP64): left singular vectors and singular values of
-// A = B^H from the m x m upper triangular B (the R factor of A^H), by
-// one-sided (Hestenes) Jacobi on the columns of B with round-robin pairs; the
-// accumulated rotations are the left singular vectors of A.  The rank rule
-// (smallest k with sum_{i>k} sigma_i^2 <= eps^2, or sigma_{k+1} <= eps) is
-// applied in the epilogue (Section 3.1: lowest rank meeting the bound).
+// Truncation SVD (FP64): one-sided (Hestenes) Jacobi on the m columns of a
+// rows x m matrix B with round-robin pairs.  With rows = m and B the R factor
+// of A^H, the accumulated rotations V are the left singular vectors of A =
+// B^H and the column norms its singular values (exact truncation).  With
+// rows > m (the sketch path of the learned-rank form) the normalised rotated
+// columns W give an orthonormal basis of range(B), and V the left singular
+// vectors of B^H.  The rank rule (smallest k with res^2 + sum_{i>k}
+// sigma_i^2 <= eps^2, or max(sigma_{k+1}, res) <= eps; Section 3.1: lowest
+// rank meeting the bound) is applied in the epilogue; res is the Frobenius
+// norm a sketch has already discarded (0 for the exact path), and rank -1
+// reports that it alone exceeds the tolerance.
 // The input is scaled by a power of two to unit magnitude, and rotations with
 // a numerically zero column are skipped, so no product of tiny quantities
 // reaches the subnormal range (where the rotation phase would lose its bits).
-// Workspace: 2 m^2 complex (B and V), in LDS when lds != 0, else in global
-// scratch given by the task.
+// Workspace: (rows + m) m complex (B and V), in LDS when lds != 0, else in
+// global scratch given by the task.
 __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ tasks, int use_lds) {
   extern __shared__ double lds_raw[];
   const SvdTask tk = tasks[blockIdx.x];
   const int m = tk.m;
+  const int r = tk.rows > 0 ? tk.rows : m;
   const int mp = (m + 1) & ~1;   // padded to even
   z64* B = use_lds ? (z64*)lds_raw : (z64*)tk.scratch;
-  z64* V = B + (int64_t)m * m;
+  z64* V = B + (int64_t)r * m;
   __shared__ int s_pos[512];
   __shared__ int s_rot;
-  __shared__ double s_sig[256];
-  __shared__ int s_ord[256];
+  __shared__ double s_sig[512];
+  __shared__ int s_ord[512];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   __shared__ double s_wmax[4];
   const z64* Bin = (const z64*)tk.B;
   double lmax = 0.0;
-  for (int e = tid; e < m * m; e += 256) {
-    const int i = e % m, j = e / m;
+  for (int e = tid; e < r * m; e += 256) {
+    const int i = e % r, j = e / r;
     const z64 v = Bin[i + (int64_t)j * tk.ldb];
     lmax = fmax(lmax, fmax(fabs(v.x), fabs(v.y)));
   }
@@ -979,10 +985,13 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
     const double mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
     if (mx > 0.0) frexp(mx, &sexp);
   }
-  for (int e = tid; e < m * m; e += 256) {
-    const int i = e % m, j = e / m;
+  for (int e = tid; e < r * m; e += 256) {
+    const int i = e % r, j = e / r;
     const z64 v = Bin[i + (int64_t)j * tk.ldb];
     B[e] = z64{ldexp(v.x, -sexp), ldexp(v.y, -sexp)};
+  }
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
     V[e] = z64{i == j ? 1.0 : 0.0, 0.0};
   }
   for (int i = tid; i < mp; i += 256) s_pos[i] = i;
@@ -1001,8 +1010,8 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
         }
         double a = 0, b = 0;
         z64 g{0, 0};
-        for (int i = lane; i < m; i += 64) {
-          const z64 bp = B[i + p * m], bq = B[i + q * m];
+        for (int i = lane; i < r; i += 64) {
+          const z64 bp = B[i + p * r], bq = B[i + q * r];
           a += abs2(bp);
           b += abs2(bq);
           cfmac(g, bp, bq);
@@ -1024,11 +1033,13 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
         const double c = 1.0 / sqrt(1.0 + t * t);
         const double s = c * t;
         const z64 e{g.x / ag, -g.y / ag};   // exp(-i phi), phi = arg g
-        for (int i = lane; i < m; i += 64) {
-          const z64 bp = B[i + p * m], bq = B[i + q * m];
+        for (int i = lane; i < r; i += 64) {
+          const z64 bp = B[i + p * r], bq = B[i + q * r];
           const z64 ebq = e * bq;
-          B[i + p * m] = z64{c * bp.x - s * ebq.x, c * bp.y - s * ebq.y};
-          B[i + q * m] = z64{s * bp.x + c * ebq.x, s * bp.y + c * ebq.y};
+          B[i + p * r] = z64{c * bp.x - s * ebq.x, c * bp.y - s * ebq.y};
+          B[i + q * r] = z64{s * bp.x + c * ebq.x, s * bp.y + c * ebq.y};
+        }
+        for (int i = lane; i < m; i += 64) {
           const z64 vp = V[i + p * m], vq = V[i + q * m];
           const z64 evq = e * vq;
           V[i + p * m] = z64{c * vp.x - s * evq.x, c * vp.y - s * evq.y};
@@ -1047,12 +1058,12 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
     if (!s_rot) break;
     __syncthreads();
   }
-  // singular values = column norms of B, sorted descending (stable)
+  // singular values = column norms of B (scaled), sorted descending (stable)
   for (int j = wave; j < m; j += 4) {
     double a = 0;
-    for (int i = lane; i < m; i += 64) a += abs2(B[i + j * m]);
+    for (int i = lane; i < r; i += 64) a += abs2(B[i + j * r]);
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-    if (lane == 0) s_sig[j] = ldexp(sqrt(a), sexp);
+    if (lane == 0) s_sig[j] = sqrt(a);
   }
   __syncthreads();
   if (tid == 0) {
@@ -1065,27 +1076,82 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
       for (int l = best; l > j; --l) s_ord[l] = s_ord[l - 1];
       s_ord[j] = t;
     }
+    const double res2 = tk.resid ? (*tk.resid) * (*tk.resid) : 0.0;
     int kk = m;
     if (tk.norm_mode == 0) {
-      double tail = 0.0;
+      double tail = res2;
       for (int i = m - 1; i >= 0; --i) {
-        const double sv = s_sig[s_ord[i]];
+        const double sv = ldexp(s_sig[s_ord[i]], sexp);
         tail += sv * sv;
         if (tail <= tk.eps * tk.eps) kk = i;
         else break;
       }
+      if (res2 > tk.eps * tk.eps) kk = -1;
     } else {
-      while (kk > 0 && s_sig[s_ord[kk - 1]] <= tk.eps) --kk;
+      while (kk > 0 && ldexp(s_sig[s_ord[kk - 1]], sexp) <= tk.eps) --kk;
+      if (sqrt(res2) > tk.eps) kk = -1;
     }
-    *tk.rank = kk;
-    for (int j = 0; j < m; ++j) tk.sig[j] = s_sig[s_ord[j]];
+    if (tk.rank) *tk.rank = kk;
+    for (int j = 0; j < m; ++j) tk.sig[j] = ldexp(s_sig[s_ord[j]], sexp);
   }
   __syncthreads();
-  z64* U = (z64*)tk.U;
-  for (int e = tid; e < m * m; e += 256) {
-    const int i = e % m, j = e / m;
-    U[i + (int64_t)j * tk.ldu] = V[i + s_ord[j] * m];
+  if (tk.U) {
+    z64* U = (z64*)tk.U;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = e % m, j = e / m;
+      U[i + (int64_t)j * tk.ldu] = V[i + s_ord[j] * m];
+    }
   }
+  if (tk.W) {
+    z64* W = (z64*)tk.W;
+    const double top = s_sig[s_ord[0]];
+    for (int e = tid; e < r * m; e += 256) {
+      const int i = e % r, j = e / r;
+      const double sj = s_sig[s_ord[j]];
+      const z64 v = B[i + s_ord[j] * r];
+      W[i + (int64_t)j * tk.ldw] = sj > 1e-13 * top ? z64{v.x / sj, v.y / sj} : z64{0, 0};
+    }
+  }
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): ten rounds of two 32 x 32 -> 64 bit products
+// with the published multipliers and Weyl key increments.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sketch_omega(const SketchDesc* __restrict__ dd, uint32_t seed) {
+  const SketchDesc d = dd[blockIdx.x];
+  z64* Om = (z64*)d.Om;
+  for (int e = threadIdx.x; e < d.rows * d.cols; e += 256) {
+    const int i = e % d.rows, j = e / d.rows;
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)j, (uint32_t)d.stream, (uint32_t)(d.stream >> 32)};
+    philox4x32_10(c, seed, 0u);
+    // Box-Muller: u1 in (0, 1], u2 in [0, 1)
+    const double u1 = ((double)c[0] + 1.0) * 0x1p-32;
+    const double u2 = (double)c[1] * 0x1p-32;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(6.283185307179586 * u2, &sn, &cs);
+    Om[i + (int64_t)j * d.ld] = z64{rad * cs, rad * sn};
+  }
+}
+
+void launch_sketch_omega(const SketchDesc* d, int64_t nd, uint32_t seed, hipStream_t st) {
+  if (nd > 0) hipLaunchKernelGGL(k_sketch_omega, dim3((unsigned)nd), dim3(256), 0, st, d, seed);
 }
 
 // Frobenius norms of a batch of matrices (block weights omega_b).
@@ -1394,9 +1460,9 @@ void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, h
 template void launch_fold<double>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
 template void launch_fold<float>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
 
-void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, hipStream_t st) {
+void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, int maxr, hipStream_t st) {
   if (ntasks <= 0) return;
-  const size_t need = (size_t)2 * maxm * maxm * 16;
+  const size_t need = (size_t)(maxr + maxm) * maxm * 16;
   const int use_lds = need <= g_lds_limit ? 1 : 0;
   hipLaunchKernelGGL(k_jacobi, dim3((unsigned)ntasks), dim3(256), use_lds ? need : 0, st, t, use_lds);
 }

@@ -68,14 +68,33 @@ struct FoldPiece {
 };
 
 struct SvdTask {
-  const void* B;      // m x m FP64 complex (R factor of A^H), leading dimension ldb
-  void* U;            // m x m output: left singular vectors of A, sorted
+  const void* B;      // rows x m FP64 complex, leading dimension ldb (exact truncation: the
+                      // m x m R factor of A^H, rows = m)
+  void* U;            // m x m output: the accumulated rotations V sorted by singular value
+                      // (the left singular vectors of A = B^H); may be NULL
   double* sig;        // m singular values, descending
-  int32_t* rank;      // chosen rank
-  void* scratch;      // 2 m^2 complex doubles when not in LDS
+  int32_t* rank;      // chosen rank, -1 when the discarded norm alone exceeds the tolerance; may be NULL
+  void* scratch;      // (rows + m) m complex doubles when not in LDS
   int32_t m, ldb, ldu, norm_mode;
   double eps;
+  int32_t rows;       // rows of B (0 = m)
+  int32_t ldw;
+  void* W;            // rows x m output: the rotated columns of B divided by their norms,
+                      // sorted (an orthonormal basis of range(B)); columns at or below
+                      // 1e-13 of the largest are zero; may be NULL
+  const double* resid; // Frobenius norm already discarded (its square is added to the rank
+                       // rule's tail); may be NULL
 };
+
+// Gaussian sketch matrices: Omega (rows x cols, leading dimension ld), entry
+// (i, j) = z0 + i z1 from Philox4x32-10 (counter (i, j, stream, 0), key (seed,
+// 0)) and the Box-Muller transform.
+struct SketchDesc {
+  void* Om;
+  int32_t rows, cols, ld, pad;
+  int64_t stream;
+};
+void launch_sketch_omega(const SketchDesc* d, int64_t nd, uint32_t seed, hipStream_t st);
 
 struct FrobDesc {
   const void* A;
@@ -127,7 +146,8 @@ void set_lds_limit(size_t bytes);
 int fold_rows_per_chunk(int n);
 template <typename PT>
 void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, hipStream_t st);
-void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, hipStream_t st);
+// maxm, maxr: the largest m and rows of the tasks (LDS sizing)
+void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, int maxr, hipStream_t st);
 template <typename R>
 void launch_frob(const FrobDesc* d, int64_t nb, double* out, hipStream_t st);
 // A <- A 2^-e per matrix (FP64 complex, FrobDesc.A is written), 2^(e-1) <= max |a| < 2^e

@@ -16,15 +16,17 @@ LIB_PATH = os.path.join(HERE, "libdh2.so")
 DH2_OK = 0
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_GEOMETRY", 3: "ERR_OOM", 4: "ERR_DEVICE", 5: "ERR_NUMERIC"}
 FP64, FP32, BF16X3 = 0, 1, 2
+RANKS_EXACT, RANKS_LEARNED = 0, 1
 NORM_FROBENIUS, NORM_SPECTRAL = 0, 1
 INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col": 5,
            "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
-           "total_weight_row": 10, "total_weight_col": 11, "coupling": 12}
+           "total_weight_row": 10, "total_weight_col": 11, "coupling": 12, "rank_pred_row": 13,
+           "rank_pred_col": 14}
 
 EXPORTED = ["dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_free", "dh2_last_error",
             "dh2_get_stats", "dh2_plan_create", "dh2_plan_get_sizes", "dh2_plan_export",
             "dh2_plan_free", "dh2_inspect", "dh2_batch_create", "dh2_batch_run", "dh2_batch_free",
-            "dh2_matvec_stream", "dh2_build_many", "dh2_matvec_noalloc"]
+            "dh2_matvec_stream", "dh2_build_many", "dh2_matvec_noalloc", "dh2_plan_rank_features"]
 
 
 class Dh2Error(RuntimeError):
@@ -41,7 +43,8 @@ class Geometry(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("eta1", ctypes.c_double),
                 ("max_nrhs", ctypes.c_int32), ("norm", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("workspace_gb", ctypes.c_double)]
+                ("stream", ctypes.c_void_p), ("workspace_gb", ctypes.c_double),
+                ("rank_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -64,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("batches_total_weights_row", ctypes.c_int64), ("batches_total_weights_col", ctypes.c_int64),
                 ("batches_truncation", ctypes.c_int64),
                 ("batches_projection", ctypes.c_int64), ("slots_straddled", ctypes.c_int64),
-                ("coupling_regeneration", ctypes.c_double)]
+                ("coupling_regeneration", ctypes.c_double), ("sketch_slots", ctypes.c_int64),
+                ("sketch_fallbacks", ctypes.c_int64), ("ms_rank_predict", ctypes.c_double)]
 
 
 class PlanSizes(ctypes.Structure):
@@ -99,6 +103,7 @@ def load():
     lib.dh2_plan_create.argtypes = [P, D, I32, D, I32, D, P]
     lib.dh2_plan_get_sizes.argtypes = [P, P]
     lib.dh2_plan_export.argtypes = [P] * 13
+    lib.dh2_plan_rank_features.argtypes = [P, D, I32, P]
     lib.dh2_plan_free.argtypes = [P]
     lib.dh2_plan_free.restype = None
     lib.dh2_inspect.argtypes = [P, I32, I64, P, P, P]
@@ -111,7 +116,7 @@ def load():
     lib.dh2_batch_free.restype = None
     for name in ("dh2_build", "dh2_build_ex", "dh2_matvec", "dh2_matvec_profile", "dh2_get_stats", "dh2_plan_create",
                  "dh2_plan_get_sizes", "dh2_plan_export", "dh2_inspect", "dh2_batch_create", "dh2_batch_run",
-                 "dh2_matvec_stream", "dh2_build_many", "dh2_matvec_noalloc"):
+                 "dh2_matvec_stream", "dh2_build_many", "dh2_matvec_noalloc", "dh2_plan_rank_features"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -156,6 +161,15 @@ class Plan:
         _check(lib.dh2_plan_export(self._p, *[out[k].ctypes.data for k in keys]))
         return out
 
+    def rank_features(self, tol, kind="row"):
+        """Features of the learned rank predictor, (n_slots, 12) float32."""
+        lib = load()
+        s = PlanSizes()
+        _check(lib.dh2_plan_get_sizes(self._p, ctypes.byref(s)))
+        out = np.empty((s.n_slots, 12), dtype=np.float32)
+        _check(lib.dh2_plan_rank_features(self._p, tol, 0 if kind == "row" else 1, out.ctypes.data))
+        return out
+
     def __del__(self):
         if getattr(self, "_p", None) and _lib is not None:
             _lib.dh2_plan_free(self._p)
@@ -166,7 +180,8 @@ class Handle:
     """A built DH^2 matrix on the current HIP device."""
 
     def __init__(self, V, T, kappa, order, eta, leafsize, tol, eta1=10.0, precision=FP64,
-                 max_nrhs=16, stream=None, workspace_gb=0.0, norm=NORM_FROBENIUS):
+                 max_nrhs=16, stream=None, workspace_gb=0.0, norm=NORM_FROBENIUS, rank_mode=RANKS_EXACT,
+                 sketch_rank=0):
         lib = load()
         g, keep = _geometry(V, T)
         opt = Options()
@@ -177,6 +192,8 @@ class Handle:
         opt.stream = stream
         opt.workspace_gb = workspace_gb
         opt.norm = norm
+        opt.rank_mode = rank_mode
+        opt.sketch_rank = sketch_rank
         self.precision = precision
         self.max_nrhs = max_nrhs
         self.n = int(np.asarray(T).shape[0])

@@ -56,6 +56,11 @@ WORKLOADS = {
     "dir8k": Workload("dir8k", "sphere", 32, 16.0, 4, 32, 1e-6, eta=4.0, eta1=2.0),
     # dir2k at the benchmark's tolerance 1e-4 (rank decisions far from FP32 rounding)
     "dir2k_t4": Workload("dir2k_t4", "sphere", 16, 8.0, 3, 16, 1e-4, eta=4.0, eta1=1.0),
+    # the learned-rank family: side-2 cube, m 6 (k = 216), leaf 16, tol 1e-4, with kappa
+    # scaled with sqrt(n) from kappa 64 at n = 524172 (q = 209), the largest member
+    # being far beyond one GPU's memory at leaf 16; these are sizes that fit
+    "cube7k_m6": Workload("cube7k_m6", "cube", 24, 7.35, 6, 16, 1e-4),
+    "cube28k_m6": Workload("cube28k_m6", "cube", 48, 14.7, 6, 16, 1e-4),
     # cube [-1,1]^3 (flat cluster boxes on the faces), low frequency and directional
     "cube768": Workload("cube768", "cube", 8, 4.0, 3, 16, 1e-6, eta=2.0),
     "cube1200dir": Workload("cube1200dir", "cube", 10, 4.0, 3, 16, 1e-6, eta=4.0, eta1=2.0),
