@@ -323,7 +323,9 @@ void dh2_plan_free(dh2_plan p);
  *          DH2_INSPECT_SIGMA_COL   same for the column pass
  *          DH2_INSPECT_OMEGA       index ignored: block weights |G_int restricted to b|_F, n_adm x 1
  *          DH2_INSPECT_BASIS_WEIGHT      index = slot: R_tc with V_tc = P_tc R_tc (eq. (basis_weights_def))
- *          DH2_INSPECT_TOTAL_WEIGHT_ROW  index = slot: Zhat_tc of the row pass (eq. (recomp_weight_full))
+ *          DH2_INSPECT_TOTAL_WEIGHT_ROW  index = slot: Zhat_tc of the row pass (eq. (recomp_weight_full));
+ *                                  for a leaf with #t < k the projected weight, the R factor of
+ *                                  Z_tc^* V_tc^H (rows x #t), whose Gram matrix is V Zhat^H Zhat V^H
  *          DH2_INSPECT_TOTAL_WEIGHT_COL  index = slot: Zhat of the column pass (adjoint matrix)
  *          DH2_INSPECT_COUPLING    index = admissible leaf: S_b = (g_c(xi_t,nu, xi_s,mu)), k x k
  *          DH2_INSPECT_RANK_PRED_ROW  index ignored: learned-rank form, predicted rank of every

@@ -334,6 +334,8 @@ struct Builder {
   Builder(dh2_problem& hh) : h(hh), p(hh.plan) {}
 
   C64* Rp(int64_t q) { return R_d + (size_t)q * k * k; }
+  // leaf slots narrower than k keep projected total weights (see total_weights)
+  bool projected(int64_t q) const { return si[q].leaf && si[q].nrows < k; }
   C64* Zp(bool row, int64_t q) { return (row ? Zr_d : Zc_d) + (size_t)q * k * k; }
   int64_t gdir(int64_t t, int32_t c) { return h.dir_off[p.cl[t].level] + c; }
   int child_index(int64_t t) {
@@ -670,6 +672,13 @@ struct Builder {
   // total weights, top-down (eq. (recomp_weight_full)).  row = true: rows of
   // Z_tc^* are omega_b^{-1} R_sc S_b^* (blocks of row(t,c)) and Zhat_{t+c+} E_{tc+}^*
   // (inherited); row = false: the same for G^* with omega_b^{-1} R_tc S_b.
+  // A leaf's Zhat enters nothing but its own truncation, and only through
+  // V_tc Zhat^H, whose Gram matrix is (Z^* V^H)^H (Z^* V^H): every stacked row
+  // of a leaf slot with #t < k is multiplied by V_tc^H before the fold, which
+  // then factors an M x #t matrix instead of an M x k one.  The slot keeps that #t x #t
+  // factor ("projected total weight", rows rZ) in place of Zhat; the
+  // truncation's SVD of V Zhat^H is its SVD (same singular values and left
+  // singular vectors).
   void total_weights(bool row) {
     const std::vector<uint8_t>& flag = row ? p.slot_row : p.slot_col;
     const std::vector<int64_t>& ptr = row ? p.row_ptr : p.col_ptr;
@@ -729,7 +738,7 @@ struct Builder {
           Item it{a, e, e};
           while (e < srcs[a].size()) {
             const PieceSrc& s = srcs[a][e];
-            const size_t need = (size_t)s.rows * k;
+            const size_t need = (size_t)s.rows * (k + (projected(qs[a]) ? si[qs[a]].nrows : 0));
             if ((s.blockid >= 0 && (int64_t)sblocks.size() >= maxS) ||
                 (prow + need) * sizeof(C64) > wsP)
               break;
@@ -754,12 +763,15 @@ struct Builder {
             }
         std::vector<void*> tmp;
         gen_couplings(sblocks, Sbuf, tmp);
-        std::vector<GemmDesc> gd;
+        std::vector<GemmDesc> gd, gp;
         std::vector<FoldPiece> pieces;
         std::vector<std::pair<size_t, size_t>> item_pieces;  // piece range per item
         size_t sidx = 0, poff = 0;
         for (const Item& it : items) {
           const size_t pb = pieces.size();
+          const int64_t qi = qs[it.a];
+          const bool proj = projected(qi);
+          const int mq = si[qi].nrows;
           for (size_t ee = it.e0; ee < it.e1; ++ee) {
             const PieceSrc& s = srcs[it.a][ee];
             C64* dst = Pbuf + poff;
@@ -780,11 +792,25 @@ struct Builder {
               g.alpha_re = 1.0;
             }
             gd.push_back(g);
-            pieces.push_back({dst, s.rows, s.rows});
+            if (proj) {
+              // the stacked row block times V_tc^H (rows x #t)
+              C64* dp = Pbuf + poff;
+              poff += (size_t)s.rows * mq;
+              GemmDesc gq{};
+              gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
+              gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = mq; gq.N = mq; gq.opB = 2;
+              gq.C = dp; gq.ldc = s.rows;
+              gq.alpha_re = 1.0;
+              gp.push_back(gq);
+              pieces.push_back({dp, s.rows, s.rows});
+            } else {
+              pieces.push_back({dst, s.rows, s.rows});
+            }
           }
           item_pieces.push_back({pb, pieces.size()});
         }
         gemm(gd, tmp);
+        gemm(gp, tmp);
         h.check_launch();
         // TSQR split: fold segments of each item into temporaries when the
         // batch has few slots, merge the temporaries in a tree of 8-way folds
@@ -807,11 +833,12 @@ struct Builder {
         for (size_t ii = 0; ii < items.size(); ++ii) {
           const Item& it = items[ii];
           const int64_t q = qs[it.a];
+          const int nw = projected(q) ? si[q].nrows : k;     // fold width
           const size_t pb = item_pieces[ii].first, pe = item_pieces[ii].second;
           const int64_t np = (int64_t)(pe - pb);
           const int64_t g = std::min<int64_t>(G, np);
           const int last = it.e1 >= srcs[it.a].size() ? 1 : 0;
-          FoldTask fin{Zp(row, q), k, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
+          FoldTask fin{Zp(row, q), nw, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
           if (g <= 1) {
             fin.piece_begin = (int32_t)pb;
             fin.piece_end = (int32_t)pe;
@@ -829,7 +856,7 @@ struct Builder {
               if (sgi == g - 1) se = pe;
               if (se <= sb) continue;
               C64* Rt = new_temp();
-              t1.push_back(FoldTask{Rt, k, k, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
+              t1.push_back(FoldTask{Rt, nw, nw, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
               cur.push_back(Rt);
               sb = se;
             }
@@ -844,15 +871,15 @@ struct Builder {
                 const size_t a1 = std::min(cur.size(), a0 + (size_t)kMerge);
                 C64* Rt = new_temp();
                 const int32_t b0 = (int32_t)(pieces.size() + p2.size());
-                for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], k, k});
-                tiers[lvl].push_back(FoldTask{Rt, k, k, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
+                for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], nw, nw});
+                tiers[lvl].push_back(FoldTask{Rt, nw, nw, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
                 nxt.push_back(Rt);
               }
               cur.swap(nxt);
               ++lvl;
             }
             fin.piece_begin = (int32_t)(pieces.size() + p2.size());
-            for (C64* Rt : cur) p2.push_back({Rt, k, k});
+            for (C64* Rt : cur) p2.push_back({Rt, nw, nw});
             fin.piece_end = (int32_t)(pieces.size() + p2.size());
             t2.push_back(fin);
           }
@@ -863,10 +890,25 @@ struct Builder {
         for (const auto& tier : tiers) count_folds(tier, pieces);
         count_folds(t2, pieces);
         FoldPiece* pd = upload_tmp(pieces, tmp);
-        if (!t1.empty()) launch_fold<double>(upload_tmp(t1, tmp), (int64_t)t1.size(), pd, k, h.stream);
-        for (const auto& tier : tiers)
-          if (!tier.empty()) launch_fold<double>(upload_tmp(tier, tmp), (int64_t)tier.size(), pd, k, h.stream);
-        launch_fold<double>(upload_tmp(t2, tmp), (int64_t)t2.size(), pd, k, h.stream);
+        // full-width (k) and projected (#t) folds in separate launches: the
+        // chunk height follows the launch's largest width
+        auto folds = [&](const std::vector<FoldTask>& ts) {
+          std::vector<FoldTask> wide, narrow;
+          int nmax = 0;
+          for (const FoldTask& t : ts) {
+            if (t.n == k) wide.push_back(t);
+            else {
+              narrow.push_back(t);
+              nmax = std::max(nmax, t.n);
+            }
+          }
+          if (!wide.empty()) launch_fold<double>(upload_tmp(wide, tmp), (int64_t)wide.size(), pd, k, h.stream);
+          if (!narrow.empty())
+            launch_fold<double>(upload_tmp(narrow, tmp), (int64_t)narrow.size(), pd, nmax, h.stream);
+        };
+        folds(t1);
+        for (const auto& tier : tiers) folds(tier);
+        folds(t2);
         h.check_launch();
         free_tmp(tmp);
         // advance
@@ -974,7 +1016,7 @@ struct Builder {
           j.m = si[q].leaf ? si[q].nrows : rank[si[q].child_slot[0]] + rank[si[q].child_slot[1]];
           const int m = j.m, rz = rZ[q];
           j.ell = 0;
-          if (!pred.empty() && m > 0 && rz > 0) {
+          if (!pred.empty() && m > 0 && rz > 0 && !projected(q)) {
             const int want = h.sketch_rank > 0 ? pred[q] : pred[q] + kSketchOversample;
             if (want < m && want < rz) j.ell = std::max(want, 1);
           }
@@ -1057,6 +1099,20 @@ struct Builder {
             const int m = j.m, rz = rZ[j.q];
             if (m == 0 || rz == 0) continue;
             mm = std::max(mm, m);
+            if (projected(j.q)) {
+              // the projected total weight is already the R factor of B
+              SvdTask st{};
+              st.B = Zp(row, j.q); st.ldb = k;
+              st.U = ws + j.u; st.ldu = m;
+              st.sig = sig_d + b * kSigStride;
+              st.rank = rk_d + b;
+              st.scratch = ws + j.sc;
+              st.m = m;
+              st.norm_mode = h.norm_mode;
+              st.eps = h.tol;
+              sv.push_back(st);
+              continue;
+            }
             C64* B = (C64*)(ws + j.b);
             GemmDesc g{};
             g.A = Zp(row, j.q); g.lda = k; g.M = rz; g.K = k;
@@ -1077,10 +1133,12 @@ struct Builder {
             st.eps = h.tol;
             sv.push_back(st);
           }
-          if (ft.empty()) return;
-          count_folds(ft, fp);
-          gemm(g2, tmp);
-          launch_fold<double>(upload_tmp(ft, tmp), (int64_t)ft.size(), upload_tmp(fp, tmp), mm, h.stream);
+          if (sv.empty()) return;
+          if (!ft.empty()) {
+            count_folds(ft, fp);
+            gemm(g2, tmp);
+            launch_fold<double>(upload_tmp(ft, tmp), (int64_t)ft.size(), upload_tmp(fp, tmp), mm, h.stream);
+          }
           launch_jacobi(upload_tmp(sv, tmp), (int64_t)sv.size(), mm, mm, h.stream);
         };
         std::vector<size_t> ex, sk;
@@ -2346,6 +2404,11 @@ dh2_status dh2_inspect(dh2_handle h, int what, int64_t index, double* out, int64
                            : what == DH2_INSPECT_TOTAL_WEIGHT_ROW ? h->rZr : h->rZc;
         r = rows[index];
         c = k;
+        // projected total weights of leaves narrower than k (Z^* V^H): #t columns
+        if (what != DH2_INSPECT_BASIS_WEIGHT) {
+          const Cluster& cl = p.cl[p.slots[index].t];
+          if (cl.leaf() && cl.size < k) c = cl.size;
+        }
         // rows of a k x k column-major buffer: copy column by column
         if (out && r > 0) {
           HIPCHK(hipStreamSynchronize(h->stream));

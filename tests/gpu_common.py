@@ -82,8 +82,14 @@ def check_weight_invariants(h, slots, o, label):
             if (t, c) not in Zo:
                 continue
             Z = h.inspect("total_weight_" + kind, q)
-            G, Go = H(Z) @ Z, H(Zo[(t, c)]) @ Zo[(t, c)]
+            Go = H(Zo[(t, c)]) @ Zo[(t, c)]
+            if o.st.is_leaf(t) and o.st.size[t] < o.k:
+                # projected total weight of a leaf: Gram V Zhat^H Zhat V^H
+                Vo = o.Vleaf[(t, c)]
+                Go = Vo @ Go @ H(Vo)
+            G = H(Z) @ Z
             assert Z.shape[0] <= o.k, (label, kind, q)
+            assert G.shape == Go.shape, (label, kind, q, G.shape, Go.shape)
             assert np.linalg.norm(G - Go) <= 1e-11 * max(np.linalg.norm(Go), 1e-300), (label, kind, q, t, c)
 
 
