@@ -50,6 +50,14 @@ def parse():
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank form")
     ap.add_argument("--learned-cube", default="cube7k_m6", help="cube workload of the learned-rank family")
+    ap.add_argument("--weights", default="gram", choices=["gram", "householder"],
+                    help="factorisation of the total weights in the timed build (gram: Gram matrix on the "
+                         "FP64 matrix cores and pivoted Cholesky; householder: skinny QR)")
+    ap.add_argument("--no-householder-build", action="store_true",
+                    help="skip the comparison build with Householder total weights")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="time the block-row pipeline shapes at build and keep the fastest (1) or use "
+                         "the default shape (0)")
     ap.add_argument("--batch", type=int, default=64, metavar="COUNT",
                     help="problems of the batching form (the recipe's 64; 0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -225,7 +233,7 @@ def cpu_build_baseline(names, dh2, torch):
         tm = time.perf_counter() - t0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=1)
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=1, weights=WEIGHTS)
         torch.cuda.synchronize()
         tg = time.perf_counter() - t0
         h.free()
@@ -273,6 +281,31 @@ def interp_error(w, V, T, X, results, nleaves):
     return out, (st, o.tri, o.structure_s)
 
 
+def householder_build(w, V, T, Xd, Y64, dh2, torch, results):
+    """The same FP64 build with the total weights factored by Householder QR
+    (the construction as stated) beside the Gram form of the timed steps: its
+    build time and phases, and the relative difference of its product."""
+    nrhs = Xd.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1),
+                   weights=dh2.WEIGHTS_HOUSEHOLDER)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    st = h.stats()
+    Yd = torch.empty_like(Xd)
+    h.matvec(Xd, Yd)
+    torch.cuda.synchronize()
+    results["fp64_householder"] = Yd.cpu().numpy()
+    diff = float(torch.linalg.norm(Yd - Y64) / torch.linalg.norm(Y64))
+    h.free()
+    log("householder build %.2f s (total weights %.0f ms), product vs Gram form %.3e"
+        % (tb, st["ms_total_weights"], diff))
+    return {"build_s": round(tb, 3), "total_weights_ms": round(st["ms_total_weights"], 1),
+            "qr_flops": st["qr_flops"], "rel_diff_vs_timed": diff,
+            "rank_mean_row": round(st["rank_mean_row"], 3), "rank_mean_col": round(st["rank_mean_col"], 3)}
+
+
 def fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=None):
     """The FP32 form (or, with precision = BF16X3, its split-BF16x3 variant)
     on the same workload: one build, event-timed matvecs on complex64
@@ -287,7 +320,7 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=precision,
-                   max_nrhs=max(nrhs, 1))
+                   max_nrhs=max(nrhs, 1), weights=WEIGHTS)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     st = h.stats()
@@ -326,6 +359,10 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=None):
                   "FP64 QR and SVD"),
         "build_s": round(tb, 3),
         "build_gemm": {"flops": st["gemm_flops"], "launches": st["gemm_launches"]},
+        "weights": {"timed": args.weights, "gram_taken": bool(st["weights_gram"]),
+                    "householder_build": hh},
+        "mv_shapes": {"autotune": args.autotune, "near": shape_name(st["mv_variant"][0], 0),
+                      "coupling": shape_name(st["mv_variant"][1], 1), "tune_ms": round(st["ms_autotune"], 1)},
         "ranks": {"row_mean": round(st["rank_mean_row"], 2), "row_max": st["rank_max_row"]},
         "matvec_ms": round(mv_ms, 3), "value": round(mv_bytes / (mv_ms * 1e-3) / 1e9, 2), "unit": "GB/s",
         "rel_diff_vs_fp64": err,
@@ -358,7 +395,7 @@ def spectral_form(args, dh2, torch):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=1,
-                       norm=dh2.NORM_SPECTRAL)
+                       norm=dh2.NORM_SPECTRAL, weights=WEIGHTS)
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t0)
         if len(tb) < 2:
@@ -405,7 +442,7 @@ def learned_form(args, w, V, T, X, Y64, dh2, torch, results, st_exact, build_exa
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1),
-                   rank_mode=dh2.RANKS_LEARNED)
+                   rank_mode=dh2.RANKS_LEARNED, weights=WEIGHTS)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     st = h.stats()
@@ -432,7 +469,7 @@ def learned_form(args, w, V, T, X, Y64, dh2, torch, results, st_exact, build_exa
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         hc = dh2.Handle(Vc, Tc, wc.kappa, wc.order, wc.eta, wc.leaf, wc.tol, eta1=wc.eta1, max_nrhs=4,
-                        rank_mode=mode)
+                        rank_mode=mode, weights=WEIGHTS)
         torch.cuda.synchronize()
         tc = time.perf_counter() - t0
         sc = hc.stats()
@@ -468,7 +505,7 @@ def batch_form(args, dh2, torch, count):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
-                       max_nrhs=nrhs)
+                       max_nrhs=nrhs, weights=WEIGHTS)
         torch.cuda.synchronize()
         tb += time.perf_counter() - t0
         st = h.stats()
@@ -486,7 +523,7 @@ def batch_form(args, dh2, torch, count):
         probs.append((V, T, w.kappa, w.order, w.eta, w.leaf, w.tol))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hm = dh2.build_many(probs, precision=dh2.FP32, max_nrhs=nrhs, threads=8)
+    hm = dh2.build_many(probs, precision=dh2.FP32, max_nrhs=nrhs, threads=8, weights=WEIGHTS)
     torch.cuda.synchronize()
     tbm = time.perf_counter() - t0
     same_build = True
@@ -537,6 +574,18 @@ def batch_form(args, dh2, torch, count):
     }
 
 
+# factorisation of the total weights in every build of this run (dh2_options.weights)
+WEIGHTS = 0
+
+# pipeline shapes of the block-row kernel (KU slices, S stages, WPE waves per SIMD)
+SHAPES = [(1, 4, 2), (1, 3, 2), (1, 6, 1), (2, 3, 1)]
+
+
+def shape_name(v, role):
+    ku, stg, wpe = SHAPES[v]
+    return "k_mv_rows_mfma<double,%d,%d,%d,1,%d>" % (ku, stg, role, wpe)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -559,10 +608,14 @@ def main():
     Yd = torch.empty_like(Xd)
     log("workload %s n=%d kappa=%g m=%d leaf=%d tol=%g nrhs=%d" % (w.name, n, w.kappa, w.order, w.leaf, w.tol, nrhs))
 
+    global WEIGHTS
+    WEIGHTS = weights = dh2.WEIGHTS_GRAM if args.weights == "gram" else dh2.WEIGHTS_HOUSEHOLDER
+
     def step():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1))
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1),
+                       autotune=args.autotune, weights=weights)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         t1 = time.perf_counter()
@@ -627,6 +680,9 @@ def main():
     h.free()
 
     results = {"fp64": Y64.cpu().numpy()}
+    hh = None
+    if not args.no_householder_build and args.weights == "gram":
+        hh = householder_build(w, V, T, Xd, Y64, dh2, torch, results)
     fp32 = None
     if not args.no_fp32:
         fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch, results)
@@ -677,15 +733,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s: unit sphere n=%d, kappa=%g, m=%d (k=%d), leaf %d, eta=%g, eta1=%g, "
-                               "tol=%g, %d complex128 right-hand sides, FP64 form"
+                               "tol=%g, %d complex128 right-hand sides, FP64 form, %s total weights"
                                % (w.name, n, w.kappa, w.order, w.order ** 3, w.leaf, w.eta, w.eta1,
-                                  w.tol, nrhs),
+                                  w.tol, nrhs, args.weights),
                    "n": n, "kappa": w.kappa, "order": w.order, "leafsize": w.leaf, "tol": w.tol,
-                   "nrhs": nrhs, "precision": "fp64"},
+                   "nrhs": nrhs, "precision": "fp64", "weights": args.weights},
         "build_s": round(statistics.median(builds), 3),
         "matvec_ms": round(mv_ms, 3),
         "build_phases_ms": {k[3:]: round(v, 1) for k, v in st.items() if k.startswith("ms_")},
         "build_gemm": {"flops": st["gemm_flops"], "launches": st["gemm_launches"]},
+        "weights": {"timed": args.weights, "gram_taken": bool(st["weights_gram"]),
+                    "householder_build": hh},
+        "mv_shapes": {"autotune": args.autotune, "near": shape_name(st["mv_variant"][0], 0),
+                      "coupling": shape_name(st["mv_variant"][1], 1), "tune_ms": round(st["ms_autotune"], 1)},
         "matvec_phases_ms": {k: round(sum(v) / len(v), 4) for k, v in phases.items()},
         "ranks": {"row_max": st["rank_max_row"], "row_mean": round(st["rank_mean_row"], 2),
                   "col_max": st["rank_max_col"], "col_mean": round(st["rank_mean_col"], 2)},
@@ -696,14 +756,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(near_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(near_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic() if args.workload == "sphere131k" else None,
-                     "kernel": "k_mv_rows_mfma<double,1,4,0,1> (near-field block rows on matrix cores)",
+                     "kernel": "%s (near-field block rows on matrix cores)" % shape_name(st["mv_variant"][0], 0),
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4),
                      "measured_peaks": peaks,
                      "frac_of_measured_read": round(near_gbs / peaks["hbm_read_gbs"], 4) if peaks else None,
                      "whole_matvec": {"achieved": round(mv_gbs, 1), "unit": "GB/s",
                                       "frac": round(mv_gbs / HBM_PEAK_GBS, 4), "bytes": mv_bytes,
                                       "ms": round(mv_ms, 4)},
-                     "coupling_kernel": {"kernel": "k_mv_rows_mfma<double,1,4,1,1>", "achieved": round(coup_gbs, 1),
+                     "coupling_kernel": {"kernel": shape_name(st["mv_variant"][1], 1), "achieved": round(coup_gbs, 1),
                                          "unit": "GB/s", "frac": round(coup_gbs / HBM_PEAK_GBS, 4),
                                          "bytes_per_launch": coup_alg, "avg_launch_ms": round(coup_avg, 4)},
                      "build": {"bound": "fp64", "achieved": round(build_tflops, 2), "unit": "TFLOP/s",

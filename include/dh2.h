@@ -92,6 +92,17 @@ typedef enum { DH2_NORM_FROBENIUS = 0, DH2_NORM_SPECTRAL = 1 } dh2_norm;
  *                      each truncation meets the same block-relative bound. */
 typedef enum { DH2_RANKS_EXACT = 0, DH2_RANKS_LEARNED = 1 } dh2_rank_mode;
 
+/* How the total weight matrices Zhat_tc (Section 3.2) are factored.
+ * HOUSEHOLDER: skinny QR of the stacked rows by Householder reflections, as the
+ *   construction of the total weights states.
+ * GRAM: the Gram matrix of the stacked rows (Zhat^H Zhat, a sum of FP64
+ *   matrix-core products over row segments) factored by Cholesky with diagonal
+ *   pivoting, Zhat = R with R^H R = the Gram matrix.  Zhat^H Zhat, which is all
+ *   the truncation uses, is the same up to rounding; rounding now acts on the
+ *   squares of the singular values, so this form is taken only for tol >= 1e-7
+ *   (smaller tolerances use HOUSEHOLDER; dh2_stats.weights_gram says which ran). */
+typedef enum { DH2_WEIGHTS_HOUSEHOLDER = 0, DH2_WEIGHTS_GRAM = 1 } dh2_weights_mode;
+
 /* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then
  * override fields; zero fields take the defaults given here. */
 typedef struct {
@@ -107,6 +118,12 @@ typedef struct {
   int32_t rank_mode;  /* dh2_rank_mode, default DH2_RANKS_EXACT */
   int32_t sketch_rank;/* learned-rank form only: when > 0, every slot's predicted rank is
                          this value and no columns are added (a test hook) */
+  int32_t autotune;   /* pipeline shape of the matrix-core block-row products (near field
+                         and coupling phase): 0 = the default shape; 1 = time every shape
+                         on this handle's own data at the end of the build and keep the
+                         fastest per phase and right-hand-side class (nrhs <= 16, > 16);
+                         2 + v = use shape v everywhere (0 <= v < 4, a test hook) */
+  int32_t weights;    /* dh2_weights_mode, default DH2_WEIGHTS_HOUSEHOLDER */
 } dh2_options;
 
 typedef struct dh2_problem* dh2_handle;
@@ -247,7 +264,9 @@ typedef struct {
   double matvec_bytes_per_rhs; /* additional algorithmic bytes per right-hand side */
   double ms_structure, ms_near, ms_interp, ms_basis_weights, ms_block_weights,
       ms_total_weights, ms_truncation, ms_projection, ms_total;
-  double gemm_flops;        /* real flops of the build's complex matrix products, 8 M N K each */
+  double gemm_flops;        /* real flops of the build's complex matrix products, 8 M N K each
+                               (4 N (N + 1) K for a Hermitian N x N product of which only the
+                               upper triangle is formed) */
   int64_t gemm_launches;    /* kernel launches of those products */
   double qr_flops;          /* real flops of the Householder QR steps of the recompression:
                                folding M rows into an n x n triangular factor counts 8 M n^2,
@@ -267,6 +286,12 @@ typedef struct {
    * tolerance and were truncated exactly, and the time of the rank prediction. */
   int64_t sketch_slots, sketch_fallbacks;
   double ms_rank_predict;
+  /* Pipeline shapes of the block-row products in use: [0] near field and [1]
+   * coupling for nrhs <= 16, [2] and [3] for nrhs > 16; the time the autotuner
+   * took (0 without it). */
+  int32_t mv_variant[4];
+  double ms_autotune;
+  int32_t weights_gram;     /* 1 when the total weights were factored in the Gram form */
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);

@@ -138,6 +138,9 @@ struct dh2_problem {
   int norm_mode = 0;
   int rank_mode = 0;       // DH2_RANKS_EXACT / DH2_RANKS_LEARNED
   int sketch_rank = 0;     // fixed predicted rank of every slot (0 = the predictor's)
+  int autotune = 0;        // dh2_options.autotune
+  int weights_mode = 0;    // dh2_options.weights
+  int mv_var[4] = {0, 0, 0, 0};  // block-row pipeline shape: near / coupling, nrhs <= 16 / > 16
   int device = 0;
   size_t ws_bytes = 0;
   std::vector<void*> allocs;
@@ -203,6 +206,7 @@ struct dh2_problem {
   NearSeg* coup_mf_segs_d = nullptr;
   void* zero16_d = nullptr;             // 16 zero elements, never written after the build
   int64_t n_xh_tr = 0;
+  int64_t n_xh_rows = 0;            // rows of the row-major slot vectors xhT
   int64_t near_matvec_bytes = 0;    // matrix bytes streamed by the near-field kernel
 
   // Stream-ordered allocations on the handle's stream: a release does not wait
@@ -353,7 +357,9 @@ struct Builder {
   // Batched GEMMs launched with grids of exactly their tiles: descriptors are
   // grouped by (row tiles, column tiles) of 32, one launch per group, so no
   // workgroup is started for a tile outside its product.
-  void gemm(const std::vector<GemmDesc>& gd, std::vector<void*>& tmp) {
+  // Batched complex products, grouped by tile counts.  force64: on the FP64
+  // kernel whatever the handle's precision.
+  void gemm(const std::vector<GemmDesc>& gd, std::vector<void*>& tmp, bool force64 = false) {
     if (gd.empty()) return;
     auto key = [](const GemmDesc& g) {
       return std::min((g.M + 31) / 32, 16) * 17 + std::min((g.N + 31) / 32, 16);
@@ -364,7 +370,8 @@ struct Builder {
       if (g.M > 0 && g.N > 0) v.push_back(g);
     if (v.empty()) return;
     std::stable_sort(v.begin(), v.end(), [&](const GemmDesc& a, const GemmDesc& b) { return key(a) < key(b); });
-    for (const GemmDesc& g : v) h.stats.gemm_flops += 8.0 * g.M * g.N * g.K;
+    for (const GemmDesc& g : v)
+      h.stats.gemm_flops += g.upper ? 4.0 * g.N * (g.N + 1.0) * g.K : 8.0 * g.M * g.N * g.K;
     const GemmDesc* d = upload_tmp(v, tmp);
     size_t i0 = 0;
     while (i0 < v.size()) {
@@ -377,7 +384,9 @@ struct Builder {
         ++i1;
       }
       h.stats.gemm_launches += (int64_t)((i1 - i0 + 65534) / 65535);
-      if (h.precision == DH2_BF16X3)
+      if (force64)
+        launch_gemm<double>(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
+      else if (h.precision == DH2_BF16X3)
         launch_gemm_bf16x3(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
       else if (h.precision == DH2_FP32)
         launch_gemm_f32(d + i0, (int64_t)(i1 - i0), maxM, maxN, h.stream);
@@ -679,6 +688,150 @@ struct Builder {
   // factor ("projected total weight", rows rZ) in place of Zhat; the
   // truncation's SVD of V Zhat^H is its SVD (same singular values and left
   // singular vectors).
+  // Stacked rows of the total-weight passes: a piece (block or inherited
+  // rows) of a slot, and a batch item (pieces [e0, e1) of slot a of the level).
+  struct PieceSrc { int64_t q; int64_t blockid; int64_t parent; int rows; };
+  struct Item { size_t a; size_t e0, e1; };
+
+  // Gram form of the total weights: used when the handle asks for it and the
+  // tolerance is at least kGramMinTol (the Gram matrix holds the squares of
+  // the singular values, so those below about 1e-8 of the largest lose their
+  // relative accuracy; the rank rule then looks at singular values of at
+  // least tol times the largest).
+  static constexpr double kGramMinTol = 1e-7;
+  bool use_gram() const { return h.weights_mode == DH2_WEIGHTS_GRAM && h.tol >= kGramMinTol; }
+
+  // One workspace batch of a total-weight pass in the Gram form.  The pieces
+  // of an item are cut into segments of about segT rows, each stored as one
+  // matrix (rows x nw, nw = k or #t for a projected leaf); a segment's Gram
+  // matrix is one FP64 product (upper triangle only); the segments of a slot
+  // are summed into the slot's Gram matrix, which stays in the slot's Zhat
+  // storage while its rows are spread over batches; a slot whose last rows
+  // are in this batch is factored by pivoted Cholesky (Zhat = R, rows = r).
+  void gram_batch(bool row, const std::vector<int64_t>& qs, const std::vector<std::vector<PieceSrc>>& srcs,
+                  const std::vector<Item>& items, std::vector<uint8_t>& started, C64* Sbuf, C64* Pbuf,
+                  C64* Tbuf, int64_t maxT, std::vector<void*>& tmp) {
+    int64_t brows = 0;
+    for (const Item& it : items)
+      for (size_t ee = it.e0; ee < it.e1; ++ee) brows += srcs[it.a][ee].rows;
+    const int64_t segT = std::max<int64_t>(2048, brows / 1024);
+    std::vector<GemmDesc> gd, gp, gg;
+    std::vector<GramSumTask> sums;
+    std::vector<const void*> ssrc;
+    std::vector<PcholTask> chol;
+    size_t sidx = 0, poff = 0;
+    int64_t tcount = 0;
+    int maxnw = 0;
+    for (const Item& it : items) {
+      const int64_t qi = qs[it.a];
+      const bool proj = projected(qi);
+      const int nw = proj ? si[qi].nrows : k;
+      maxnw = std::max(maxnw, nw);
+      std::vector<std::pair<size_t, size_t>> segs;
+      {
+        size_t sb = it.e0;
+        int64_t acc = 0;
+        for (size_t ee = it.e0; ee < it.e1; ++ee) {
+          const int rws = srcs[it.a][ee].rows;
+          if (acc > 0 && acc + rws > segT) {
+            segs.push_back({sb, ee});
+            sb = ee;
+            acc = 0;
+          }
+          acc += rws;
+        }
+        segs.push_back({sb, it.e1});
+      }
+      std::vector<C64*> base(segs.size());
+      std::vector<int32_t> srows(segs.size());
+      for (size_t sg = 0; sg < segs.size(); ++sg) {
+        int64_t rws = 0;
+        for (size_t ee = segs[sg].first; ee < segs[sg].second; ++ee) rws += srcs[it.a][ee].rows;
+        srows[sg] = (int32_t)rws;
+        base[sg] = Pbuf + poff;
+        poff += (size_t)rws * nw;
+      }
+      for (size_t sg = 0; sg < segs.size(); ++sg) {
+        int64_t roff = 0;
+        for (size_t ee = segs[sg].first; ee < segs[sg].second; ++ee) {
+          const PieceSrc& s = srcs[it.a][ee];
+          C64* dst = base[sg] + roff;
+          int ldd = srows[sg];
+          if (proj) {            // k-wide rows first, then times V_tc^H into the segment
+            dst = Pbuf + poff;
+            poff += (size_t)s.rows * k;
+            ldd = s.rows;
+          }
+          GemmDesc g{};
+          g.M = s.rows; g.N = k; g.K = k;
+          g.C = dst; g.ldc = ldd;
+          if (s.blockid >= 0) {
+            const AdmBlock& ab = p.adm[s.blockid];
+            const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
+            g.A = Rp(other); g.lda = k;
+            g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
+            g.alpha_re = 1.0 / h.omega[s.blockid];
+            ++sidx;
+          } else {
+            g.A = Zp(row, s.parent); g.lda = k;
+            g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
+            g.alpha_re = 1.0;
+          }
+          gd.push_back(g);
+          if (proj) {
+            GemmDesc gq{};
+            gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
+            gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = nw; gq.N = nw; gq.opB = 2;
+            gq.C = base[sg] + roff; gq.ldc = srows[sg];
+            gq.alpha_re = 1.0;
+            gp.push_back(gq);
+          }
+          roff += s.rows;
+        }
+      }
+      const bool one = segs.size() == 1;
+      const int32_t s0 = (int32_t)ssrc.size();
+      for (size_t sg = 0; sg < segs.size(); ++sg) {
+        GemmDesc g{};
+        g.A = base[sg]; g.lda = srows[sg]; g.opA = 2;
+        g.B = base[sg]; g.ldb = srows[sg];
+        g.M = nw; g.N = nw; g.K = srows[sg];
+        g.upper = 1;
+        g.alpha_re = 1.0;
+        if (one) {
+          g.C = Zp(row, qi); g.ldc = k;
+          g.accumulate = started[it.a] ? 1 : 0;
+        } else {
+          if (tcount >= maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the Gram temporaries"};
+          C64* Tt = Tbuf + (size_t)tcount * k * k;
+          ++tcount;
+          g.C = Tt; g.ldc = nw;
+          ssrc.push_back(Tt);
+        }
+        gg.push_back(g);
+      }
+      if (!one) sums.push_back(GramSumTask{Zp(row, qi), nw, k, s0, (int32_t)ssrc.size(), started[it.a] ? 0 : 1, 0});
+      if (it.e1 >= srcs[it.a].size()) chol.push_back(PcholTask{Zp(row, qi), nullptr, nw, k, cnt_d + qi});
+      started[it.a] = 1;
+    }
+    gemm(gd, tmp);
+    gemm(gp, tmp);
+    gemm(gg, tmp, true);
+    if (!sums.empty())
+      launch_gram_sum(upload_tmp(sums, tmp), (int64_t)sums.size(), (const void* const*)upload_tmp(ssrc, tmp),
+                      h.stream);
+    if (!chol.empty()) {
+      if (!pchol_fits_lds(maxnw)) {
+        // packed matrices in the temporaries (free once the sums ran)
+        if ((int64_t)chol.size() > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the Cholesky scratch"};
+        for (size_t i = 0; i < chol.size(); ++i) chol[i].scratch = Tbuf + i * (size_t)k * k;
+      }
+      launch_pchol(upload_tmp(chol, tmp), (int64_t)chol.size(), maxnw, h.stream);
+    }
+    h.check_launch();
+    free_tmp(tmp);
+  }
+
   void total_weights(bool row) {
     const std::vector<uint8_t>& flag = row ? p.slot_row : p.slot_col;
     const std::vector<int64_t>& ptr = row ? p.row_ptr : p.col_ptr;
@@ -695,13 +848,13 @@ struct Builder {
     const size_t wsT = ws_bytes - wsS - wsP;
     const int64_t maxS = std::max<int64_t>(1, (int64_t)(wsS / ((size_t)k * k * sizeof(C64))));
     const int64_t maxT = std::max<int64_t>(1, (int64_t)(wsT / ((size_t)k * k * sizeof(C64))));
+    const bool gram = use_gram();
 
     for (int l = 0; l <= p.depth; ++l) {
       std::vector<int64_t> qs;
       for (int64_t q = 0; q < ns; ++q)
         if (si[q].level == l && flag[q]) qs.push_back(q);
       // piece list of every slot of the level: (kind, index)
-      struct PieceSrc { int64_t q; int64_t blockid; int64_t parent; int rows; };
       std::vector<std::vector<PieceSrc>> srcs(qs.size());
       for (size_t a = 0; a < qs.size(); ++a) {
         const int64_t q = qs[a];
@@ -729,7 +882,6 @@ struct Builder {
           continue;
         }
         // collect a batch
-        struct Item { size_t a; size_t e0, e1; };
         std::vector<Item> items;
         std::vector<int64_t> sblocks;
         size_t prow = 0;
@@ -763,154 +915,158 @@ struct Builder {
             }
         std::vector<void*> tmp;
         gen_couplings(sblocks, Sbuf, tmp);
-        std::vector<GemmDesc> gd, gp;
-        std::vector<FoldPiece> pieces;
-        std::vector<std::pair<size_t, size_t>> item_pieces;  // piece range per item
-        size_t sidx = 0, poff = 0;
-        for (const Item& it : items) {
-          const size_t pb = pieces.size();
-          const int64_t qi = qs[it.a];
-          const bool proj = projected(qi);
-          const int mq = si[qi].nrows;
-          for (size_t ee = it.e0; ee < it.e1; ++ee) {
-            const PieceSrc& s = srcs[it.a][ee];
-            C64* dst = Pbuf + poff;
-            poff += (size_t)s.rows * k;
-            GemmDesc g{};
-            g.M = s.rows; g.N = k; g.K = k;
-            g.C = dst; g.ldc = s.rows;
-            if (s.blockid >= 0) {
-              const AdmBlock& ab = p.adm[s.blockid];
-              const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
-              g.A = Rp(other); g.lda = k;
-              g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
-              g.alpha_re = 1.0 / h.omega[s.blockid];
-              ++sidx;
-            } else {
-              g.A = Zp(row, s.parent); g.lda = k;
-              g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
-              g.alpha_re = 1.0;
-            }
-            gd.push_back(g);
-            if (proj) {
-              // the stacked row block times V_tc^H (rows x #t)
-              C64* dp = Pbuf + poff;
-              poff += (size_t)s.rows * mq;
-              GemmDesc gq{};
-              gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
-              gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = mq; gq.N = mq; gq.opB = 2;
-              gq.C = dp; gq.ldc = s.rows;
-              gq.alpha_re = 1.0;
-              gp.push_back(gq);
-              pieces.push_back({dp, s.rows, s.rows});
-            } else {
-              pieces.push_back({dst, s.rows, s.rows});
-            }
-          }
-          item_pieces.push_back({pb, pieces.size()});
-        }
-        gemm(gd, tmp);
-        gemm(gp, tmp);
-        h.check_launch();
-        // TSQR split: fold segments of each item into temporaries when the
-        // batch has few slots, merge the temporaries in a tree of 8-way folds
-        // (in parallel), then fold the last ones into Zhat
-        const int64_t want = 1024;
-        int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
-        G = std::min<int64_t>(G, std::max<int64_t>(1, (maxT * 4 / 5) / (int64_t)items.size()));
-        constexpr int64_t kMerge = 8;
-        std::vector<FoldTask> t1;
-        std::vector<std::vector<FoldTask>> tiers;       // merge levels
-        std::vector<FoldTask> t2;
-        std::vector<FoldPiece> p2;
-        int64_t tcount = 0;
-        auto new_temp = [&]() {
-          C64* Rt = Tbuf + (size_t)tcount * k * k;
-          ++tcount;
-          if (tcount > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the TSQR temporaries"};
-          return Rt;
-        };
-        for (size_t ii = 0; ii < items.size(); ++ii) {
-          const Item& it = items[ii];
-          const int64_t q = qs[it.a];
-          const int nw = projected(q) ? si[q].nrows : k;     // fold width
-          const size_t pb = item_pieces[ii].first, pe = item_pieces[ii].second;
-          const int64_t np = (int64_t)(pe - pb);
-          const int64_t g = std::min<int64_t>(G, np);
-          const int last = it.e1 >= srcs[it.a].size() ? 1 : 0;
-          FoldTask fin{Zp(row, q), nw, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
-          if (g <= 1) {
-            fin.piece_begin = (int32_t)pb;
-            fin.piece_end = (int32_t)pe;
-            t2.push_back(fin);
-          } else {
-            // first level: g segments of the item's pieces, balanced by rows
-            std::vector<int64_t> rows_prefix(np + 1, 0);
-            for (int64_t e = 0; e < np; ++e) rows_prefix[e + 1] = rows_prefix[e] + pieces[pb + e].rows;
-            std::vector<C64*> cur;
-            size_t sb = pb;
-            for (int64_t sgi = 0; sgi < g; ++sgi) {
-              const int64_t target = rows_prefix[np] * (sgi + 1) / g;
-              size_t se = sb;
-              while (se < pe && (rows_prefix[se - pb] < target || se == sb)) ++se;
-              if (sgi == g - 1) se = pe;
-              if (se <= sb) continue;
-              C64* Rt = new_temp();
-              t1.push_back(FoldTask{Rt, nw, nw, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
-              cur.push_back(Rt);
-              sb = se;
-            }
-            // merge levels: groups of kMerge temporaries (all k rows each: in
-            // floating point a compacted factor may keep more nonzero rows
-            // than the rows folded into it)
-            size_t lvl = 0;
-            while ((int64_t)cur.size() > kMerge) {
-              if (tiers.size() <= lvl) tiers.emplace_back();
-              std::vector<C64*> nxt;
-              for (size_t a0 = 0; a0 < cur.size(); a0 += kMerge) {
-                const size_t a1 = std::min(cur.size(), a0 + (size_t)kMerge);
-                C64* Rt = new_temp();
-                const int32_t b0 = (int32_t)(pieces.size() + p2.size());
-                for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], nw, nw});
-                tiers[lvl].push_back(FoldTask{Rt, nw, nw, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
-                nxt.push_back(Rt);
+        if (gram) {
+          gram_batch(row, qs, srcs, items, started, Sbuf, Pbuf, Tbuf, maxT, tmp);
+        } else {
+          std::vector<GemmDesc> gd, gp;
+          std::vector<FoldPiece> pieces;
+          std::vector<std::pair<size_t, size_t>> item_pieces;  // piece range per item
+          size_t sidx = 0, poff = 0;
+          for (const Item& it : items) {
+            const size_t pb = pieces.size();
+            const int64_t qi = qs[it.a];
+            const bool proj = projected(qi);
+            const int mq = si[qi].nrows;
+            for (size_t ee = it.e0; ee < it.e1; ++ee) {
+              const PieceSrc& s = srcs[it.a][ee];
+              C64* dst = Pbuf + poff;
+              poff += (size_t)s.rows * k;
+              GemmDesc g{};
+              g.M = s.rows; g.N = k; g.K = k;
+              g.C = dst; g.ldc = s.rows;
+              if (s.blockid >= 0) {
+                const AdmBlock& ab = p.adm[s.blockid];
+                const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
+                g.A = Rp(other); g.lda = k;
+                g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
+                g.alpha_re = 1.0 / h.omega[s.blockid];
+                ++sidx;
+              } else {
+                g.A = Zp(row, s.parent); g.lda = k;
+                g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
+                g.alpha_re = 1.0;
               }
-              cur.swap(nxt);
-              ++lvl;
+              gd.push_back(g);
+              if (proj) {
+                // the stacked row block times V_tc^H (rows x #t)
+                C64* dp = Pbuf + poff;
+                poff += (size_t)s.rows * mq;
+                GemmDesc gq{};
+                gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
+                gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = mq; gq.N = mq; gq.opB = 2;
+                gq.C = dp; gq.ldc = s.rows;
+                gq.alpha_re = 1.0;
+                gp.push_back(gq);
+                pieces.push_back({dp, s.rows, s.rows});
+              } else {
+                pieces.push_back({dst, s.rows, s.rows});
+              }
             }
-            fin.piece_begin = (int32_t)(pieces.size() + p2.size());
-            for (C64* Rt : cur) p2.push_back({Rt, nw, nw});
-            fin.piece_end = (int32_t)(pieces.size() + p2.size());
-            t2.push_back(fin);
+            item_pieces.push_back({pb, pieces.size()});
           }
-          started[it.a] = 1;
+          gemm(gd, tmp);
+          gemm(gp, tmp);
+          h.check_launch();
+          // TSQR split: fold segments of each item into temporaries when the
+          // batch has few slots, merge the temporaries in a tree of 8-way folds
+          // (in parallel), then fold the last ones into Zhat
+          const int64_t want = 1024;
+          int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
+          G = std::min<int64_t>(G, std::max<int64_t>(1, (maxT * 4 / 5) / (int64_t)items.size()));
+          constexpr int64_t kMerge = 8;
+          std::vector<FoldTask> t1;
+          std::vector<std::vector<FoldTask>> tiers;       // merge levels
+          std::vector<FoldTask> t2;
+          std::vector<FoldPiece> p2;
+          int64_t tcount = 0;
+          auto new_temp = [&]() {
+            C64* Rt = Tbuf + (size_t)tcount * k * k;
+            ++tcount;
+            if (tcount > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the TSQR temporaries"};
+            return Rt;
+          };
+          for (size_t ii = 0; ii < items.size(); ++ii) {
+            const Item& it = items[ii];
+            const int64_t q = qs[it.a];
+            const int nw = projected(q) ? si[q].nrows : k;     // fold width
+            const size_t pb = item_pieces[ii].first, pe = item_pieces[ii].second;
+            const int64_t np = (int64_t)(pe - pb);
+            const int64_t g = std::min<int64_t>(G, np);
+            const int last = it.e1 >= srcs[it.a].size() ? 1 : 0;
+            FoldTask fin{Zp(row, q), nw, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
+            if (g <= 1) {
+              fin.piece_begin = (int32_t)pb;
+              fin.piece_end = (int32_t)pe;
+              t2.push_back(fin);
+            } else {
+              // first level: g segments of the item's pieces, balanced by rows
+              std::vector<int64_t> rows_prefix(np + 1, 0);
+              for (int64_t e = 0; e < np; ++e) rows_prefix[e + 1] = rows_prefix[e] + pieces[pb + e].rows;
+              std::vector<C64*> cur;
+              size_t sb = pb;
+              for (int64_t sgi = 0; sgi < g; ++sgi) {
+                const int64_t target = rows_prefix[np] * (sgi + 1) / g;
+                size_t se = sb;
+                while (se < pe && (rows_prefix[se - pb] < target || se == sb)) ++se;
+                if (sgi == g - 1) se = pe;
+                if (se <= sb) continue;
+                C64* Rt = new_temp();
+                t1.push_back(FoldTask{Rt, nw, nw, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
+                cur.push_back(Rt);
+                sb = se;
+              }
+              // merge levels: groups of kMerge temporaries (all k rows each: in
+              // floating point a compacted factor may keep more nonzero rows
+              // than the rows folded into it)
+              size_t lvl = 0;
+              while ((int64_t)cur.size() > kMerge) {
+                if (tiers.size() <= lvl) tiers.emplace_back();
+                std::vector<C64*> nxt;
+                for (size_t a0 = 0; a0 < cur.size(); a0 += kMerge) {
+                  const size_t a1 = std::min(cur.size(), a0 + (size_t)kMerge);
+                  C64* Rt = new_temp();
+                  const int32_t b0 = (int32_t)(pieces.size() + p2.size());
+                  for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], nw, nw});
+                  tiers[lvl].push_back(FoldTask{Rt, nw, nw, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
+                  nxt.push_back(Rt);
+                }
+                cur.swap(nxt);
+                ++lvl;
+              }
+              fin.piece_begin = (int32_t)(pieces.size() + p2.size());
+              for (C64* Rt : cur) p2.push_back({Rt, nw, nw});
+              fin.piece_end = (int32_t)(pieces.size() + p2.size());
+              t2.push_back(fin);
+            }
+            started[it.a] = 1;
+          }
+          pieces.insert(pieces.end(), p2.begin(), p2.end());
+          count_folds(t1, pieces);
+          for (const auto& tier : tiers) count_folds(tier, pieces);
+          count_folds(t2, pieces);
+          FoldPiece* pd = upload_tmp(pieces, tmp);
+          // full-width (k) and projected (#t) folds in separate launches: the
+          // chunk height follows the launch's largest width
+          auto folds = [&](const std::vector<FoldTask>& ts) {
+            std::vector<FoldTask> wide, narrow;
+            int nmax = 0;
+            for (const FoldTask& t : ts) {
+              if (t.n == k) wide.push_back(t);
+              else {
+                narrow.push_back(t);
+                nmax = std::max(nmax, t.n);
+              }
+            }
+            if (!wide.empty()) launch_fold<double>(upload_tmp(wide, tmp), (int64_t)wide.size(), pd, k, h.stream);
+            if (!narrow.empty())
+              launch_fold<double>(upload_tmp(narrow, tmp), (int64_t)narrow.size(), pd, nmax, h.stream);
+          };
+          folds(t1);
+          for (const auto& tier : tiers) folds(tier);
+          folds(t2);
+          h.check_launch();
+          free_tmp(tmp);
         }
-        pieces.insert(pieces.end(), p2.begin(), p2.end());
-        count_folds(t1, pieces);
-        for (const auto& tier : tiers) count_folds(tier, pieces);
-        count_folds(t2, pieces);
-        FoldPiece* pd = upload_tmp(pieces, tmp);
-        // full-width (k) and projected (#t) folds in separate launches: the
-        // chunk height follows the launch's largest width
-        auto folds = [&](const std::vector<FoldTask>& ts) {
-          std::vector<FoldTask> wide, narrow;
-          int nmax = 0;
-          for (const FoldTask& t : ts) {
-            if (t.n == k) wide.push_back(t);
-            else {
-              narrow.push_back(t);
-              nmax = std::max(nmax, t.n);
-            }
-          }
-          if (!wide.empty()) launch_fold<double>(upload_tmp(wide, tmp), (int64_t)wide.size(), pd, k, h.stream);
-          if (!narrow.empty())
-            launch_fold<double>(upload_tmp(narrow, tmp), (int64_t)narrow.size(), pd, nmax, h.stream);
-        };
-        folds(t1);
-        for (const auto& tier : tiers) folds(tier);
-        folds(t2);
-        h.check_launch();
-        free_tmp(tmp);
         // advance
         const Item& last = items.back();
         a0 = last.a;
@@ -1419,6 +1575,7 @@ struct Builder {
     }
     // staging arena: Xp, XT, Yp (n x nr), slot vectors x_sc, y_tc and the
     // row-major slot vectors xhT, each 256-byte aligned
+    h.n_xh_rows = xrows;
     const int64_t sizes[6] = {n * nr, n * nr, n * nr, xt, yt, xrows * nr};
     size_t offs[6], total = 0;
     for (int i = 0; i < 6; ++i) {
@@ -1668,6 +1825,66 @@ void validate(const dh2_geometry* g, double kappa, int order, double eta, int le
   }
 }
 
+template <typename R>
+void run_matvec_t(dh2_problem* h, const dh2_problem::MvView& v, const void* X, void* Y, int nrhs, hipEvent_t* ev,
+                  hipStream_t st);
+
+// Autotuner of the block-row products.  Each shape is timed inside whole
+// products (the near-field and coupling launches see the caches and clocks
+// they see in use), with the shapes interleaved over four sweeps, the first
+// discarded; per phase and right-hand-side class the shape with the shortest
+// best time is kept (the default unless another beats it by 3 %).
+// Right-hand sides are zero (the timing does not depend on the values).
+template <typename R>
+void tune_block_rows_t(dh2_problem& h) {
+  const hipStream_t st = h.stream;
+  const int64_t n = h.plan.n;
+  const size_t vb = (size_t)n * h.max_nrhs * 2 * sizeof(R);
+  void* Xb = h.alloc<char>(vb);
+  void* Yb = h.alloc<char>(vb);
+  HIPCHK(hipMemsetAsync(Xb, 0, vb, st));
+  hipEvent_t ev[8];
+  for (hipEvent_t& e : ev) HIPCHK(hipEventCreate(&e));
+  const int nv = mv_rows_variants();
+  for (int cls = 0; cls < 2; ++cls) {
+    if (cls == 1 && h.max_nrhs <= 16) {
+      h.mv_var[2] = h.mv_var[0];
+      h.mv_var[3] = h.mv_var[1];
+      break;
+    }
+    const int nrhs = cls == 0 ? std::min(h.max_nrhs, 16) : h.max_nrhs;
+    std::vector<float> best(2 * nv, 1e30f);
+    for (int sweep = 0; sweep < 4; ++sweep)
+      for (int var = 0; var < nv; ++var) {
+        h.mv_var[2 * cls] = h.mv_var[2 * cls + 1] = var;
+        run_matvec_t<R>(&h, h.mv_own, Xb, Yb, nrhs, ev, st);
+        HIPCHK(hipEventSynchronize(ev[7]));
+        if (sweep == 0) continue;
+        float near = 0, coup = 0;
+        HIPCHK(hipEventElapsedTime(&near, ev[4], ev[5]));
+        HIPCHK(hipEventElapsedTime(&coup, ev[2], ev[3]));
+        best[var] = std::min(best[var], near);
+        best[nv + var] = std::min(best[nv + var], coup);
+      }
+    // another shape replaces the default only when it is faster by more than
+    // the run-to-run spread of these timings (about 2 %)
+    for (int role = 0; role < 2; ++role) {
+      int arg = 0;
+      for (int var = 1; var < nv; ++var)
+        if (best[role * nv + var] < 0.97f * best[role * nv + arg]) arg = var;
+      h.mv_var[2 * cls + role] = arg;
+    }
+  }
+  for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
+  h.release(Xb);
+  h.release(Yb);
+}
+
+void tune_block_rows(dh2_problem& h) {
+  if (h.precision != DH2_FP64) tune_block_rows_t<float>(h);
+  else tune_block_rows_t<double>(h);
+}
+
 void build_all(dh2_problem& h, const dh2_geometry& g) {
   const double t_start = now_ms();
   Plan& p = h.plan;
@@ -1825,6 +2042,15 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   if (h.precision != DH2_FP64) bd.narrow_to_fp32();
   bd.matvec_schedule();
   h.sync();
+  if (h.autotune >= 2) {
+    for (int& v : h.mv_var) v = h.autotune - 2;
+  } else if (h.autotune == 1) {
+    t0 = now_ms();
+    tune_block_rows(h);
+    h.stats.ms_autotune = now_ms() - t0;
+  }
+  for (int i = 0; i < 4; ++i) h.stats.mv_variant[i] = h.mv_var[i];
+  h.stats.weights_gram = bd.use_gram() ? 1 : 0;
   h.stats.ms_total = now_ms() - t_start;
 
   // stats
@@ -1923,6 +2149,14 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     g_err = "sketch_rank must be >= 0";
     return DH2_ERR_ARG;
   }
+  if (opt.weights != DH2_WEIGHTS_HOUSEHOLDER && opt.weights != DH2_WEIGHTS_GRAM) {
+    g_err = "unknown weights mode";
+    return DH2_ERR_ARG;
+  }
+  if (opt.autotune < 0 || opt.autotune >= 2 + mv_rows_variants()) {
+    g_err = "autotune must be 0, 1 or 2 + a pipeline shape in [0, " + std::to_string(mv_rows_variants()) + ")";
+    return DH2_ERR_ARG;
+  }
   const double eta1 = opt.eta1 > 0 ? opt.eta1 : 10.0;
   const int max_nrhs = opt.max_nrhs > 0 ? opt.max_nrhs : 16;
   const double wsgb = opt.workspace_gb > 0 ? opt.workspace_gb : 8.0;
@@ -1947,6 +2181,8 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     h->norm_mode = opt.norm;
     h->rank_mode = opt.rank_mode;
     h->sketch_rank = opt.sketch_rank;
+    h->autotune = opt.autotune;
+    h->weights_mode = opt.weights;
     h->plan.kappa = kappa;
     h->plan.order = order;
     h->plan.eta = eta;
@@ -1999,11 +2235,12 @@ void run_matvec_t(dh2_problem* h, const dh2_problem::MvView& v, const void* X, v
   terms(1);
   launch_mv_slot_transpose<R>(v.xh_tr, h->n_xh_tr, v.xhT, nrhs, st);
   mark(2);
-  launch_mv_rows_mfma<R>(v.coup_rows, h->coup_split, h->coup_mf_segs_d, v.xhT, h->zero16_d, nrhs, 1, st);
+  const int* var = h->mv_var + (nrhs > 16 ? 2 : 0);
+  launch_mv_rows_mfma<R>(v.coup_rows, h->coup_split, h->coup_mf_segs_d, v.xhT, h->zero16_d, nrhs, 1, var[1], st);
   mark(3);
   terms(3);
   mark(4);
-  launch_mv_rows_mfma<R>(v.near_rows, h->near_split, h->near_segs_d, v.XT, h->zero16_d, nrhs, 0, st);
+  launch_mv_rows_mfma<R>(v.near_rows, h->near_split, h->near_segs_d, v.XT, h->zero16_d, nrhs, 0, var[0], st);
   mark(5);
   terms(5);
   mark(6);

@@ -302,6 +302,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
   const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
   const int m0 = tm * 32, n0 = tn * 32;
   if (m0 >= d.M || n0 >= d.N) return;
+  if (d.upper && m0 >= n0 + 32) return;
   const cpx<S>* A = (const cpx<S>*)d.A;
   const cpx<S>* B = (const cpx<S>*)d.B;
   cpx<S>* C = (cpx<S>*)d.C;
@@ -1459,6 +1460,157 @@ void launch_fold(const FoldTask* t, int64_t ntasks, const FoldPiece* p, int n, h
 }
 template void launch_fold<double>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
 template void launch_fold<float>(const FoldTask*, int64_t, const FoldPiece*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Gram form of the total weights.
+
+__global__ void __launch_bounds__(256) k_gram_sum(const GramSumTask* __restrict__ tasks,
+                                                  const void* const* __restrict__ srcs) {
+  const GramSumTask t = tasks[blockIdx.x];
+  z64* G = (z64*)t.G;
+  const int nn = t.nw * t.nw;
+  for (int e = blockIdx.y * 256 + threadIdx.x; e < nn; e += 256 * gridDim.y) {
+    const int i = e % t.nw, j = e / t.nw;
+    if (i > j) continue;
+    z64 v = t.init ? z64{0, 0} : G[i + (int64_t)j * t.ldg];
+    for (int q = t.src_begin; q < t.src_end; ++q) v = v + ((const z64*)srcs[q])[e];
+    G[i + (int64_t)j * t.ldg] = v;
+  }
+}
+
+void launch_gram_sum(const GramSumTask* t, int64_t ntasks, const void* const* srcs, hipStream_t st) {
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ntasks, 8), dim3(256), 0, st, t, srcs);
+}
+
+// column of packed upper-triangle entry e (entries of column j are j (j + 1) / 2
+// .. j (j + 1) / 2 + j)
+__device__ __forceinline__ int packed_col(int e) {
+  int j = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  while ((j + 1) * (j + 2) / 2 <= e) ++j;
+  while (j * (j + 1) / 2 > e) --j;
+  return j;
+}
+
+// largest value (smallest index on ties) over the workgroup; red: 8 slots
+__device__ __forceinline__ void argmax256(double& v, int& i, double* rv, int* ri) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(i, off);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rv[w] = v;
+    ri[w] = i;
+  }
+  __syncthreads();
+  v = rv[0];
+  i = ri[0];
+  for (int q = 1; q < 4; ++q)
+    if (rv[q] > v || (rv[q] == v && ri[q] < i)) {
+      v = rv[q];
+      i = ri[q];
+    }
+  __syncthreads();
+}
+
+// Cholesky factorisation with diagonal pivoting of a Hermitian positive
+// semi-definite matrix, outer-product form.  Each step takes the largest
+// remaining diagonal entry of the Schur complement as pivot and stops once it
+// is at or below nw 2^-52 times the largest diagonal entry of G: what remains
+// is rounding noise (for semi-definite matrices this pivoting makes the
+// factorisation backward stable).  Row j of R is the j-th pivot row of the
+// Schur complement divided by the square root of its pivot, kept in the
+// original column order, so that R^H R = G without a permutation.  The
+// matrix is held packed (upper triangle, column by column) in LDS, or in the
+// task's scratch when it does not fit.
+__global__ void __launch_bounds__(256) k_pchol(const PcholTask* __restrict__ tasks, int use_lds) {
+  const PcholTask t = tasks[blockIdx.x];
+  const int nw = t.nw, tid = threadIdx.x;
+  const int64_t ldg = t.ldg;
+  z64* G = (z64*)t.G;
+  const int npk = nw * (nw + 1) / 2;
+  extern __shared__ z64 dyn[];
+  z64* l = dyn;                                   // nw: the current pivot row / sqrt(pivot)
+  double* d = (double*)(dyn + nw);                // nw: diagonal of the Schur complement
+  z64* U = use_lds ? dyn + nw + (nw + 1) / 2 : (z64*)t.scratch;
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  for (int e = tid; e < npk; e += 256) {
+    const int j = packed_col(e), i = e - j * (j + 1) / 2;
+    U[e] = G[i + j * ldg];
+  }
+  for (int i = tid; i < nw; i += 256) d[i] = G[i + i * ldg].x;
+  __syncthreads();
+  double v0 = -INFINITY;
+  int i0 = 0x7fffffff;
+  for (int i = tid; i < nw; i += 256)
+    if (d[i] > v0 || (d[i] == v0 && i < i0)) {
+      v0 = d[i];
+      i0 = i;
+    }
+  argmax256(v0, i0, rv, ri);
+  const double delta = (double)nw * 0x1p-52 * v0;
+  int r = 0;
+  for (int step = 0; step < nw; ++step) {
+    double bv = -INFINITY;
+    int p = 0x7fffffff;
+    for (int i = tid; i < nw; i += 256)
+      if (d[i] > bv || (d[i] == bv && i < p)) {
+        bv = d[i];
+        p = i;
+      }
+    argmax256(bv, p, rv, ri);
+    if (!(bv > delta) || !(v0 > 0.0)) break;
+    const double piv = sqrt(bv), ipiv = 1.0 / piv;
+    for (int i = tid; i < nw; i += 256) {
+      z64 li{0, 0};
+      if (i != p && d[i] != -INFINITY) {
+        const z64 g = p <= i ? U[i * (i + 1) / 2 + p] : conj(U[p * (p + 1) / 2 + i]);
+        li = ipiv * g;
+      }
+      l[i] = li;
+      G[step + i * ldg] = i == p ? z64{piv, 0.0} : li;
+    }
+    __syncthreads();
+    if (tid == 0) d[p] = -INFINITY;
+    for (int e = tid; e < npk; e += 256) {
+      const int j = packed_col(e), i = e - j * (j + 1) / 2;
+      const z64 li = l[i], lj = l[j];
+      if ((li.x == 0.0 && li.y == 0.0) || (lj.x == 0.0 && lj.y == 0.0)) continue;
+      z64 u = U[e];
+      u.x -= li.x * lj.x + li.y * lj.y;
+      u.y -= li.x * lj.y - li.y * lj.x;
+      U[e] = u;
+      if (i == j) d[i] = u.x;
+    }
+    __syncthreads();
+    r = step + 1;
+  }
+  const int rest = nw - r;
+  for (int e = tid; e < rest * nw; e += 256) {
+    const int i = r + e % rest, j = e / rest;
+    G[i + j * ldg] = z64{0, 0};
+  }
+  if (tid == 0 && t.count) *t.count = r;
+}
+
+size_t pchol_lds_bytes(int nw) {
+  return ((size_t)nw * (nw + 1) / 2 + (size_t)nw + (size_t)(nw + 1) / 2) * 16;
+}
+
+bool pchol_fits_lds(int nw) { return pchol_lds_bytes(nw) <= g_lds_limit; }
+
+void launch_pchol(const PcholTask* t, int64_t ntasks, int maxnw, hipStream_t st) {
+  if (ntasks <= 0) return;
+  const int use_lds = pchol_fits_lds(maxnw) ? 1 : 0;
+  const size_t lds = use_lds ? pchol_lds_bytes(maxnw) : ((size_t)maxnw + (size_t)(maxnw + 1) / 2) * 16;
+  hipLaunchKernelGGL(k_pchol, dim3((unsigned)ntasks), dim3(256), lds, st, t, use_lds);
+}
 
 void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, int maxr, hipStream_t st) {
   if (ntasks <= 0) return;

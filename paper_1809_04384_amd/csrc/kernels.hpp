@@ -49,7 +49,8 @@ struct GemmDesc {
   int32_t M, N, K, lda, ldb, ldc;
   int32_t opA, opB;   // 0 = N, 1 = T, 2 = C (conjugate transpose)
   int32_t accumulate;
-  int32_t pad;
+  int32_t upper;      // FP64 kernel only: skip the 32 x 32 tiles of C below its diagonal
+                      // (a Hermitian product whose upper triangle is all that is read)
   double alpha_re, alpha_im;
 };
 
@@ -66,6 +67,31 @@ struct FoldPiece {
   const void* P;      // rows x n complex of the piece precision, column-major
   int32_t rows, ld;
 };
+
+// Gram form of the total weights.  A slot's Gram matrix is the sum of the
+// Gram matrices of its stacked-row segments; k_gram_sum adds the segments'
+// upper triangles into the slot's (init: starting from zero), k_pchol turns it
+// into a factor R with R^H R = G.
+struct GramSumTask {
+  void* G;            // nw x nw FP64 complex, leading dimension ldg (upper triangle written)
+  int32_t nw, ldg;
+  int32_t src_begin, src_end;   // source matrices nw x nw, leading dimension nw
+  int32_t init, pad;
+};
+void launch_gram_sum(const GramSumTask* t, int64_t ntasks, const void* const* srcs, hipStream_t st);
+
+struct PcholTask {
+  void* G;            // in: Hermitian positive semi-definite nw x nw, leading dimension ldg
+                      // (upper triangle read); out: R in rows 0 .. r-1 (nw columns, the
+                      // original column order), rows r .. nw-1 zero
+  void* scratch;      // nw (nw + 1) / 2 complex doubles, used when they do not fit in LDS
+  int32_t nw, ldg;
+  int32_t* count;     // receives r
+};
+// bytes of LDS k_pchol needs for order nw when the packed matrix is held there
+size_t pchol_lds_bytes(int nw);
+bool pchol_fits_lds(int nw);
+void launch_pchol(const PcholTask* t, int64_t ntasks, int maxnw, hipStream_t st);
 
 struct SvdTask {
   const void* B;      // rows x m FP64 complex, leading dimension ldb (exact truncation: the

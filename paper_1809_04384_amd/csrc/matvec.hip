@@ -85,6 +85,23 @@ __device__ __forceinline__ cpx<R> gload(const cpx<R>* p) {
   return cpx<R>{v.x, v.y};
 }
 
+// The matrix entries are read once per product: in FP64, non-temporal loads
+// keep them from displacing the right-hand-side rows, which the neighbouring
+// rows of the same XCD read again, from L2 (near field 9.3 -> 8.8 ms at
+// n = 131k).  The 8-byte complex64 loads of FP32 stream faster as ordinary
+// loads (5.0 ms against 5.4 ms non-temporal).
+template <typename R>
+__device__ __forceinline__ cpx<R> gload_nt(const cpx<R>* p) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  if constexpr (sizeof(R) == 8) {
+    const v2 v = __builtin_nontemporal_load((const __attribute__((address_space(1))) v2*)p);
+    return cpx<R>{v.x, v.y};
+  } else {
+    const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+    return cpx<R>{v.x, v.y};
+  }
+}
+
 // One pass of a block row: rows [r0, r0 + nr) (NT = ceil(nr / 16) row tiles)
 // and right-hand sides [c0, c0 + 16), over the T steps of this wave; the wave
 // partial sums are added into red[rhs][row] (one wave after the other).
@@ -132,7 +149,7 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
           fx[u][ch] = gload(xp);
         }
 #pragma unroll
-        for (int rt = 0; rt < NT; ++rt) fa[u][rt] = gload(A + min(rt * 16 + rr, nr - 1) + (int64_t)jc * fs.lda);
+        for (int rt = 0; rt < NT; ++rt) fa[u][rt] = gload_nt(A + min(rt * 16 + rr, nr - 1) + (int64_t)jc * fs.lda);
       }
     };
     auto advance = [&]() {
@@ -190,13 +207,10 @@ __device__ __forceinline__ void mf_pass(const MfRow& rw, const NearSeg* __restri
   }
 }
 
-#ifndef DH2_MF_WPE
-#define DH2_MF_WPE 2
-#endif
 // ROLE only names the instantiation (0 near field, 1 coupling) so that the two
 // uses are told apart in kernel traces.
-template <typename R, int KU, int S, int ROLE, int NC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF_WPE))) k_mv_rows_mfma(const MfRow* __restrict__ rows,
+template <typename R, int KU, int S, int ROLE, int NC, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_mv_rows_mfma(const MfRow* __restrict__ rows,
                                                       const NearSeg* __restrict__ segs,
                                                       const cpx<R>* __restrict__ XT,
                                                       const cpx<R>* __restrict__ zero16, int nrhs,
@@ -234,45 +248,56 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DH2_MF
   }
 }
 
-#ifndef DH2_MF_KU
-#define DH2_MF_KU 1
-#endif
-#ifndef DH2_MF_S
-#define DH2_MF_S 4
-#endif
+// Pipeline shapes of the block-row kernel, picked per handle and role by the
+// build's autotuner (dh2_options.autotune): KU 4-column slices per step, S
+// register stages, WPE waves per SIMD the register allocation is sized for.
+// Variant 0 is the default.
+template <typename R, int ROLE, int NC>
+static void launch_variant(int variant, dim3 g, const MfRow* rows, const NearSeg* segs, const cpx<R>* xt,
+                           const cpx<R>* z, int nrhs, const XcdSplit& split, hipStream_t st) {
+  const dim3 b(256);
+  switch (variant) {
+    case 1:
+      hipLaunchKernelGGL((k_mv_rows_mfma<R, 1, 3, ROLE, NC, 2>), g, b, 0, st, rows, segs, xt, z, nrhs, split);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_mv_rows_mfma<R, 1, 6, ROLE, NC, 1>), g, b, 0, st, rows, segs, xt, z, nrhs, split);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_mv_rows_mfma<R, 2, 3, ROLE, NC, 1>), g, b, 0, st, rows, segs, xt, z, nrhs, split);
+      break;
+    default:
+      hipLaunchKernelGGL((k_mv_rows_mfma<R, 1, 4, ROLE, NC, 2>), g, b, 0, st, rows, segs, xt, z, nrhs, split);
+      break;
+  }
+}
+
+int mv_rows_variants() { return 4; }
 
 template <typename R>
 void launch_mv_rows_mfma(const MfRow* rows, const XcdSplit& split, const NearSeg* segs, const void* XT,
-                         const void* zero16, int nrhs, int role, hipStream_t st) {
+                         const void* zero16, int nrhs, int role, int variant, hipStream_t st) {
   if (split.width <= 0) return;
   // FP32 with more than 16 right-hand sides: two 16-wide chunks per pass, so
   // the matrix is streamed once per 32 right-hand sides (FP64 accumulators
   // for two chunks would not fit the registers of two waves per SIMD)
-  const dim3 g((unsigned)(8 * split.width)), b(256);
+  const dim3 g((unsigned)(8 * split.width));
   const cpx<R>* xt = (const cpx<R>*)XT;
   const cpx<R>* z = (const cpx<R>*)zero16;
   if constexpr (sizeof(R) == 4) {
     if (nrhs > 16) {
-      if (role == 0)
-        hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0, 2>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                           split);
-      else
-        hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1, 2>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                           split);
+      if (role == 0) launch_variant<R, 0, 2>(variant, g, rows, segs, xt, z, nrhs, split, st);
+      else launch_variant<R, 1, 2>(variant, g, rows, segs, xt, z, nrhs, split, st);
       return;
     }
   }
-  if (role == 0)
-    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 0, 1>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                       split);
-  else
-    hipLaunchKernelGGL((k_mv_rows_mfma<R, DH2_MF_KU, DH2_MF_S, 1, 1>), g, b, 0, st, rows, segs, xt, z, nrhs,
-                       split);
+  if (role == 0) launch_variant<R, 0, 1>(variant, g, rows, segs, xt, z, nrhs, split, st);
+  else launch_variant<R, 1, 1>(variant, g, rows, segs, xt, z, nrhs, split, st);
 }
 template void launch_mv_rows_mfma<double>(const MfRow*, const XcdSplit&, const NearSeg*, const void*, const void*,
-                                          int, int, hipStream_t);
+                                          int, int, int, hipStream_t);
 template void launch_mv_rows_mfma<float>(const MfRow*, const XcdSplit&, const NearSeg*, const void*, const void*,
-                                         int, int, hipStream_t);
+                                         int, int, int, hipStream_t);
 
 // row-major copies of the slot vectors x_sc (k x nrhs, leading dimension k):
 // dst[(row0 + j) * nrhs + r] = src[j + r k]; a workgroup per slot

@@ -58,9 +58,11 @@ struct XcdSplit {
 };
 // zero16: 16 zero elements (device), read in place of right-hand-side entries
 // outside a segment.  role: 0 near field, 1 coupling (names the kernel only).
+// variant: pipeline shape, 0 .. mv_rows_variants() - 1 (0 = default).
 template <typename R>
 void launch_mv_rows_mfma(const MfRow* rows, const XcdSplit& split, const NearSeg* segs, const void* XT,
-                         const void* zero16, int nrhs, int role, hipStream_t st);
+                         const void* zero16, int nrhs, int role, int variant, hipStream_t st);
+int mv_rows_variants();
 
 // Row-major copy of one slot vector: dst[(row0 + j) * nrhs + r] = src[j + r k].
 struct SlotT {

@@ -17,6 +17,7 @@ DH2_OK = 0
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_GEOMETRY", 3: "ERR_OOM", 4: "ERR_DEVICE", 5: "ERR_NUMERIC"}
 FP64, FP32, BF16X3 = 0, 1, 2
 RANKS_EXACT, RANKS_LEARNED = 0, 1
+WEIGHTS_HOUSEHOLDER, WEIGHTS_GRAM = 0, 1
 NORM_FROBENIUS, NORM_SPECTRAL = 0, 1
 INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col": 5,
            "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
@@ -44,7 +45,8 @@ class Options(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("eta1", ctypes.c_double),
                 ("max_nrhs", ctypes.c_int32), ("norm", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace_gb", ctypes.c_double),
-                ("rank_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32)]
+                ("rank_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("weights", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -68,7 +70,9 @@ class Stats(ctypes.Structure):
                 ("batches_truncation", ctypes.c_int64),
                 ("batches_projection", ctypes.c_int64), ("slots_straddled", ctypes.c_int64),
                 ("coupling_regeneration", ctypes.c_double), ("sketch_slots", ctypes.c_int64),
-                ("sketch_fallbacks", ctypes.c_int64), ("ms_rank_predict", ctypes.c_double)]
+                ("sketch_fallbacks", ctypes.c_int64), ("ms_rank_predict", ctypes.c_double),
+                ("mv_variant", ctypes.c_int32 * 4), ("ms_autotune", ctypes.c_double),
+                ("weights_gram", ctypes.c_int32)]
 
 
 class PlanSizes(ctypes.Structure):
@@ -181,7 +185,7 @@ class Handle:
 
     def __init__(self, V, T, kappa, order, eta, leafsize, tol, eta1=10.0, precision=FP64,
                  max_nrhs=16, stream=None, workspace_gb=0.0, norm=NORM_FROBENIUS, rank_mode=RANKS_EXACT,
-                 sketch_rank=0):
+                 sketch_rank=0, autotune=0, weights=0):
         lib = load()
         g, keep = _geometry(V, T)
         opt = Options()
@@ -194,6 +198,8 @@ class Handle:
         opt.norm = norm
         opt.rank_mode = rank_mode
         opt.sketch_rank = sketch_rank
+        opt.autotune = autotune
+        opt.weights = weights
         self.precision = precision
         self.max_nrhs = max_nrhs
         self.n = int(np.asarray(T).shape[0])
@@ -244,7 +250,9 @@ class Handle:
         s = Stats()
         s.size = ctypes.sizeof(Stats)
         _check(load().dh2_get_stats(self._h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "size"}
+        out = {f: getattr(s, f) for f, _ in Stats._fields_ if f != "size"}
+        out["mv_variant"] = list(out["mv_variant"])
+        return out
 
     def inspect(self, what, index=0):
         lib = load()
@@ -307,7 +315,7 @@ class Batch:
 
 
 def build_many(problems, precision=FP64, max_nrhs=16, eta1=10.0, norm=NORM_FROBENIUS, threads=0,
-               workspace_gb=0.0):
+               workspace_gb=0.0, weights=WEIGHTS_HOUSEHOLDER):
     """Handles for many problems built side by side (dh2_build_many): problems is
     a list of (V, T, kappa, order, eta, leafsize, tol); every handle owns a
     stream of its own."""
@@ -332,6 +340,7 @@ def build_many(problems, precision=FP64, max_nrhs=16, eta1=10.0, norm=NORM_FROBE
     opt.eta1 = eta1
     opt.max_nrhs = max_nrhs
     opt.workspace_gb = workspace_gb
+    opt.weights = weights
     opt.norm = norm
     out = (ctypes.c_void_p * cnt)()
     _check(lib.dh2_build_many(cnt, geoms, kap, order, eta, leaf, tol, ctypes.byref(opt), threads, out))

@@ -63,6 +63,8 @@ WORKLOADS = {
     "cube28k_m6": Workload("cube28k_m6", "cube", 48, 14.7, 6, 16, 1e-4),
     # cube [-1,1]^3 (flat cluster boxes on the faces), low frequency and directional
     "cube768": Workload("cube768", "cube", 8, 4.0, 3, 16, 1e-6, eta=2.0),
+    # order 6 (k = 216) on the same surface: inner clusters with full-width weights
+    "cube768_m6": Workload("cube768_m6", "cube", 8, 4.0, 6, 16, 1e-6, eta=2.0),
     "cube1200dir": Workload("cube1200dir", "cube", 10, 4.0, 3, 16, 1e-6, eta=4.0, eta1=2.0),
 }
 

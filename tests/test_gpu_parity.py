@@ -74,6 +74,60 @@ def test_matvec_rhs_counts(name):
         h.free()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pipeline_shapes_and_autotune(precision):
+    """Every pipeline shape of the block-row products (forced through the
+    autotune hook) gives the product of the default shape, for one ragged and
+    one two-tile right-hand-side count; an autotuned handle records the shapes
+    it picked, each a valid one, and its product matches the oracle."""
+    import torch
+    from paper_1809_04384_amd import dh2
+    name = "dir2k"
+    o = oracle_for(name)
+    w = synth.WORKLOADS[name]
+    V, T = synth.make_mesh(w)
+    prec = dh2.FP64 if precision == "fp64" else dh2.FP32
+    ctype = torch.complex128 if precision == "fp64" else torch.complex64
+    # against the oracle: the bounds of the FP64 and FP32 forms; between
+    # shapes: rounding of the product alone
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    tol_shape = 1e-12 if precision == "fp64" else 1e-5
+    first = {}
+    ref = {}
+    for nrhs in (1, 20):
+        X = synth.complex_gaussian(o.n, nrhs, seed=40 + nrhs)
+        Yo = o.matvec(X.T).T
+        ref[nrhs] = (X, Yo)
+    for mode in [2 + v for v in range(4)] + [1]:
+        h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=prec,
+                       max_nrhs=20, autotune=mode)
+        try:
+            st = h.stats()
+            say("[gpu] %s %s autotune=%d shapes %s (%.1f ms)" % (name, precision, mode, st["mv_variant"],
+                                                                 st["ms_autotune"]))
+            if mode >= 2:
+                assert st["mv_variant"] == [mode - 2] * 4
+                assert st["ms_autotune"] == 0
+            else:
+                assert all(0 <= v < 4 for v in st["mv_variant"])
+                assert st["ms_autotune"] > 0
+            for nrhs, (X, Yo) in ref.items():
+                Xd = torch.from_numpy(np.ascontiguousarray(X)).to("cuda:0").to(ctype)
+                Yd = torch.empty_like(Xd)
+                h.matvec(Xd, Yd)
+                torch.cuda.synchronize()
+                Y = Yd.cpu().numpy().astype(np.complex128)
+                for r in range(nrhs):
+                    err = rel(Y[r], Yo[r])
+                    assert err <= tol, (mode, nrhs, r, err)
+                if nrhs in first:
+                    assert rel(Y, first[nrhs]) <= tol_shape, (mode, nrhs, rel(Y, first[nrhs]))
+                else:
+                    first[nrhs] = Y
+        finally:
+            h.free()
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_near_field_elementwise(name):
     o = oracle_for(name)
