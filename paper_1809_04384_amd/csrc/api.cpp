@@ -693,143 +693,266 @@ struct Builder {
   struct PieceSrc { int64_t q; int64_t blockid; int64_t parent; int rows; };
   struct Item { size_t a; size_t e0, e1; };
 
-  // Gram form of the total weights: used when the handle asks for it and the
-  // tolerance is at least kGramMinTol (the Gram matrix holds the squares of
+  // Gram form of the block and total weights: used when the handle asks for
+  // it and the tolerance is at least kGramMinTol (the Gram matrix holds the squares of
   // the singular values, so those below about 1e-8 of the largest lose their
   // relative accuracy; the rank rule then looks at singular values of at
   // least tol times the largest).
   static constexpr double kGramMinTol = 1e-7;
   bool use_gram() const { return h.weights_mode == DH2_WEIGHTS_GRAM && h.tol >= kGramMinTol; }
 
-  // One workspace batch of a total-weight pass in the Gram form.  The pieces
-  // of an item are cut into segments of about segT rows, each stored as one
-  // matrix (rows x nw, nw = k or #t for a projected leaf); a segment's Gram
-  // matrix is one FP64 product (upper triangle only); the segments of a slot
-  // are summed into the slot's Gram matrix, which stays in the slot's Zhat
-  // storage while its rows are spread over batches; a slot whose last rows
-  // are in this batch is factored by pivoted Cholesky (Zhat = R, rows = r).
-  void gram_batch(bool row, const std::vector<int64_t>& qs, const std::vector<std::vector<PieceSrc>>& srcs,
-                  const std::vector<Item>& items, std::vector<uint8_t>& started, C64* Sbuf, C64* Pbuf,
-                  C64* Tbuf, int64_t maxT, std::vector<void*>& tmp) {
-    int64_t brows = 0;
-    for (const Item& it : items)
-      for (size_t ee = it.e0; ee < it.e1; ++ee) brows += srcs[it.a][ee].rows;
-    const int64_t segT = std::max<int64_t>(2048, brows / 1024);
-    std::vector<GemmDesc> gd, gp, gg;
-    std::vector<GramSumTask> sums;
-    std::vector<const void*> ssrc;
-    std::vector<PcholTask> chol;
-    size_t sidx = 0, poff = 0;
-    int64_t tcount = 0;
-    int maxnw = 0;
-    for (const Item& it : items) {
-      const int64_t qi = qs[it.a];
-      const bool proj = projected(qi);
-      const int nw = proj ? si[qi].nrows : k;
-      maxnw = std::max(maxnw, nw);
-      std::vector<std::pair<size_t, size_t>> segs;
-      {
-        size_t sb = it.e0;
-        int64_t acc = 0;
-        for (size_t ee = it.e0; ee < it.e1; ++ee) {
-          const int rws = srcs[it.a][ee].rows;
-          if (acc > 0 && acc + rws > segT) {
-            segs.push_back({sb, ee});
-            sb = ee;
-            acc = 0;
-          }
-          acc += rws;
+  // ------------------------------------------------------------------
+  // Gram form of the block and total weights (dh2_options.weights = GRAM).
+  // The total weight of a slot enters the truncation only through
+  // Zhat^H Zhat, the Gram matrix of its stacked rows, and a Gram matrix is a
+  // sum: G_tc = sum over the blocks b of row (t, c) of omega_b^-2
+  // (R_sc S_b^H)^H (R_sc S_b^H), plus E G_{t+c+} E^H for the inherited rows
+  // (the same for the column side with R_tc S_b).  The block part needs no
+  // parent, so it is accumulated in the block-weight pass, which generates
+  // S_b and forms R_tc S_b anyway (its omega_b is the norm of R_tc S_b R_sc^H):
+  // per batch of blocks the rows R_tc S_b and R_sc S_b^H are formed into
+  // per-slot segments, scaled by 1 / omega_b once omega_b is known, and the
+  // Gram matrix of each segment is added to its slot's on the FP64 matrix
+  // cores (segments of one slot in separate launches, so no two products add
+  // to one matrix at once).  The top-down pass then adds the inherited rows
+  // Zhat_{t+c+} E^H level by level, projects leaf slots narrower than k
+  // (V G V^H), and factors every Gram matrix by pivoted Cholesky (Zhat = R).
+  // S_b is generated once for block and total weights (instead of three
+  // times), and R_tc S_b once (instead of twice).
+  void weights_gram() {
+    const int64_t nb = (int64_t)p.adm.size();
+    const size_t kk = (size_t)k * k;
+    double* om_d = h.alloc<double>(nb);
+    Zr_d = h.alloc<C64>((size_t)ns * kk);
+    Zc_d = h.alloc<C64>((size_t)ns * kk);
+    HIPCHK(hipMemsetAsync(Zr_d, 0, (size_t)ns * kk * sizeof(C64), h.stream));
+    HIPCHK(hipMemsetAsync(Zc_d, 0, (size_t)ns * kk * sizeof(C64), h.stream));
+    rZr.assign(ns, 0);
+    rZc.assign(ns, 0);
+    // per block: S_b, scratch of the spectral norm, R_tc S_b R_sc^H, and at
+    // most two k x k of stacked rows
+    const size_t per = 5 * kk * sizeof(C64);
+    if (per > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for one block of the Gram weights"};
+    const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
+    constexpr int64_t kSegRows = 2048;
+    for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+      const int64_t b1 = std::min(nb, b0 + batch);
+      const size_t nbat = (size_t)(b1 - b0);
+      std::vector<int64_t> blocks;
+      for (int64_t b = b0; b < b1; ++b) blocks.push_back(b);
+      C64* S = (C64*)ws;
+      C64* T1 = S + nbat * kk;
+      C64* T2 = T1 + nbat * kk;
+      C64* P = T2 + nbat * kk;
+      std::vector<void*> tmp;
+      ++h.stats.batches_block_weights;
+      gen_couplings(blocks, S, tmp);
+      // stacked rows of the batch: entries (slot, block) of both sides,
+      // grouped by slot, cut into segments of about kSegRows rows
+      struct Ent { int64_t q; int64_t b; int rows; };
+      std::vector<C64*> colpiece(nbat, nullptr);
+      std::vector<int32_t> colld(nbat, 0);
+      std::vector<GemmDesc> gpc, g2, gg;
+      std::vector<ScaleTask> sc;
+      std::vector<std::vector<GemmDesc>> rounds;
+      size_t poff = 0;
+      for (int side = 0; side < 2; ++side) {          // 0: column slots, 1: row slots
+        const bool row = side == 1;
+        std::vector<Ent> ents;
+        for (int64_t b = b0; b < b1; ++b) {
+          const AdmBlock& a = p.adm[b];
+          const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
+          const int64_t q = row ? qt : qs;
+          const int rows = row ? rR[qs] : rR[qt];
+          if ((row ? p.slot_row[q] : p.slot_col[q]) && rows > 0) ents.push_back({q, b, rows});
         }
-        segs.push_back({sb, it.e1});
-      }
-      std::vector<C64*> base(segs.size());
-      std::vector<int32_t> srows(segs.size());
-      for (size_t sg = 0; sg < segs.size(); ++sg) {
-        int64_t rws = 0;
-        for (size_t ee = segs[sg].first; ee < segs[sg].second; ++ee) rws += srcs[it.a][ee].rows;
-        srows[sg] = (int32_t)rws;
-        base[sg] = Pbuf + poff;
-        poff += (size_t)rws * nw;
-      }
-      for (size_t sg = 0; sg < segs.size(); ++sg) {
-        int64_t roff = 0;
-        for (size_t ee = segs[sg].first; ee < segs[sg].second; ++ee) {
-          const PieceSrc& s = srcs[it.a][ee];
-          C64* dst = base[sg] + roff;
-          int ldd = srows[sg];
-          if (proj) {            // k-wide rows first, then times V_tc^H into the segment
-            dst = Pbuf + poff;
-            poff += (size_t)s.rows * k;
-            ldd = s.rows;
+        std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.q < y.q; });
+        size_t e = 0;
+        while (e < ents.size()) {
+          const int64_t q = ents[e].q;
+          int round = 0;
+          while (e < ents.size() && ents[e].q == q) {
+            size_t f = e;
+            int64_t rows = 0;
+            while (f < ents.size() && ents[f].q == q && (f == e || rows + ents[f].rows <= kSegRows)) rows += ents[f++].rows;
+            C64* base = P + poff;
+            poff += (size_t)rows * k;
+            int64_t roff = 0;
+            for (size_t g = e; g < f; ++g) {
+              const AdmBlock& a = p.adm[ents[g].b];
+              const size_t i = (size_t)(ents[g].b - b0);
+              const int64_t other = row ? p.slot_of(a.s, a.c) : p.slot_of(a.t, a.c);
+              GemmDesc d{};
+              d.A = Rp(other); d.lda = k; d.M = ents[g].rows; d.K = k;
+              d.B = S + i * kk; d.ldb = k; d.N = k; d.opB = row ? 2 : 0;
+              d.C = base + roff; d.ldc = (int32_t)rows;
+              d.alpha_re = 1.0;
+              gpc.push_back(d);
+              if (!row) {
+                colpiece[i] = base + roff;
+                colld[i] = (int32_t)rows;
+              }
+              sc.push_back(ScaleTask{base + roff, ents[g].rows, k, (int32_t)rows, 0, ents[g].b});
+              roff += ents[g].rows;
+            }
+            GemmDesc d{};
+            d.A = base; d.lda = (int32_t)rows; d.opA = 2;
+            d.B = base; d.ldb = (int32_t)rows;
+            d.M = k; d.N = k; d.K = (int32_t)rows;
+            d.C = Zp(row, q); d.ldc = k;
+            d.accumulate = 1;
+            d.upper = projected(q) ? 0 : 1;       // leaf projections need the whole matrix
+            d.alpha_re = 1.0;
+            if ((int)rounds.size() <= round) rounds.emplace_back();
+            rounds[round++].push_back(d);
+            e = f;
           }
-          GemmDesc g{};
-          g.M = s.rows; g.N = k; g.K = k;
-          g.C = dst; g.ldc = ldd;
-          if (s.blockid >= 0) {
-            const AdmBlock& ab = p.adm[s.blockid];
-            const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
-            g.A = Rp(other); g.lda = k;
-            g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
-            g.alpha_re = 1.0 / h.omega[s.blockid];
-            ++sidx;
-          } else {
-            g.A = Zp(row, s.parent); g.lda = k;
-            g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
-            g.alpha_re = 1.0;
-          }
-          gd.push_back(g);
-          if (proj) {
-            GemmDesc gq{};
-            gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
-            gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = nw; gq.N = nw; gq.opB = 2;
-            gq.C = base[sg] + roff; gq.ldc = srows[sg];
-            gq.alpha_re = 1.0;
-            gp.push_back(gq);
-          }
-          roff += s.rows;
         }
       }
-      const bool one = segs.size() == 1;
-      const int32_t s0 = (int32_t)ssrc.size();
-      for (size_t sg = 0; sg < segs.size(); ++sg) {
-        GemmDesc g{};
-        g.A = base[sg]; g.lda = srows[sg]; g.opA = 2;
-        g.B = base[sg]; g.ldb = srows[sg];
-        g.M = nw; g.N = nw; g.K = srows[sg];
-        g.upper = 1;
-        g.alpha_re = 1.0;
-        if (one) {
-          g.C = Zp(row, qi); g.ldc = k;
-          g.accumulate = started[it.a] ? 1 : 0;
-        } else {
-          if (tcount >= maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the Gram temporaries"};
-          C64* Tt = Tbuf + (size_t)tcount * k * k;
-          ++tcount;
-          g.C = Tt; g.ldc = nw;
-          ssrc.push_back(Tt);
+      // omega_b = |R_tc S_b R_sc^H| from the column rows when they were formed
+      std::vector<GemmDesc> g1;
+      std::vector<FrobDesc> fd;
+      for (int64_t b = b0; b < b1; ++b) {
+        const AdmBlock& a = p.adm[b];
+        const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
+        const int rt = rR[qt], rs = rR[qs];
+        const size_t i = (size_t)(b - b0);
+        const C64* t1 = colpiece[i];
+        int ld1 = colld[i];
+        if (!t1) {
+          GemmDesc d{};
+          d.A = Rp(qt); d.lda = k; d.M = rt; d.K = k;
+          d.B = S + i * kk; d.ldb = k; d.N = k;
+          d.C = T1 + i * kk; d.ldc = std::max(rt, 1);
+          d.alpha_re = 1.0;
+          g1.push_back(d);
+          t1 = T1 + i * kk;
+          ld1 = std::max(rt, 1);
         }
-        gg.push_back(g);
+        GemmDesc d{};
+        d.A = t1; d.lda = ld1; d.M = rt; d.K = k;
+        d.B = Rp(qs); d.ldb = k; d.N = rs; d.opB = 2;
+        d.C = T2 + i * kk; d.ldc = std::max(rt, 1);
+        d.alpha_re = 1.0;
+        g2.push_back(d);
+        fd.push_back({T2 + i * kk, rt, rs, std::max(rt, 1), 0, b});
       }
-      if (!one) sums.push_back(GramSumTask{Zp(row, qi), nw, k, s0, (int32_t)ssrc.size(), started[it.a] ? 0 : 1, 0});
-      if (it.e1 >= srcs[it.a].size()) chol.push_back(PcholTask{Zp(row, qi), nullptr, nw, k, cnt_d + qi});
-      started[it.a] = 1;
+      gemm(gpc, tmp);
+      gemm(g1, tmp);
+      gemm(g2, tmp);
+      if (h.norm_mode == 0)
+        launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
+      else
+        spectral_weights(b0, b1, S, T1, T2, om_d, tmp);   // S and T1 are free by now
+      launch_scale_rows(upload_tmp(sc, tmp), (int64_t)sc.size(), om_d, h.stream);
+      for (const auto& r : rounds) gemm(r, tmp, true);
+      h.check_launch();
+      free_tmp(tmp);
     }
-    gemm(gd, tmp);
-    gemm(gp, tmp);
-    gemm(gg, tmp, true);
-    if (!sums.empty())
-      launch_gram_sum(upload_tmp(sums, tmp), (int64_t)sums.size(), (const void* const*)upload_tmp(ssrc, tmp),
-                      h.stream);
-    if (!chol.empty()) {
-      if (!pchol_fits_lds(maxnw)) {
-        // packed matrices in the temporaries (free once the sums ran)
-        if ((int64_t)chol.size() > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the Cholesky scratch"};
-        for (size_t i = 0; i < chol.size(); ++i) chol[i].scratch = Tbuf + i * (size_t)k * k;
+    h.omega.resize(nb);
+    if (nb) HIPCHK(hipMemcpy(h.omega.data(), om_d, nb * sizeof(double), hipMemcpyDeviceToHost));
+    h.release(om_d);
+  }
+
+  // Top-down pass of the Gram form (see weights_gram) for the row (row =
+  // true) or column slots: per level, the inherited rows Zhat_{t+c+} E^H of
+  // every slot are formed (stacked per slot) and their Gram matrix added;
+  // leaf slots narrower than k get V G V^H (#t x #t); every slot's Gram
+  // matrix is factored by pivoted Cholesky in place (Zhat = R, rZ rows).
+  void total_gram_topdown(bool row) {
+    const std::vector<uint8_t>& flag = row ? p.slot_row : p.slot_col;
+    std::vector<int32_t>& rZ = row ? rZr : rZc;
+    const size_t kk = (size_t)k * k;
+    // per slot at most: two parents' rows (2 k x k), V G (k x k), Cholesky scratch (k x k)
+    const size_t per = 4 * kk * sizeof(C64);
+    if (per > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for one slot of the Gram weights"};
+    const int64_t chunk = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
+    for (int l = 0; l <= p.depth; ++l) {
+      std::vector<int64_t> qs;
+      for (int64_t q = 0; q < ns; ++q)
+        if (si[q].level == l && flag[q]) qs.push_back(q);
+      for (size_t c0 = 0; c0 < qs.size(); c0 += (size_t)chunk) {
+        const size_t c1 = std::min(qs.size(), c0 + (size_t)chunk);
+        std::vector<void*> tmp;
+        std::vector<GemmDesc> gd, gg, v1, v2;
+        std::vector<PcholTask> chol;
+        C64* W = (C64*)ws;
+        size_t off = 0;
+        int maxnw = 0;
+        for (size_t a = c0; a < c1; ++a) {
+          const int64_t q = qs[a];
+          int64_t rows = 0;
+          std::vector<int64_t> par;
+          for (int64_t pq : parents_of(q, flag))
+            if (rZ[pq] > 0) {
+              par.push_back(pq);
+              rows += rZ[pq];
+            }
+          if (rows > 0) {
+            if ((off + (size_t)rows * k) * sizeof(C64) > ws_bytes)
+              throw Fail{DH2_ERR_OOM, "workspace too small for the inherited rows"};
+            C64* base = W + off;
+            off += (size_t)rows * k;
+            int64_t roff = 0;
+            for (int64_t pq : par) {
+              GemmDesc d{};
+              d.A = Zp(row, pq); d.lda = k; d.M = rZ[pq]; d.K = k;
+              d.B = Ep(pq, child_index(si[q].t)); d.ldb = k; d.N = k; d.opB = 2;
+              d.C = base + roff; d.ldc = (int32_t)rows;
+              d.alpha_re = 1.0;
+              gd.push_back(d);
+              roff += rZ[pq];
+            }
+            GemmDesc d{};
+            d.A = base; d.lda = (int32_t)rows; d.opA = 2;
+            d.B = base; d.ldb = (int32_t)rows;
+            d.M = k; d.N = k; d.K = (int32_t)rows;
+            d.C = Zp(row, q); d.ldc = k;
+            d.accumulate = 1;
+            d.upper = projected(q) ? 0 : 1;
+            d.alpha_re = 1.0;
+            gg.push_back(d);
+          }
+          const int nw = projected(q) ? si[q].nrows : k;
+          if (projected(q)) {
+            // V G into the workspace, then V G V^H over G
+            const int mq = si[q].nrows;
+            C64* VG = W + off;
+            off += (size_t)mq * k;
+            GemmDesc d{};
+            d.A = (C64*)h.V_d + h.V_off[q]; d.lda = mq; d.M = mq; d.K = k;
+            d.B = Zp(row, q); d.ldb = k; d.N = k;
+            d.C = VG; d.ldc = mq;
+            d.alpha_re = 1.0;
+            v1.push_back(d);
+            GemmDesc e{};
+            e.A = VG; e.lda = mq; e.M = mq; e.K = k;
+            e.B = (C64*)h.V_d + h.V_off[q]; e.ldb = mq; e.N = mq; e.opB = 2;
+            e.C = Zp(row, q); e.ldc = k;
+            e.alpha_re = 1.0;
+            v2.push_back(e);
+          }
+          maxnw = std::max(maxnw, nw);
+          chol.push_back(PcholTask{Zp(row, q), nullptr, nw, k, cnt_d + q});
+        }
+        if (!pchol_fits_lds(maxnw)) {
+          for (PcholTask& t : chol) {
+            if ((off + kk) * sizeof(C64) > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for the Cholesky scratch"};
+            t.scratch = W + off;
+            off += kk;
+          }
+        }
+        gemm(gd, tmp);
+        gemm(gg, tmp, true);
+        gemm(v1, tmp, true);
+        gemm(v2, tmp, true);
+        launch_pchol(upload_tmp(chol, tmp), (int64_t)chol.size(), maxnw, h.stream);
+        ++(row ? h.stats.batches_total_weights_row : h.stats.batches_total_weights_col);
+        h.check_launch();
+        free_tmp(tmp);
       }
-      launch_pchol(upload_tmp(chol, tmp), (int64_t)chol.size(), maxnw, h.stream);
+      read_counts(qs, rZ);
     }
-    h.check_launch();
-    free_tmp(tmp);
   }
 
   void total_weights(bool row) {
@@ -848,7 +971,6 @@ struct Builder {
     const size_t wsT = ws_bytes - wsS - wsP;
     const int64_t maxS = std::max<int64_t>(1, (int64_t)(wsS / ((size_t)k * k * sizeof(C64))));
     const int64_t maxT = std::max<int64_t>(1, (int64_t)(wsT / ((size_t)k * k * sizeof(C64))));
-    const bool gram = use_gram();
 
     for (int l = 0; l <= p.depth; ++l) {
       std::vector<int64_t> qs;
@@ -915,158 +1037,154 @@ struct Builder {
             }
         std::vector<void*> tmp;
         gen_couplings(sblocks, Sbuf, tmp);
-        if (gram) {
-          gram_batch(row, qs, srcs, items, started, Sbuf, Pbuf, Tbuf, maxT, tmp);
-        } else {
-          std::vector<GemmDesc> gd, gp;
-          std::vector<FoldPiece> pieces;
-          std::vector<std::pair<size_t, size_t>> item_pieces;  // piece range per item
-          size_t sidx = 0, poff = 0;
-          for (const Item& it : items) {
-            const size_t pb = pieces.size();
-            const int64_t qi = qs[it.a];
-            const bool proj = projected(qi);
-            const int mq = si[qi].nrows;
-            for (size_t ee = it.e0; ee < it.e1; ++ee) {
-              const PieceSrc& s = srcs[it.a][ee];
-              C64* dst = Pbuf + poff;
-              poff += (size_t)s.rows * k;
-              GemmDesc g{};
-              g.M = s.rows; g.N = k; g.K = k;
-              g.C = dst; g.ldc = s.rows;
-              if (s.blockid >= 0) {
-                const AdmBlock& ab = p.adm[s.blockid];
-                const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
-                g.A = Rp(other); g.lda = k;
-                g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
-                g.alpha_re = 1.0 / h.omega[s.blockid];
-                ++sidx;
-              } else {
-                g.A = Zp(row, s.parent); g.lda = k;
-                g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
-                g.alpha_re = 1.0;
-              }
-              gd.push_back(g);
-              if (proj) {
-                // the stacked row block times V_tc^H (rows x #t)
-                C64* dp = Pbuf + poff;
-                poff += (size_t)s.rows * mq;
-                GemmDesc gq{};
-                gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
-                gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = mq; gq.N = mq; gq.opB = 2;
-                gq.C = dp; gq.ldc = s.rows;
-                gq.alpha_re = 1.0;
-                gp.push_back(gq);
-                pieces.push_back({dp, s.rows, s.rows});
-              } else {
-                pieces.push_back({dst, s.rows, s.rows});
-              }
-            }
-            item_pieces.push_back({pb, pieces.size()});
-          }
-          gemm(gd, tmp);
-          gemm(gp, tmp);
-          h.check_launch();
-          // TSQR split: fold segments of each item into temporaries when the
-          // batch has few slots, merge the temporaries in a tree of 8-way folds
-          // (in parallel), then fold the last ones into Zhat
-          const int64_t want = 1024;
-          int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
-          G = std::min<int64_t>(G, std::max<int64_t>(1, (maxT * 4 / 5) / (int64_t)items.size()));
-          constexpr int64_t kMerge = 8;
-          std::vector<FoldTask> t1;
-          std::vector<std::vector<FoldTask>> tiers;       // merge levels
-          std::vector<FoldTask> t2;
-          std::vector<FoldPiece> p2;
-          int64_t tcount = 0;
-          auto new_temp = [&]() {
-            C64* Rt = Tbuf + (size_t)tcount * k * k;
-            ++tcount;
-            if (tcount > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the TSQR temporaries"};
-            return Rt;
-          };
-          for (size_t ii = 0; ii < items.size(); ++ii) {
-            const Item& it = items[ii];
-            const int64_t q = qs[it.a];
-            const int nw = projected(q) ? si[q].nrows : k;     // fold width
-            const size_t pb = item_pieces[ii].first, pe = item_pieces[ii].second;
-            const int64_t np = (int64_t)(pe - pb);
-            const int64_t g = std::min<int64_t>(G, np);
-            const int last = it.e1 >= srcs[it.a].size() ? 1 : 0;
-            FoldTask fin{Zp(row, q), nw, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
-            if (g <= 1) {
-              fin.piece_begin = (int32_t)pb;
-              fin.piece_end = (int32_t)pe;
-              t2.push_back(fin);
+        std::vector<GemmDesc> gd, gp;
+        std::vector<FoldPiece> pieces;
+        std::vector<std::pair<size_t, size_t>> item_pieces;  // piece range per item
+        size_t sidx = 0, poff = 0;
+        for (const Item& it : items) {
+          const size_t pb = pieces.size();
+          const int64_t qi = qs[it.a];
+          const bool proj = projected(qi);
+          const int mq = si[qi].nrows;
+          for (size_t ee = it.e0; ee < it.e1; ++ee) {
+            const PieceSrc& s = srcs[it.a][ee];
+            C64* dst = Pbuf + poff;
+            poff += (size_t)s.rows * k;
+            GemmDesc g{};
+            g.M = s.rows; g.N = k; g.K = k;
+            g.C = dst; g.ldc = s.rows;
+            if (s.blockid >= 0) {
+              const AdmBlock& ab = p.adm[s.blockid];
+              const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
+              g.A = Rp(other); g.lda = k;
+              g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
+              g.alpha_re = 1.0 / h.omega[s.blockid];
+              ++sidx;
             } else {
-              // first level: g segments of the item's pieces, balanced by rows
-              std::vector<int64_t> rows_prefix(np + 1, 0);
-              for (int64_t e = 0; e < np; ++e) rows_prefix[e + 1] = rows_prefix[e] + pieces[pb + e].rows;
-              std::vector<C64*> cur;
-              size_t sb = pb;
-              for (int64_t sgi = 0; sgi < g; ++sgi) {
-                const int64_t target = rows_prefix[np] * (sgi + 1) / g;
-                size_t se = sb;
-                while (se < pe && (rows_prefix[se - pb] < target || se == sb)) ++se;
-                if (sgi == g - 1) se = pe;
-                if (se <= sb) continue;
-                C64* Rt = new_temp();
-                t1.push_back(FoldTask{Rt, nw, nw, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
-                cur.push_back(Rt);
-                sb = se;
-              }
-              // merge levels: groups of kMerge temporaries (all k rows each: in
-              // floating point a compacted factor may keep more nonzero rows
-              // than the rows folded into it)
-              size_t lvl = 0;
-              while ((int64_t)cur.size() > kMerge) {
-                if (tiers.size() <= lvl) tiers.emplace_back();
-                std::vector<C64*> nxt;
-                for (size_t a0 = 0; a0 < cur.size(); a0 += kMerge) {
-                  const size_t a1 = std::min(cur.size(), a0 + (size_t)kMerge);
-                  C64* Rt = new_temp();
-                  const int32_t b0 = (int32_t)(pieces.size() + p2.size());
-                  for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], nw, nw});
-                  tiers[lvl].push_back(FoldTask{Rt, nw, nw, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
-                  nxt.push_back(Rt);
-                }
-                cur.swap(nxt);
-                ++lvl;
-              }
-              fin.piece_begin = (int32_t)(pieces.size() + p2.size());
-              for (C64* Rt : cur) p2.push_back({Rt, nw, nw});
-              fin.piece_end = (int32_t)(pieces.size() + p2.size());
-              t2.push_back(fin);
+              g.A = Zp(row, s.parent); g.lda = k;
+              g.B = Ep(s.parent, child_index(si[s.q].t)); g.ldb = k; g.opB = 2;
+              g.alpha_re = 1.0;
             }
-            started[it.a] = 1;
+            gd.push_back(g);
+            if (proj) {
+              // the stacked row block times V_tc^H (rows x #t)
+              C64* dp = Pbuf + poff;
+              poff += (size_t)s.rows * mq;
+              GemmDesc gq{};
+              gq.A = dst; gq.lda = s.rows; gq.M = s.rows; gq.K = k;
+              gq.B = (C64*)h.V_d + h.V_off[qi]; gq.ldb = mq; gq.N = mq; gq.opB = 2;
+              gq.C = dp; gq.ldc = s.rows;
+              gq.alpha_re = 1.0;
+              gp.push_back(gq);
+              pieces.push_back({dp, s.rows, s.rows});
+            } else {
+              pieces.push_back({dst, s.rows, s.rows});
+            }
           }
-          pieces.insert(pieces.end(), p2.begin(), p2.end());
-          count_folds(t1, pieces);
-          for (const auto& tier : tiers) count_folds(tier, pieces);
-          count_folds(t2, pieces);
-          FoldPiece* pd = upload_tmp(pieces, tmp);
-          // full-width (k) and projected (#t) folds in separate launches: the
-          // chunk height follows the launch's largest width
-          auto folds = [&](const std::vector<FoldTask>& ts) {
-            std::vector<FoldTask> wide, narrow;
-            int nmax = 0;
-            for (const FoldTask& t : ts) {
-              if (t.n == k) wide.push_back(t);
-              else {
-                narrow.push_back(t);
-                nmax = std::max(nmax, t.n);
-              }
-            }
-            if (!wide.empty()) launch_fold<double>(upload_tmp(wide, tmp), (int64_t)wide.size(), pd, k, h.stream);
-            if (!narrow.empty())
-              launch_fold<double>(upload_tmp(narrow, tmp), (int64_t)narrow.size(), pd, nmax, h.stream);
-          };
-          folds(t1);
-          for (const auto& tier : tiers) folds(tier);
-          folds(t2);
-          h.check_launch();
-          free_tmp(tmp);
+          item_pieces.push_back({pb, pieces.size()});
         }
+        gemm(gd, tmp);
+        gemm(gp, tmp);
+        h.check_launch();
+        // TSQR split: fold segments of each item into temporaries when the
+        // batch has few slots, merge the temporaries in a tree of 8-way folds
+        // (in parallel), then fold the last ones into Zhat
+        const int64_t want = 1024;
+        int64_t G = std::max<int64_t>(1, (want + (int64_t)items.size() - 1) / (int64_t)items.size());
+        G = std::min<int64_t>(G, std::max<int64_t>(1, (maxT * 4 / 5) / (int64_t)items.size()));
+        constexpr int64_t kMerge = 8;
+        std::vector<FoldTask> t1;
+        std::vector<std::vector<FoldTask>> tiers;       // merge levels
+        std::vector<FoldTask> t2;
+        std::vector<FoldPiece> p2;
+        int64_t tcount = 0;
+        auto new_temp = [&]() {
+          C64* Rt = Tbuf + (size_t)tcount * k * k;
+          ++tcount;
+          if (tcount > maxT) throw Fail{DH2_ERR_OOM, "workspace too small for the TSQR temporaries"};
+          return Rt;
+        };
+        for (size_t ii = 0; ii < items.size(); ++ii) {
+          const Item& it = items[ii];
+          const int64_t q = qs[it.a];
+          const int nw = projected(q) ? si[q].nrows : k;     // fold width
+          const size_t pb = item_pieces[ii].first, pe = item_pieces[ii].second;
+          const int64_t np = (int64_t)(pe - pb);
+          const int64_t g = std::min<int64_t>(G, np);
+          const int last = it.e1 >= srcs[it.a].size() ? 1 : 0;
+          FoldTask fin{Zp(row, q), nw, k, 0, 0, started[it.a] ? 0 : 1, last, cnt_d + q};
+          if (g <= 1) {
+            fin.piece_begin = (int32_t)pb;
+            fin.piece_end = (int32_t)pe;
+            t2.push_back(fin);
+          } else {
+            // first level: g segments of the item's pieces, balanced by rows
+            std::vector<int64_t> rows_prefix(np + 1, 0);
+            for (int64_t e = 0; e < np; ++e) rows_prefix[e + 1] = rows_prefix[e] + pieces[pb + e].rows;
+            std::vector<C64*> cur;
+            size_t sb = pb;
+            for (int64_t sgi = 0; sgi < g; ++sgi) {
+              const int64_t target = rows_prefix[np] * (sgi + 1) / g;
+              size_t se = sb;
+              while (se < pe && (rows_prefix[se - pb] < target || se == sb)) ++se;
+              if (sgi == g - 1) se = pe;
+              if (se <= sb) continue;
+              C64* Rt = new_temp();
+              t1.push_back(FoldTask{Rt, nw, nw, (int32_t)sb, (int32_t)se, 1, 0, nullptr});
+              cur.push_back(Rt);
+              sb = se;
+            }
+            // merge levels: groups of kMerge temporaries (all k rows each: in
+            // floating point a compacted factor may keep more nonzero rows
+            // than the rows folded into it)
+            size_t lvl = 0;
+            while ((int64_t)cur.size() > kMerge) {
+              if (tiers.size() <= lvl) tiers.emplace_back();
+              std::vector<C64*> nxt;
+              for (size_t a0 = 0; a0 < cur.size(); a0 += kMerge) {
+                const size_t a1 = std::min(cur.size(), a0 + (size_t)kMerge);
+                C64* Rt = new_temp();
+                const int32_t b0 = (int32_t)(pieces.size() + p2.size());
+                for (size_t a = a0; a < a1; ++a) p2.push_back({cur[a], nw, nw});
+                tiers[lvl].push_back(FoldTask{Rt, nw, nw, b0, (int32_t)(pieces.size() + p2.size()), 1, 0, nullptr});
+                nxt.push_back(Rt);
+              }
+              cur.swap(nxt);
+              ++lvl;
+            }
+            fin.piece_begin = (int32_t)(pieces.size() + p2.size());
+            for (C64* Rt : cur) p2.push_back({Rt, nw, nw});
+            fin.piece_end = (int32_t)(pieces.size() + p2.size());
+            t2.push_back(fin);
+          }
+          started[it.a] = 1;
+        }
+        pieces.insert(pieces.end(), p2.begin(), p2.end());
+        count_folds(t1, pieces);
+        for (const auto& tier : tiers) count_folds(tier, pieces);
+        count_folds(t2, pieces);
+        FoldPiece* pd = upload_tmp(pieces, tmp);
+        // full-width (k) and projected (#t) folds in separate launches: the
+        // chunk height follows the launch's largest width
+        auto folds = [&](const std::vector<FoldTask>& ts) {
+          std::vector<FoldTask> wide, narrow;
+          int nmax = 0;
+          for (const FoldTask& t : ts) {
+            if (t.n == k) wide.push_back(t);
+            else {
+              narrow.push_back(t);
+              nmax = std::max(nmax, t.n);
+            }
+          }
+          if (!wide.empty()) launch_fold<double>(upload_tmp(wide, tmp), (int64_t)wide.size(), pd, k, h.stream);
+          if (!narrow.empty())
+            launch_fold<double>(upload_tmp(narrow, tmp), (int64_t)narrow.size(), pd, nmax, h.stream);
+        };
+        folds(t1);
+        for (const auto& tier : tiers) folds(tier);
+        folds(t2);
+        h.check_launch();
+        free_tmp(tmp);
         // advance
         const Item& last = items.back();
         a0 = last.a;
@@ -2005,11 +2123,20 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   h.sync();
   h.stats.ms_basis_weights = now_ms() - t0;
   t0 = now_ms();
-  bd.block_weights();
-  h.stats.ms_block_weights = now_ms() - t0;
-  t0 = now_ms();
-  bd.total_weights(true);
-  bd.total_weights(false);
+  if (bd.use_gram()) {
+    // block weights and the blocks' share of the total weights in one pass
+    bd.weights_gram();
+    h.stats.ms_block_weights = now_ms() - t0;
+    t0 = now_ms();
+    bd.total_gram_topdown(true);
+    bd.total_gram_topdown(false);
+  } else {
+    bd.block_weights();
+    h.stats.ms_block_weights = now_ms() - t0;
+    t0 = now_ms();
+    bd.total_weights(true);
+    bd.total_weights(false);
+  }
   h.sync();
   h.stats.ms_total_weights = now_ms() - t0;
   t0 = now_ms();

@@ -1483,6 +1483,24 @@ void launch_gram_sum(const GramSumTask* t, int64_t ntasks, const void* const* sr
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ntasks, 8), dim3(256), 0, st, t, srcs);
 }
 
+__global__ void __launch_bounds__(256) k_scale_rows(const ScaleTask* __restrict__ tasks,
+                                                    const double* __restrict__ w) {
+  const ScaleTask t = tasks[blockIdx.x];
+  const double wv = w[t.index];
+  const double s = wv > 0.0 ? 1.0 / wv : 0.0;
+  z64* A = (z64*)t.A;
+  const int nn = t.rows * t.cols;
+  for (int e = blockIdx.y * 256 + threadIdx.x; e < nn; e += 256 * gridDim.y) {
+    const int i = e % t.rows, j = e / t.rows;
+    z64& a = A[i + (int64_t)j * t.ld];
+    a = s * a;
+  }
+}
+
+void launch_scale_rows(const ScaleTask* t, int64_t ntasks, const double* w, hipStream_t st) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)ntasks, 4), dim3(256), 0, st, t, w);
+}
+
 // column of packed upper-triangle entry e (entries of column j are j (j + 1) / 2
 // .. j (j + 1) / 2 + j)
 __device__ __forceinline__ int packed_col(int e) {

@@ -80,6 +80,16 @@ struct GramSumTask {
 };
 void launch_gram_sum(const GramSumTask* t, int64_t ntasks, const void* const* srcs, hipStream_t st);
 
+// Rows [0, rows) of a rows x cols block (leading dimension ld) multiplied by
+// 1 / w[index] (by zero when w[index] is not positive): the stacked rows
+// omega_b^-1 R S_b of the total weights, scaled once omega_b is known.
+struct ScaleTask {
+  void* A;
+  int32_t rows, cols, ld, pad;
+  int64_t index;
+};
+void launch_scale_rows(const ScaleTask* t, int64_t ntasks, const double* w, hipStream_t st);
+
 struct PcholTask {
   void* G;            // in: Hermitian positive semi-definite nw x nw, leading dimension ldg
                       // (upper triangle read); out: R in rows 0 .. r-1 (nw columns, the

@@ -43,7 +43,7 @@ def rel(a, b):
 H = lambda a: a.conj().T
 
 
-def check_ranks_and_sigma(h, slots, o, label, gram_eps=None):
+def check_ranks_and_sigma(h, slots, o, label, gram_eps=None, spectral=False):
     """Ranks and singular values of both truncation passes against the oracle:
     singular values to 1e-12 of the largest, ranks equal except at a near-tie
     of the rank rule (a tail sum within 1e-8 of eps^2).
@@ -53,7 +53,11 @@ def check_ranks_and_sigma(h, slots, o, label, gram_eps=None):
     then move by at most gram_eps s_1^2 (Weyl), so each singular value by at
     most min(sqrt(gram_eps) s_1, gram_eps s_1^2 / s_i), and the rank rule's
     tail sums by at most m gram_eps s_1^2: a rank may differ only where a tail
-    is that close to eps^2."""
+    is that close to eps^2.
+
+    spectral: the spectral rule (rank = number of singular values above
+    eps), where a rank may differ only where a singular value is within its
+    bound of eps."""
     worst = 0.0
     for kind, ranks_o, sig_o in (("row", o.rank, o.sig), ("col", o.rankW, o.sigW)):
         ranks = h.inspect("rank_" + kind)[:, 0].real.astype(int)
@@ -76,7 +80,14 @@ def check_ranks_and_sigma(h, slots, o, label, gram_eps=None):
                                        gram_eps * s1 * s1 / np.maximum(s_o[:m], 1e-300)) + 1e-13 * s1 + 1e-300
                     worst = max(worst, float(np.max(d / bound)))
                 assert np.all(d <= bound), (label, kind, key, float(np.max(d)))
-            if ranks[q] != ranks_o[key]:
+            if ranks[q] != ranks_o[key] and spectral:
+                s1 = s_o[0]
+                b = 1e-8 * o.tol if gram_eps is None else (
+                    np.minimum(np.sqrt(gram_eps) * s1, gram_eps * s1 * s1 / np.maximum(s_o, 1e-300)) + 1e-8 * o.tol)
+                near = np.any(np.abs(s_o - o.tol) <= b)
+                assert near, (label, kind, key, ranks[q], ranks_o[key])
+                mism += 1
+            elif ranks[q] != ranks_o[key]:
                 tail = np.cumsum((s_o ** 2)[::-1])[::-1]
                 eps2 = o.tol ** 2
                 if gram_eps is None:
