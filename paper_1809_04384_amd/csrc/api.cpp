@@ -415,6 +415,15 @@ struct Builder {
     for (void* x : tmp) h.release(x);
     tmp.clear();
   }
+  // Release without waiting: the frees are stream-ordered after the batch's
+  // kernels, so the host may prepare the next batch while they run; every
+  // few batches the stream is synchronised to drop the host copies of the
+  // uploaded descriptors.
+  void free_tmp_async(std::vector<void*>& tmp, int64_t batch_index) {
+    for (void* x : tmp) h.release(x);
+    tmp.clear();
+    if (batch_index % 8 == 7) h.sync();
+  }
 
   // ------------------------------------------------------------------
   void setup_slots() {
@@ -612,7 +621,7 @@ struct Builder {
       if (h.norm_mode == 0)
         launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
       else
-        spectral_weights(b0, b1, S, T1, T2, om_d, tmp);
+        spectral_weights(blocks, S, T1, T2, om_d, tmp);
       h.check_launch();
       free_tmp(tmp);
     }
@@ -622,23 +631,23 @@ struct Builder {
   }
 
   // omega_b = |M_b|_2 for M_b = R_tc S_b R_sc^* (rt x rs, column-major in T2 with
-  // leading dimension max(rt, 1)), blocks [b0, b1).  The Gram matrix of the
+  // leading dimension max(rt, 1)), the i-th block of the list at position i.  The Gram matrix of the
   // smaller side is squared kSpecSquarings times, each time after an exact
   // power-of-two normalisation, so Gs ~ G^(2^j); a column of Gs then spans the
   // dominant eigenvector up to (lambda_2 / lambda_1)^(2^j) and its Rayleigh
   // quotient gives |M_b|_2 (k_spec_final).  S and T1 hold the two ping-pong
   // copies of the Gram power.
   static constexpr int kSpecSquarings = 10;
-  void spectral_weights(int64_t b0, int64_t b1, C64* S, C64* T1, C64* T2, double* om_d,
+  void spectral_weights(const std::vector<int64_t>& blocks, C64* S, C64* T1, C64* T2, double* om_d,
                         std::vector<void*>& tmp) {
     const size_t kk = (size_t)k * k;
     std::vector<GemmDesc> gram, sq[2];
     std::vector<FrobDesc> sc[2];
     std::vector<SpecDesc> sd;
-    for (int64_t b = b0; b < b1; ++b) {
+    for (size_t i = 0; i < blocks.size(); ++i) {
+      const int64_t b = blocks[i];
       const AdmBlock& a = p.adm[b];
       const int rt = rR[p.slot_of(a.t, a.c)], rs = rR[p.slot_of(a.s, a.c)];
-      const size_t i = (size_t)(b - b0);
       const int side = rs <= rt ? 0 : 1;
       const int pp = side == 0 ? rs : rt;
       const int ldm = std::max(rt, 1), ldg = std::max(pp, 1);
@@ -708,17 +717,136 @@ struct Builder {
   // sum: G_tc = sum over the blocks b of row (t, c) of omega_b^-2
   // (R_sc S_b^H)^H (R_sc S_b^H), plus E G_{t+c+} E^H for the inherited rows
   // (the same for the column side with R_tc S_b).  The block part needs no
-  // parent, so it is accumulated in the block-weight pass, which generates
-  // S_b and forms R_tc S_b anyway (its omega_b is the norm of R_tc S_b R_sc^H):
-  // per batch of blocks the rows R_tc S_b and R_sc S_b^H are formed into
-  // per-slot segments, scaled by 1 / omega_b once omega_b is known, and the
-  // Gram matrix of each segment is added to its slot's on the FP64 matrix
-  // cores (segments of one slot in separate launches, so no two products add
-  // to one matrix at once).  The top-down pass then adds the inherited rows
-  // Zhat_{t+c+} E^H level by level, projects leaf slots narrower than k
-  // (V G V^H), and factors every Gram matrix by pivoted Cholesky (Zhat = R).
-  // S_b is generated once for block and total weights (instead of three
-  // times), and R_tc S_b once (instead of twice).
+  // parent, so it is accumulated before the top-down pass, in two passes over
+  // the blocks: in column-slot order (the block weights: R_tc S_b, then
+  // omega_b from R_tc S_b R_sc^H, then the column Gram matrices of those same
+  // rows scaled by omega_b^-1) and in row-slot order (R_sc S_b^H / omega_b and
+  // the row Gram matrices).  In each pass the rows of a batch are formed into
+  // per-slot segments of consecutive blocks, and the segments' Gram matrices
+  // are formed on the FP64 matrix cores and added to their slots'.  The
+  // top-down pass then adds the inherited rows Zhat_{t+c+} E^H level by level,
+  // projects leaf slots narrower than k (V G V^H), and factors every Gram
+  // matrix by pivoted Cholesky (Zhat = R).  S_b is generated twice for block
+  // and total weights (instead of three times), and R_tc S_b formed once.
+  static constexpr int64_t kSegRows = 1024;
+
+  // Stacked rows of one slot side for the blocks of a batch (in slot order):
+  // the row products into segments of at most kSegRows rows (a run of one
+  // slot's blocks, longer runs cut), and one Gram product per segment, all in
+  // one launch: a slot with a single segment in the batch adds it to its
+  // Gram matrix directly, the segments of a slot with several go to
+  // temporaries that k_gram_sum then adds.  col: column side (R_tc S_b,
+  // addresses written into colpiece / colld per block), else row side
+  // (R_sc S_b^H / omega_b).  scale_later: the rows get their omega_b^-1 by a
+  // separate pass once omega_b is known (rw, ss).
+  struct GramRows {
+    std::vector<GemmDesc> pieces, gram;
+    std::vector<GramSumTask> sums;
+    std::vector<const void*> srcs;
+    std::vector<RowWeightTask> rw;
+    std::vector<SegScaleTask> ss;
+  };
+  GramRows stack_rows(bool col, const std::vector<int64_t>& blocks, C64* S, C64* P, double* Wt, bool scale_later,
+                      std::vector<C64*>* colpiece, std::vector<int32_t>* colld, std::vector<void*>& tmp) {
+    const size_t kk = (size_t)k * k;
+    GramRows out;
+    std::vector<size_t> temp_of;    // Gram product writing each temporary
+    size_t poff = 0;
+    size_t e = 0;
+    while (e < blocks.size()) {
+      const AdmBlock& a0 = p.adm[blocks[e]];
+      const int64_t q = col ? p.slot_of(a0.s, a0.c) : p.slot_of(a0.t, a0.c);
+      size_t end = e;
+      while (end < blocks.size()) {
+        const AdmBlock& ab = p.adm[blocks[end]];
+        if ((col ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c)) != q) break;
+        ++end;
+      }
+      std::vector<GemmDesc> segs;
+      while (e < end) {
+        // one segment: blocks [e, f) of this slot
+        size_t f = e;
+        int64_t rows = 0;
+        while (f < end) {
+          const AdmBlock& ab = p.adm[blocks[f]];
+          const int r = col ? rR[p.slot_of(ab.t, ab.c)] : rR[p.slot_of(ab.s, ab.c)];
+          const int rr = (col || h.omega[blocks[f]] > 0.0) ? r : 0;
+          if (f > e && rows + rr > kSegRows) break;
+          rows += rr;
+          ++f;
+        }
+        C64* base = P + poff;
+        double* wbase = scale_later ? Wt + poff / k : nullptr;
+        poff += (size_t)rows * k;
+        int64_t roff = 0;
+        for (size_t g = e; g < f; ++g) {
+          const int64_t b = blocks[g];
+          const AdmBlock& ab = p.adm[b];
+          const int64_t other = col ? p.slot_of(ab.t, ab.c) : p.slot_of(ab.s, ab.c);
+          const int r = rR[other];
+          if (r <= 0 || (!col && !(h.omega[b] > 0.0))) continue;
+          GemmDesc d{};
+          d.A = Rp(other); d.lda = k; d.M = r; d.K = k;
+          d.B = S + (size_t)g * kk; d.ldb = k; d.N = k; d.opB = col ? 0 : 2;
+          d.C = base + roff; d.ldc = (int32_t)rows;
+          d.alpha_re = col ? 1.0 : 1.0 / h.omega[b];
+          out.pieces.push_back(d);
+          if (colpiece) {
+            (*colpiece)[g] = base + roff;
+            (*colld)[g] = (int32_t)rows;
+          }
+          if (scale_later) out.rw.push_back(RowWeightTask{(int64_t)(wbase - Wt) + roff, r, 0, b});
+          roff += r;
+        }
+        if (rows > 0) {
+          if (scale_later) out.ss.push_back(SegScaleTask{base, wbase, (int32_t)rows, k});
+          GemmDesc d{};
+          d.A = base; d.lda = (int32_t)rows; d.opA = 2;
+          d.B = base; d.ldb = (int32_t)rows;
+          d.M = k; d.N = k; d.K = (int32_t)rows;
+          d.upper = projected(q) ? 0 : 1;       // leaf projections need the whole matrix
+          d.alpha_re = 1.0;
+          segs.push_back(d);
+        }
+        e = f;
+      }
+      if (segs.size() == 1) {
+        segs[0].C = Zp(!col, q);
+        segs[0].ldc = k;
+        segs[0].accumulate = 1;
+        out.gram.push_back(segs[0]);
+      } else if (segs.size() > 1) {
+        const int32_t s0 = (int32_t)out.srcs.size();
+        for (GemmDesc& d : segs) {
+          // temporary number srcs.size(); its address is set once all are counted
+          temp_of.push_back(out.gram.size());
+          d.ldc = k;
+          out.gram.push_back(d);
+          out.srcs.push_back(nullptr);
+        }
+        // the k x k Gram matrix (a narrow leaf's is projected in the top-down pass)
+        out.sums.push_back(GramSumTask{Zp(!col, q), k, k, s0, (int32_t)out.srcs.size(), 0,
+                                       projected(q) ? 1 : 0});
+      }
+    }
+    if (!temp_of.empty()) {
+      C64* T = h.alloc<C64>(temp_of.size() * kk);
+      tmp.push_back(T);
+      for (size_t i = 0; i < temp_of.size(); ++i) {
+        out.gram[temp_of[i]].C = T + i * kk;
+        out.srcs[i] = T + i * kk;
+      }
+    }
+    return out;
+  }
+  // the Gram products of stack_rows and the sums of the split slots
+  void add_grams(const GramRows& gr, std::vector<void*>& tmp) {
+    gemm(gr.gram, tmp, true);
+    if (!gr.sums.empty())
+      launch_gram_sum(upload_tmp(gr.sums, tmp), (int64_t)gr.sums.size(),
+                      (const void* const*)upload_tmp(gr.srcs, tmp), h.stream);
+  }
+
   void weights_gram() {
     const int64_t nb = (int64_t)p.adm.size();
     const size_t kk = (size_t)k * k;
@@ -729,129 +857,80 @@ struct Builder {
     HIPCHK(hipMemsetAsync(Zc_d, 0, (size_t)ns * kk * sizeof(C64), h.stream));
     rZr.assign(ns, 0);
     rZc.assign(ns, 0);
-    // per block: S_b, scratch of the spectral norm, R_tc S_b R_sc^H, and at
-    // most two k x k of stacked rows
-    const size_t per = 5 * kk * sizeof(C64);
-    if (per > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for one block of the Gram weights"};
-    const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
-    constexpr int64_t kSegRows = 2048;
-    for (int64_t b0 = 0; b0 < nb; b0 += batch) {
-      const int64_t b1 = std::min(nb, b0 + batch);
-      const size_t nbat = (size_t)(b1 - b0);
-      std::vector<int64_t> blocks;
-      for (int64_t b = b0; b < b1; ++b) blocks.push_back(b);
-      C64* S = (C64*)ws;
-      C64* T1 = S + nbat * kk;
-      C64* T2 = T1 + nbat * kk;
-      C64* P = T2 + nbat * kk;
-      std::vector<void*> tmp;
-      ++h.stats.batches_block_weights;
-      gen_couplings(blocks, S, tmp);
-      // stacked rows of the batch: entries (slot, block) of both sides,
-      // grouped by slot, cut into segments of about kSegRows rows
-      struct Ent { int64_t q; int64_t b; int rows; };
-      std::vector<C64*> colpiece(nbat, nullptr);
-      std::vector<int32_t> colld(nbat, 0);
-      std::vector<GemmDesc> gpc, g2, gg;
-      std::vector<ScaleTask> sc;
-      std::vector<std::vector<GemmDesc>> rounds;
-      size_t poff = 0;
-      for (int side = 0; side < 2; ++side) {          // 0: column slots, 1: row slots
-        const bool row = side == 1;
-        std::vector<Ent> ents;
-        for (int64_t b = b0; b < b1; ++b) {
-          const AdmBlock& a = p.adm[b];
-          const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
-          const int64_t q = row ? qt : qs;
-          const int rows = row ? rR[qs] : rR[qt];
-          if ((row ? p.slot_row[q] : p.slot_col[q]) && rows > 0) ents.push_back({q, b, rows});
-        }
-        std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.q < y.q; });
-        size_t e = 0;
-        while (e < ents.size()) {
-          const int64_t q = ents[e].q;
-          int round = 0;
-          while (e < ents.size() && ents[e].q == q) {
-            size_t f = e;
-            int64_t rows = 0;
-            while (f < ents.size() && ents[f].q == q && (f == e || rows + ents[f].rows <= kSegRows)) rows += ents[f++].rows;
-            C64* base = P + poff;
-            poff += (size_t)rows * k;
-            int64_t roff = 0;
-            for (size_t g = e; g < f; ++g) {
-              const AdmBlock& a = p.adm[ents[g].b];
-              const size_t i = (size_t)(ents[g].b - b0);
-              const int64_t other = row ? p.slot_of(a.s, a.c) : p.slot_of(a.t, a.c);
-              GemmDesc d{};
-              d.A = Rp(other); d.lda = k; d.M = ents[g].rows; d.K = k;
-              d.B = S + i * kk; d.ldb = k; d.N = k; d.opB = row ? 2 : 0;
-              d.C = base + roff; d.ldc = (int32_t)rows;
-              d.alpha_re = 1.0;
-              gpc.push_back(d);
-              if (!row) {
-                colpiece[i] = base + roff;
-                colld[i] = (int32_t)rows;
-              }
-              sc.push_back(ScaleTask{base + roff, ents[g].rows, k, (int32_t)rows, 0, ents[g].b});
-              roff += ents[g].rows;
-            }
+    // pass 1, blocks in column-slot order.  Per block: S_b, scratch of the
+    // spectral norm, R_tc S_b R_sc^H, the rows R_tc S_b (at most k x k) and
+    // their k scale factors.
+    {
+      const size_t per = 4 * kk * sizeof(C64) + (size_t)k * sizeof(double);
+      if (per > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for one block of the Gram weights"};
+      const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
+      for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+        const int64_t b1 = std::min(nb, b0 + batch);
+        const size_t nbat = (size_t)(b1 - b0);
+        std::vector<int64_t> blocks(p.col_blk.begin() + b0, p.col_blk.begin() + b1);
+        C64* S = (C64*)ws;
+        C64* T1 = S + nbat * kk;
+        C64* T2 = T1 + nbat * kk;
+        C64* P = T2 + nbat * kk;
+        double* Wt = (double*)(P + nbat * kk);
+        std::vector<void*> tmp;
+        ++h.stats.batches_block_weights;
+        gen_couplings(blocks, S, tmp);
+        std::vector<C64*> colpiece(nbat, nullptr);
+        std::vector<int32_t> colld(nbat, 0);
+        GramRows gr = stack_rows(true, blocks, S, P, Wt, true, &colpiece, &colld, tmp);
+        std::vector<GemmDesc> g2;
+        std::vector<FrobDesc> fd;
+        for (size_t i = 0; i < nbat; ++i) {
+          const AdmBlock& a = p.adm[blocks[i]];
+          const int rt = rR[p.slot_of(a.t, a.c)], rs = rR[p.slot_of(a.s, a.c)];
+          if (colpiece[i]) {
             GemmDesc d{};
-            d.A = base; d.lda = (int32_t)rows; d.opA = 2;
-            d.B = base; d.ldb = (int32_t)rows;
-            d.M = k; d.N = k; d.K = (int32_t)rows;
-            d.C = Zp(row, q); d.ldc = k;
-            d.accumulate = 1;
-            d.upper = projected(q) ? 0 : 1;       // leaf projections need the whole matrix
+            d.A = colpiece[i]; d.lda = colld[i]; d.M = rt; d.K = k;
+            d.B = Rp(p.slot_of(a.s, a.c)); d.ldb = k; d.N = rs; d.opB = 2;
+            d.C = T2 + i * kk; d.ldc = std::max(rt, 1);
             d.alpha_re = 1.0;
-            if ((int)rounds.size() <= round) rounds.emplace_back();
-            rounds[round++].push_back(d);
-            e = f;
+            g2.push_back(d);
           }
+          fd.push_back({T2 + i * kk, colpiece[i] ? rt : 0, rs, std::max(rt, 1), 0, blocks[i]});
         }
+        gemm(gr.pieces, tmp);
+        gemm(g2, tmp);
+        if (h.norm_mode == 0)
+          launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
+        else
+          spectral_weights(blocks, S, T1, T2, om_d, tmp);   // S and T1 are free by now
+        launch_row_weights(upload_tmp(gr.rw, tmp), (int64_t)gr.rw.size(), om_d, Wt, h.stream);
+        launch_scale_segments(upload_tmp(gr.ss, tmp), (int64_t)gr.ss.size(), k, h.stream);
+        add_grams(gr, tmp);
+        h.check_launch();
+        free_tmp_async(tmp, b0 / batch);
       }
-      // omega_b = |R_tc S_b R_sc^H| from the column rows when they were formed
-      std::vector<GemmDesc> g1;
-      std::vector<FrobDesc> fd;
-      for (int64_t b = b0; b < b1; ++b) {
-        const AdmBlock& a = p.adm[b];
-        const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
-        const int rt = rR[qt], rs = rR[qs];
-        const size_t i = (size_t)(b - b0);
-        const C64* t1 = colpiece[i];
-        int ld1 = colld[i];
-        if (!t1) {
-          GemmDesc d{};
-          d.A = Rp(qt); d.lda = k; d.M = rt; d.K = k;
-          d.B = S + i * kk; d.ldb = k; d.N = k;
-          d.C = T1 + i * kk; d.ldc = std::max(rt, 1);
-          d.alpha_re = 1.0;
-          g1.push_back(d);
-          t1 = T1 + i * kk;
-          ld1 = std::max(rt, 1);
-        }
-        GemmDesc d{};
-        d.A = t1; d.lda = ld1; d.M = rt; d.K = k;
-        d.B = Rp(qs); d.ldb = k; d.N = rs; d.opB = 2;
-        d.C = T2 + i * kk; d.ldc = std::max(rt, 1);
-        d.alpha_re = 1.0;
-        g2.push_back(d);
-        fd.push_back({T2 + i * kk, rt, rs, std::max(rt, 1), 0, b});
-      }
-      gemm(gpc, tmp);
-      gemm(g1, tmp);
-      gemm(g2, tmp);
-      if (h.norm_mode == 0)
-        launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
-      else
-        spectral_weights(b0, b1, S, T1, T2, om_d, tmp);   // S and T1 are free by now
-      launch_scale_rows(upload_tmp(sc, tmp), (int64_t)sc.size(), om_d, h.stream);
-      for (const auto& r : rounds) gemm(r, tmp, true);
-      h.check_launch();
-      free_tmp(tmp);
+      h.sync();
+      h.omega.resize(nb);
+      if (nb) HIPCHK(hipMemcpy(h.omega.data(), om_d, nb * sizeof(double), hipMemcpyDeviceToHost));
+      h.release(om_d);
     }
-    h.omega.resize(nb);
-    if (nb) HIPCHK(hipMemcpy(h.omega.data(), om_d, nb * sizeof(double), hipMemcpyDeviceToHost));
-    h.release(om_d);
+    // pass 2, blocks in row-slot order: S_b and the rows R_sc S_b^H / omega_b
+    {
+      const size_t per = 2 * kk * sizeof(C64);
+      const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
+      for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+        const int64_t b1 = std::min(nb, b0 + batch);
+        const size_t nbat = (size_t)(b1 - b0);
+        std::vector<int64_t> blocks(p.row_blk.begin() + b0, p.row_blk.begin() + b1);
+        C64* S = (C64*)ws;
+        C64* P = S + nbat * kk;
+        std::vector<void*> tmp;
+        gen_couplings(blocks, S, tmp);
+        GramRows gr = stack_rows(false, blocks, S, P, nullptr, false, nullptr, nullptr, tmp);
+        gemm(gr.pieces, tmp);
+        add_grams(gr, tmp);
+        h.check_launch();
+        free_tmp_async(tmp, b0 / batch);
+      }
+      h.sync();
+    }
   }
 
   // Top-down pass of the Gram form (see weights_gram) for the row (row =

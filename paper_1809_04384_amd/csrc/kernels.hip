@@ -1471,10 +1471,11 @@ __global__ void __launch_bounds__(256) k_gram_sum(const GramSumTask* __restrict_
   const int nn = t.nw * t.nw;
   for (int e = blockIdx.y * 256 + threadIdx.x; e < nn; e += 256 * gridDim.y) {
     const int i = e % t.nw, j = e / t.nw;
-    if (i > j) continue;
-    z64 v = t.init ? z64{0, 0} : G[i + (int64_t)j * t.ldg];
-    for (int q = t.src_begin; q < t.src_end; ++q) v = v + ((const z64*)srcs[q])[e];
-    G[i + (int64_t)j * t.ldg] = v;
+    if (i > j && !t.full) continue;
+    const int64_t o = i + (int64_t)j * t.ldg;
+    z64 v = t.init ? z64{0, 0} : G[o];
+    for (int q = t.src_begin; q < t.src_end; ++q) v = v + ((const z64*)srcs[q])[o];
+    G[o] = v;
   }
 }
 
@@ -1483,22 +1484,37 @@ void launch_gram_sum(const GramSumTask* t, int64_t ntasks, const void* const* sr
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ntasks, 8), dim3(256), 0, st, t, srcs);
 }
 
-__global__ void __launch_bounds__(256) k_scale_rows(const ScaleTask* __restrict__ tasks,
-                                                    const double* __restrict__ w) {
-  const ScaleTask t = tasks[blockIdx.x];
+__global__ void k_row_weights(const RowWeightTask* __restrict__ tasks, int64_t ntasks,
+                              const double* __restrict__ w, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntasks) return;
+  const RowWeightTask t = tasks[i];
   const double wv = w[t.index];
   const double s = wv > 0.0 ? 1.0 / wv : 0.0;
+  for (int r = 0; r < t.rows; ++r) out[t.off + r] = s;
+}
+
+// a workgroup per (segment, group of 16 columns); each thread keeps the
+// factors of its rows while it walks the columns
+__global__ void __launch_bounds__(256) k_scale_segments(const SegScaleTask* __restrict__ tasks) {
+  const SegScaleTask t = tasks[blockIdx.x];
   z64* A = (z64*)t.A;
-  const int nn = t.rows * t.cols;
-  for (int e = blockIdx.y * 256 + threadIdx.x; e < nn; e += 256 * gridDim.y) {
-    const int i = e % t.rows, j = e / t.rows;
-    z64& a = A[i + (int64_t)j * t.ld];
-    a = s * a;
+  const int j0 = blockIdx.y * 16, j1 = min(t.cols, j0 + 16);
+  for (int r = threadIdx.x; r < t.rows; r += 256) {
+    const double f = t.f[r];
+    z64* a = A + r + (int64_t)j0 * t.rows;
+    for (int j = j0; j < j1; ++j, a += t.rows) *a = f * *a;
   }
 }
 
-void launch_scale_rows(const ScaleTask* t, int64_t ntasks, const double* w, hipStream_t st) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)ntasks, 4), dim3(256), 0, st, t, w);
+void launch_scale_segments(const SegScaleTask* t, int64_t ntasks, int maxcols, hipStream_t st) {
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_scale_segments, dim3((unsigned)ntasks, (unsigned)((maxcols + 15) / 16)), dim3(256), 0, st, t);
+}
+
+void launch_row_weights(const RowWeightTask* t, int64_t ntasks, const double* w, double* out, hipStream_t st) {
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_row_weights, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0, st, t, ntasks, w, out);
 }
 
 // column of packed upper-triangle entry e (entries of column j are j (j + 1) / 2

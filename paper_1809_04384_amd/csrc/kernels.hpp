@@ -73,22 +73,30 @@ struct FoldPiece {
 // upper triangles into the slot's (init: starting from zero), k_pchol turns it
 // into a factor R with R^H R = G.
 struct GramSumTask {
-  void* G;            // nw x nw FP64 complex, leading dimension ldg (upper triangle written)
+  void* G;            // nw x nw FP64 complex, leading dimension ldg (upper triangle written,
+                      // or all of it when full)
   int32_t nw, ldg;
-  int32_t src_begin, src_end;   // source matrices nw x nw, leading dimension nw
-  int32_t init, pad;
+  int32_t src_begin, src_end;   // source matrices nw x nw, leading dimension ldg
+  int32_t init, full;
 };
 void launch_gram_sum(const GramSumTask* t, int64_t ntasks, const void* const* srcs, hipStream_t st);
 
-// Rows [0, rows) of a rows x cols block (leading dimension ld) multiplied by
-// 1 / w[index] (by zero when w[index] is not positive): the stacked rows
-// omega_b^-1 R S_b of the total weights, scaled once omega_b is known.
-struct ScaleTask {
-  void* A;
-  int32_t rows, cols, ld, pad;
+// Scaling of stacked rows: out[off + r] = 1 / w[index] for r < rows (zero when
+// w[index] is not positive), the factor omega_b^-1 of the rows of block b in
+// the total weights; then every row r of a segment (rows x cols, leading
+// dimension rows) is multiplied by its factor f[r].
+struct RowWeightTask {
+  int64_t off;
+  int32_t rows, pad;
   int64_t index;
 };
-void launch_scale_rows(const ScaleTask* t, int64_t ntasks, const double* w, hipStream_t st);
+void launch_row_weights(const RowWeightTask* t, int64_t ntasks, const double* w, double* out, hipStream_t st);
+struct SegScaleTask {
+  void* A;
+  const double* f;
+  int32_t rows, cols;
+};
+void launch_scale_segments(const SegScaleTask* t, int64_t ntasks, int maxcols, hipStream_t st);
 
 struct PcholTask {
   void* G;            // in: Hermitian positive semi-definite nw x nw, leading dimension ldg

@@ -144,3 +144,39 @@ def test_gram_weights_small_workspace():
     finally:
         big.free()
         small.free()
+
+
+@pytest.mark.parametrize("name", ["sphere2k", "dir2k"])
+def test_gram_weights_fp32_form(name):
+    """FP32 form with Gram weights: the stacked rows come from the FP32
+    matrix cores, their Gram matrices from the FP64 ones.  The product agrees
+    with the FP64 oracle to the FP32 form's 1e-4, and ranks differ from the
+    FP64 Gram build in a few slots at most (FP32-sized perturbations of the
+    rows, as in the Householder FP32 form)."""
+    import torch
+    from paper_1809_04384_amd import dh2
+    o = oracle_for(name)
+    w = synth.WORKLOADS[name]
+    V, T = synth.make_mesh(w)
+    h32 = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
+                     max_nrhs=4, weights=dh2.WEIGHTS_GRAM)
+    h64 = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, weights=dh2.WEIGHTS_GRAM)
+    try:
+        assert h32.stats()["weights_gram"] == 1
+        for kind in ("row", "col"):
+            r32 = h32.inspect("rank_" + kind)[:, 0].real.astype(int)
+            r64 = h64.inspect("rank_" + kind)[:, 0].real.astype(int)
+            nd = int(np.count_nonzero(r32 != r64))
+            say("[gpu] %s gram FP32 %s ranks differing from FP64: %d of %d" % (name, kind, nd, r32.size))
+            assert nd <= max(3, r32.size // 50)
+        X = synth.complex_gaussian(o.n, 4, seed=11)
+        Xd = torch.from_numpy(X.astype(np.complex64)).to("cuda:0")
+        Yd = torch.empty_like(Xd)
+        h32.matvec(Xd, Yd)
+        torch.cuda.synchronize()
+        err = rel(Yd.cpu().numpy().astype(np.complex128), o.matvec(X.T).T)
+        say("[gpu] %s gram FP32 matvec rel err vs oracle %.3e" % (name, err))
+        assert err <= 1e-4
+    finally:
+        h32.free()
+        h64.free()
