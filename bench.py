@@ -359,10 +359,7 @@ def fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=None):
                   "FP64 QR and SVD"),
         "build_s": round(tb, 3),
         "build_gemm": {"flops": st["gemm_flops"], "launches": st["gemm_launches"]},
-        "weights": {"timed": args.weights, "gram_taken": bool(st["weights_gram"]),
-                    "householder_build": hh},
-        "mv_shapes": {"autotune": args.autotune, "near": shape_name(st["mv_variant"][0], 0),
-                      "coupling": shape_name(st["mv_variant"][1], 1), "tune_ms": round(st["ms_autotune"], 1)},
+        "weights_gram": bool(st["weights_gram"]),
         "ranks": {"row_mean": round(st["rank_mean_row"], 2), "row_max": st["rank_max_row"]},
         "matvec_ms": round(mv_ms, 3), "value": round(mv_bytes / (mv_ms * 1e-3) / 1e9, 2), "unit": "GB/s",
         "rel_diff_vs_fp64": err,
