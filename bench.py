@@ -88,11 +88,12 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     """HBM bytes per launch of the near-field kernel from the stored rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the
-    streaming-kernel calibration), or None when the summary is missing or the
-    kernel source changed since the counters were taken."""
+    streaming-kernel calibration), or None when the summary is missing, was
+    taken on another pipeline shape than `kernel`, or the kernel source
+    changed since the counters were taken."""
     if not os.path.exists(PMC_FILE):
         return None
     kv = {}
@@ -101,7 +102,7 @@ def measured_traffic():
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     sha = source_sha256()
-    if kv.get("source_sha256") != sha:
+    if kv.get("source_sha256") != sha or kv.get("kernel") != kernel:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -752,7 +753,8 @@ def main():
             "basis": round(st["basis_entries"] * 16 / 1024 / n, 1)},
         "roofline": {"bound": "hbm", "achieved": round(near_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(near_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic() if args.workload == "sphere131k" else None,
+                     "traffic": (measured_traffic(shape_name(st["mv_variant"][0], 0))
+                                 if args.workload == "sphere131k" and nrhs == 16 else None),
                      "kernel": "%s (near-field block rows on matrix cores)" % shape_name(st["mv_variant"][0], 0),
                      "bytes_per_launch": near_alg, "avg_launch_ms": round(near_avg, 4),
                      "measured_peaks": peaks,
