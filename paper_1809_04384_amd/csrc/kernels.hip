@@ -963,7 +963,6 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
   const int mp = (m + 1) & ~1;   // padded to even
   z64* B = use_lds ? (z64*)lds_raw : (z64*)tk.scratch;
   z64* V = B + (int64_t)r * m;
-  __shared__ int s_pos[512];
   __shared__ int s_rot;
   __shared__ double s_sig[512];
   __shared__ int s_ord[512];
@@ -995,14 +994,30 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
     const int i = e % m, j = e / m;
     V[e] = z64{i == j ? 1.0 : 0.0, 0.0};
   }
-  for (int i = tid; i < mp; i += 256) s_pos[i] = i;
+  // squared Frobenius norm of the scaled B (rotations keep it): a column whose
+  // squared norm is at or below 1e-30 of it (1e-15 of the norm, about 5 units
+  // of rounding) carries no singular value that rounding does not already
+  // blur, and rotating it against another column changes that column by at
+  // most as much; such pairs are skipped, so columns of rounding noise do not
+  // keep the sweeps going
+  double fro = 0.0;
+  for (int e = tid; e < r * m; e += 256) fro += abs2(B[e]);
+  for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off);
+  __syncthreads();
+  if (lane == 0) s_wmax[wave] = fro;
+  __syncthreads();
+  const double tiny = fmax(1e-200, 1e-30 * (s_wmax[0] + s_wmax[1] + s_wmax[2] + s_wmax[3]));
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int round = 0; round < mp - 1; ++round) {
+      // round-robin pairing: position 0 stays, the others turn by one place a
+      // round; position i > 0 holds column 1 + (i - 1 - round) mod (mp - 1)
       for (int pr = wave; pr < mp / 2; pr += 4) {
-        int p = s_pos[pr], q = s_pos[mp - 1 - pr];
+        const int i1 = mp - 1 - pr;
+        int p = pr == 0 ? 0 : 1 + ((pr - 1 - round) % (mp - 1) + (mp - 1)) % (mp - 1);
+        int q = 1 + ((i1 - 1 - round) % (mp - 1) + (mp - 1)) % (mp - 1);
         if (p >= m || q >= m) continue;
         if (p > q) {
           const int t = p;
@@ -1026,7 +1041,7 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
         // columns at or below 1e-100 of unit scale are numerically zero; the
         // test |g| <= 1e-15 |b_p| |b_q| uses the norms, whose product cannot
         // underflow here, so the phase g / |g| below stays exact
-        if (fmin(a, b) <= 1e-200) continue;
+        if (fmin(a, b) <= tiny) continue;
         const double ag = sqrt(abs2(g));
         if (ag <= 1e-15 * sqrt(a) * sqrt(b)) continue;
         const double zeta = (b - a) / (2.0 * ag);
@@ -1047,12 +1062,6 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
           V[i + q * m] = z64{s * vp.x + c * evq.x, s * vp.y + c * evq.y};
         }
         if (lane == 0) s_rot = 1;
-      }
-      __syncthreads();
-      if (tid == 0) {  // rotate all positions but the first
-        const int last = s_pos[mp - 1];
-        for (int i = mp - 1; i > 1; --i) s_pos[i] = s_pos[i - 1];
-        s_pos[1] = last;
       }
       __syncthreads();
     }
