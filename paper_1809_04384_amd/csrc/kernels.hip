@@ -955,7 +955,11 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldTask* __restric
 // reaches the subnormal range (where the rotation phase would lose its bits).
 // Workspace: (rows + m) m complex (B and V), in LDS when lds != 0, else in
 // global scratch given by the task.
-__global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ tasks, int use_lds) {
+// eight waves: a round's column pairs (up to m / 2) are spread over more waves
+// of the one workgroup that the LDS footprint leaves on a CU
+constexpr int kJacobiThreads = 512, kJacobiWaves = kJacobiThreads / 64;
+
+__global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const SvdTask* __restrict__ tasks, int use_lds) {
   extern __shared__ double lds_raw[];
   const SvdTask tk = tasks[blockIdx.x];
   const int m = tk.m;
@@ -968,10 +972,10 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
   __shared__ int s_ord[512];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  __shared__ double s_wmax[4];
+  __shared__ double s_wmax[kJacobiWaves];
   const z64* Bin = (const z64*)tk.B;
   double lmax = 0.0;
-  for (int e = tid; e < r * m; e += 256) {
+  for (int e = tid; e < r * m; e += kJacobiThreads) {
     const int i = e % r, j = e / r;
     const z64 v = Bin[i + (int64_t)j * tk.ldb];
     lmax = fmax(lmax, fmax(fabs(v.x), fabs(v.y)));
@@ -982,15 +986,16 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
   // exact power-of-two scaling to unit magnitude; sigma is scaled back at the end
   int sexp = 0;
   {
-    const double mx = fmax(fmax(s_wmax[0], s_wmax[1]), fmax(s_wmax[2], s_wmax[3]));
+    double mx = 0.0;
+    for (int w = 0; w < kJacobiWaves; ++w) mx = fmax(mx, s_wmax[w]);
     if (mx > 0.0) frexp(mx, &sexp);
   }
-  for (int e = tid; e < r * m; e += 256) {
+  for (int e = tid; e < r * m; e += kJacobiThreads) {
     const int i = e % r, j = e / r;
     const z64 v = Bin[i + (int64_t)j * tk.ldb];
     B[e] = z64{ldexp(v.x, -sexp), ldexp(v.y, -sexp)};
   }
-  for (int e = tid; e < m * m; e += 256) {
+  for (int e = tid; e < m * m; e += kJacobiThreads) {
     const int i = e % m, j = e / m;
     V[e] = z64{i == j ? 1.0 : 0.0, 0.0};
   }
@@ -1001,12 +1006,14 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
   // most as much; such pairs are skipped, so columns of rounding noise do not
   // keep the sweeps going
   double fro = 0.0;
-  for (int e = tid; e < r * m; e += 256) fro += abs2(B[e]);
+  for (int e = tid; e < r * m; e += kJacobiThreads) fro += abs2(B[e]);
   for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off);
   __syncthreads();
   if (lane == 0) s_wmax[wave] = fro;
   __syncthreads();
-  const double tiny = fmax(1e-200, 1e-30 * (s_wmax[0] + s_wmax[1] + s_wmax[2] + s_wmax[3]));
+  double fro_all = 0.0;
+  for (int w = 0; w < kJacobiWaves; ++w) fro_all += s_wmax[w];
+  const double tiny = fmax(1e-200, 1e-30 * fro_all);
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) s_rot = 0;
@@ -1014,7 +1021,7 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
     for (int round = 0; round < mp - 1; ++round) {
       // round-robin pairing: position 0 stays, the others turn by one place a
       // round; position i > 0 holds column 1 + (i - 1 - round) mod (mp - 1)
-      for (int pr = wave; pr < mp / 2; pr += 4) {
+      for (int pr = wave; pr < mp / 2; pr += kJacobiWaves) {
         const int i1 = mp - 1 - pr;
         int p = pr == 0 ? 0 : 1 + ((pr - 1 - round) % (mp - 1) + (mp - 1)) % (mp - 1);
         int q = 1 + ((i1 - 1 - round) % (mp - 1) + (mp - 1)) % (mp - 1);
@@ -1069,7 +1076,7 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
     __syncthreads();
   }
   // singular values = column norms of B (scaled), sorted descending (stable)
-  for (int j = wave; j < m; j += 4) {
+  for (int j = wave; j < m; j += kJacobiWaves) {
     double a = 0;
     for (int i = lane; i < r; i += 64) a += abs2(B[i + j * r]);
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
@@ -1107,7 +1114,7 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
   __syncthreads();
   if (tk.U) {
     z64* U = (z64*)tk.U;
-    for (int e = tid; e < m * m; e += 256) {
+    for (int e = tid; e < m * m; e += kJacobiThreads) {
       const int i = e % m, j = e / m;
       U[i + (int64_t)j * tk.ldu] = V[i + s_ord[j] * m];
     }
@@ -1115,7 +1122,7 @@ __global__ void __launch_bounds__(256) k_jacobi(const SvdTask* __restrict__ task
   if (tk.W) {
     z64* W = (z64*)tk.W;
     const double top = s_sig[s_ord[0]];
-    for (int e = tid; e < r * m; e += 256) {
+    for (int e = tid; e < r * m; e += kJacobiThreads) {
       const int i = e % r, j = e / r;
       const double sj = s_sig[s_ord[j]];
       const z64 v = B[i + s_ord[j] * r];
@@ -1659,7 +1666,7 @@ void launch_jacobi(const SvdTask* t, int64_t ntasks, int maxm, int maxr, hipStre
   if (ntasks <= 0) return;
   const size_t need = (size_t)(maxr + maxm) * maxm * 16;
   const int use_lds = need <= g_lds_limit ? 1 : 0;
-  hipLaunchKernelGGL(k_jacobi, dim3((unsigned)ntasks), dim3(256), use_lds ? need : 0, st, t, use_lds);
+  hipLaunchKernelGGL(k_jacobi, dim3((unsigned)ntasks), dim3(kJacobiThreads), use_lds ? need : 0, st, t, use_lds);
 }
 
 template <typename R>
