@@ -15,6 +15,10 @@ computes one by one is compared directly:
 and properties that hold at any size:
   - linearity of the matvec (1e-12);
   - the FP32 form within 1e-4 of the FP64 form over the full n x nrhs result.
+The handles are built as bench.py builds them (Gram form of the total
+weights, pipeline-shape autotuner); at n = 131072 the Householder form of
+the same build is checked against it as well (the same ranks, products
+within 1e-9: rounding of the Gram sums and of the pivoted Cholesky).
 """
 import numpy as np
 import pytest
@@ -85,10 +89,12 @@ def test_full_size(name):
     st, tri = o.st, o.tri
     leaves = [t for t in range(len(st.first)) if st.is_leaf(t)]
     pick = [leaves[i] for i in sorted(np.random.default_rng(2).choice(len(leaves), size=3, replace=False).tolist())]
-    say("[gpu] dh2_build FP64 %s" % name)
-    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 2))
+    say("[gpu] dh2_build FP64 %s (Gram weights, autotuned)" % name)
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 2),
+                   weights=dh2.WEIGHTS_GRAM, autotune=1)
     try:
         s = h.stats()
+        assert s["weights_gram"] == 1
         assert s["n"] == n
         assert s["n_adm"] == len(st.adm)
         assert s["n_near"] == len(st.near)
@@ -122,12 +128,26 @@ def test_full_size(name):
         Yc = _matvec(h, Xc, np.complex128)
         assert rel(Yc[0], Y1[0] + 2.0 * Y1[1]) <= 1e-12
         say("[gpu] %s linearity ok" % name)
+        if name == "sphere131k":
+            say("[gpu] dh2_build FP64 %s (Householder weights)" % name)
+            hh = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 2),
+                            weights=dh2.WEIGHTS_HOUSEHOLDER)
+            try:
+                assert hh.stats()["weights_gram"] == 0
+                for kind in ("row", "col"):
+                    assert np.array_equal(hh.inspect("rank_" + kind), h.inspect("rank_" + kind))
+                Yh = _matvec(hh, X, np.complex128)
+                d = rel(Y, Yh)
+                say("[gpu] %s Gram vs Householder weights: ranks equal, product rel diff %.3e" % (name, d))
+                assert d <= 1e-9
+            finally:
+                hh.free()
     finally:
         h.free()
     if nrhs >= 4:
         say("[gpu] dh2_build FP32 %s" % name)
         h32 = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
-                         max_nrhs=nrhs)
+                         max_nrhs=nrhs, weights=dh2.WEIGHTS_GRAM, autotune=1)
         try:
             Y32 = _matvec(h32, X, np.complex64)
             err32 = rel(Y32, Y)
