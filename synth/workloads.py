@@ -49,6 +49,9 @@ WORKLOADS = {
     # the spectral-norm experiment on the sphere at doubled wave numbers (Section 5):
     # n = 32768, kappa 32, m 4, leaf 32, eps 1e-4, spectral block-relative control
     "sphere32k_spec": Workload("sphere32k_spec", "sphere", 64, 32.0, 4, 32, 1e-4, norm="spectral"),
+    # the largest row of the paper's unit-sphere table (spectral control) at its own
+    # wave number: n = 131072, kappa 64, m 4, leaf 32, tol 1e-4
+    "sphere131k_k64": Workload("sphere131k_k64", "sphere", 128, 64.0, 4, 32, 1e-4, norm="spectral"),
     # directional stress cases: every admissible block carries a direction c != 0
     # (small eta1 makes every level directional, larger eta admits blocks early)
     "dir512": Workload("dir512", "sphere", 8, 6.0, 3, 8, 1e-6, eta=8.0, eta1=1.0),
