@@ -52,7 +52,8 @@ def parse():
                          "spectral control)")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank form")
-    ap.add_argument("--learned-cube", default="cube7k_m6", help="cube workload of the learned-rank family")
+    ap.add_argument("--learned-cube", default="cube28k_m6",
+                    help="cube workload of the learned-rank family (cube7k_m6, cube28k_m6, cube110k_m6)")
     ap.add_argument("--weights", default="gram", choices=["gram", "householder"],
                     help="factorisation of the total weights in the timed build (gram: Gram matrix on the "
                          "FP64 matrix cores and pivoted Cholesky; householder: skinny QR)")

@@ -64,6 +64,7 @@ WORKLOADS = {
     # being far beyond one GPU's memory at leaf 16; these are sizes that fit
     "cube7k_m6": Workload("cube7k_m6", "cube", 24, 7.35, 6, 16, 1e-4),
     "cube28k_m6": Workload("cube28k_m6", "cube", 48, 14.7, 6, 16, 1e-4),
+    "cube110k_m6": Workload("cube110k_m6", "cube", 96, 29.4, 6, 16, 1e-4),
     # cube [-1,1]^3 (flat cluster boxes on the faces), low frequency and directional
     "cube768": Workload("cube768", "cube", 8, 4.0, 3, 16, 1e-6, eta=2.0),
     # order 6 (k = 216) on the same surface: inner clusters with full-width weights
