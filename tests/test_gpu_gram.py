@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle.dh2 import OracleDH2
 from tests.gpu_common import (say, oracle_for, build_handle, rel, check_ranks_and_sigma,
                                check_weight_invariants)
 
@@ -180,3 +181,45 @@ def test_gram_weights_fp32_form(name):
     finally:
         h32.free()
         h64.free()
+
+
+def test_gram_weights_edge_cases():
+    """Gram weights where the structure degenerates: a mesh smaller than one
+    leaf (no admissible block, so both block passes and the top-down pass
+    have nothing to do) and kappa = 0 (one direction per level, real
+    couplings); both against the oracle, built as the benchmark builds
+    (autotuned block rows)."""
+    import torch
+    from paper_1809_04384_amd import dh2
+    V, T = synth.sphere_octahedral(2)                       # n = 32 <= leaf
+    o = OracleDH2(V, T, 3.0, 3, 1.0, 64, 1e-6)
+    assert len(o.st.adm) == 0
+    h = dh2.Handle(V, T, 3.0, 3, 1.0, 64, 1e-6, weights=dh2.WEIGHTS_GRAM, autotune=1)
+    try:
+        assert h.stats()["n_adm"] == 0 and h.stats()["weights_gram"] == 1
+        X = synth.complex_gaussian(len(T), 3, seed=2)
+        Xd = torch.from_numpy(X).to("cuda:0")
+        Yd = torch.empty_like(Xd)
+        h.matvec(Xd, Yd)
+        torch.cuda.synchronize()
+        err = rel(Yd.cpu().numpy(), o.matvec(X.T).T)
+        say("[gpu] gram single leaf rel err %.3e" % err)
+        assert err <= 1e-12
+    finally:
+        h.free()
+    w = synth.WORKLOADS["sphere2k"]
+    V, T = synth.make_mesh(w)
+    o = OracleDH2(V, T, 0.0, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1)
+    h = dh2.Handle(V, T, 0.0, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, weights=dh2.WEIGHTS_GRAM, autotune=1)
+    try:
+        assert h.stats()["n_adm"] == len(o.st.adm)
+        X = synth.complex_gaussian(len(T), 5, seed=1)
+        Xd = torch.from_numpy(X).to("cuda:0")
+        Yd = torch.empty_like(Xd)
+        h.matvec(Xd, Yd)
+        torch.cuda.synchronize()
+        err = rel(Yd.cpu().numpy(), o.matvec(X.T).T)
+        say("[gpu] gram kappa 0 rel err %.3e" % err)
+        assert err <= 1e-9
+    finally:
+        h.free()
