@@ -94,10 +94,12 @@ __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ block
         R accr = 0, acci = 0;
         for (int q = 0; q < 16; ++q) {
           const R dx = (R)(ax - xj[3 * q]), dy = (R)(ay - xj[3 * q + 1]), dz = (R)(az - xj[3 * q + 2]);
-          const R r = sqrt_r(dx * dx + dy * dy + dz * dz);
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          const R ir = rsqrt_r(r2);
+          const R r = r2 * ir;
           R sn, cs;
           sincos_r(kap * r, &sn, &cs);
-          const R f = (R)wj[q] / r;
+          const R f = (R)wj[q] * ir;
           accr += f * cs;
           acci += f * sn;
         }
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(256) k_leaf_basis(const LeafDesc* __restrict__
       lagrange<double>(ct, to_ref(x[2], lo[2], hi[2]), Lz);
       const double L = Lx[jx] * Ly[jy] * Lz[jz];
       double sn, cs;
-      sincos(kappa * (x[0] * c[0] + x[1] * c[1] + x[2] * c[2]), &sn, &cs);
+      sincos_fast(kappa * (x[0] * c[0] + x[1] * c[1] + x[2] * c[2]), &sn, &cs);
       const double f = w7[g * 7 + q] * L;
       sre += f * cs;
       sim += f * sn;
@@ -200,7 +202,7 @@ __global__ void __launch_bounds__(256) k_transfer(const TransDesc* __restrict__ 
     lagrange<double>(ct, to_ref(xi[2], bp[2], bp[5]), Lz);
     const double L = Lx[jx] * Ly[jy] * Lz[jz];
     double sn, cs;
-    sincos(kappa * (xi[0] * dc[0] + xi[1] * dc[1] + xi[2] * dc[2]), &sn, &cs);
+    sincos_fast(kappa * (xi[0] * dc[0] + xi[1] * dc[1] + xi[2] * dc[2]), &sn, &cs);
     out[d.off + e] = cpx<R>{(R)(L * cs), (R)(L * sn)};
   }
 }
@@ -249,10 +251,12 @@ __global__ void __launch_bounds__(256) k_coupling(const CoupDesc* __restrict__ d
       const double dx = xt - qs[0][mu];
       const double dy = yt - qs[1][mu];
       const double dz = zt - qs[2][mu];
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ir = rsqrt_r(r2);
+      const double r = r2 * ir;
       double sn, cs;
-      sincos(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
-      const double f = f0 / r;
+      sincos_fast(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
+      const double f = f0 * ir;
       o[nu + (int64_t)mu * k] = cpx<R>{(R)(f * cs), (R)(f * sn)};
     }
   }
