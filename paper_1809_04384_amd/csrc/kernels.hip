@@ -67,8 +67,9 @@ __global__ void k_tri_data(int64_t n, const double* __restrict__ V, const int32_
 //   i != j: sum_{p,q<16} w_i,p w_j,q g(x_i,p, y_j,q),  g = exp(i kappa r) / (4 pi r)
 //   i == j: Laplace closed form + sum w w rho(r), rho(r) = (exp(i kappa r) - 1) / r,
 //           rho(0) = i kappa (singularity subtraction).
-// One workgroup per block, one thread per entry; the 16-point data is read
-// through the caches.  Output column-major, leading dimension #t.
+// One workgroup per block, one thread per entry; the 16-point data of the row
+// triangles is read through the caches, that of the column triangles from LDS.
+// Output column-major, leading dimension #t.
 template <typename R>
 __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ blocks, double kappa,
                                               const double* __restrict__ x16,
@@ -76,60 +77,76 @@ __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ block
                                               const double* __restrict__ self_lap,
                                               cpx<R>* __restrict__ out) {
   const NearDesc d = blocks[blockIdx.x];
-  const int64_t total = (int64_t)d.nr * d.nc;
   const R kap = (R)kappa;
   const R inv4pi = (R)(0.25 / M_PI);
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int i = (int)(e % d.nr);
-    const int j = (int)(e / d.nr);
-    const int64_t gi = d.row0 + i, gj = d.col0 + j;
-    const double* xi = x16 + gi * 48;
-    const double* xj = x16 + gj * 48;
-    const double* wi = w16 + gi * 16;
-    const double* wj = w16 + gj * 16;
-    R sre = 0, sim = 0;
-    if (gi != gj) {
-      for (int p = 0; p < 16; ++p) {
-        const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
-        R accr = 0, acci = 0;
-        for (int q = 0; q < 16; ++q) {
-          const R dx = (R)(ax - xj[3 * q]), dy = (R)(ay - xj[3 * q + 1]), dz = (R)(az - xj[3 * q + 2]);
-          const R r2 = dx * dx + dy * dy + dz * dz;
-          const R ir = rsqrt_r(r2);
-          const R r = r2 * ir;
-          R sn, cs;
-          sincos_r(kap * r, &sn, &cs);
-          const R f = (R)wj[q] * ir;
-          accr += f * cs;
-          acci += f * sn;
-        }
-        sre += (R)wi[p] * accr;
-        sim += (R)wi[p] * acci;
-      }
-      sre *= inv4pi;
-      sim *= inv4pi;
-    } else {
-      for (int p = 0; p < 16; ++p) {
-        const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
-        for (int q = 0; q < 16; ++q) {
-          const R w = (R)(wi[p] * wj[q]);
-          const R dx = (R)(ax - xj[3 * q]), dy = (R)(ay - xj[3 * q + 1]), dz = (R)(az - xj[3 * q + 2]);
-          const R r = sqrt_r(dx * dx + dy * dy + dz * dz);
-          if (r == (R)0) {
-            sim += w * kap;
-          } else {
-            R sh, ch, sn, cs;
-            sincos_r((R)0.5 * kap * r, &sh, &ch);
+  // the 16 points and weights of up to 64 column triangles, staged in LDS per
+  // chunk of columns: every evaluation reads them from there (the lanes of a
+  // wave mostly share one column, so the reads are broadcasts)
+  __shared__ double cp[64 * 16][4];
+  for (int c0 = 0; c0 < d.nc; c0 += 64) {
+    const int cn = min(64, d.nc - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cn * 16; e += blockDim.x) {
+      const int64_t gj = d.col0 + c0 + e / 16;
+      const int q = e % 16;
+      cp[e][0] = x16[gj * 48 + 3 * q];
+      cp[e][1] = x16[gj * 48 + 3 * q + 1];
+      cp[e][2] = x16[gj * 48 + 3 * q + 2];
+      cp[e][3] = w16[gj * 16 + q];
+    }
+    __syncthreads();
+    const int64_t total = (int64_t)d.nr * cn;
+    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+      const int i = (int)(e % d.nr);
+      const int jj = (int)(e / d.nr);
+      const int64_t gi = d.row0 + i, gj = d.col0 + c0 + jj;
+      const double* xi = x16 + gi * 48;
+      const double* wi = w16 + gi * 16;
+      const double(*pj)[4] = cp + jj * 16;
+      R sre = 0, sim = 0;
+      if (gi != gj) {
+        for (int p = 0; p < 16; ++p) {
+          const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
+          R accr = 0, acci = 0;
+          for (int q = 0; q < 16; ++q) {
+            const R dx = (R)(ax - pj[q][0]), dy = (R)(ay - pj[q][1]), dz = (R)(az - pj[q][2]);
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            const R ir = rsqrt_r(r2);
+            const R r = r2 * ir;
+            R sn, cs;
             sincos_r(kap * r, &sn, &cs);
-            sre += w * ((R)-2 * sh * sh) / r;
-            sim += w * sn / r;
+            const R f = (R)pj[q][3] * ir;
+            accr += f * cs;
+            acci += f * sn;
+          }
+          sre += (R)wi[p] * accr;
+          sim += (R)wi[p] * acci;
+        }
+        sre *= inv4pi;
+        sim *= inv4pi;
+      } else {
+        for (int p = 0; p < 16; ++p) {
+          const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
+          for (int q = 0; q < 16; ++q) {
+            const R w = (R)(wi[p] * pj[q][3]);
+            const R dx = (R)(ax - pj[q][0]), dy = (R)(ay - pj[q][1]), dz = (R)(az - pj[q][2]);
+            const R r = sqrt_r(dx * dx + dy * dy + dz * dz);
+            if (r == (R)0) {
+              sim += w * kap;
+            } else {
+              R sh, ch, sn, cs;
+              sincos_r((R)0.5 * kap * r, &sh, &ch);
+              sincos_r(kap * r, &sn, &cs);
+              sre += w * ((R)-2 * sh * sh) / r;
+              sim += w * sn / r;
+            }
           }
         }
+        sre = (R)self_lap[gi] + sre * inv4pi;
+        sim = sim * inv4pi;
       }
-      sre = (R)self_lap[gi] + sre * inv4pi;
-      sim = sim * inv4pi;
+      out[d.off + i + (int64_t)(c0 + jj) * d.nr] = cpx<R>{sre, sim};
     }
-    out[d.off + e] = cpx<R>{sre, sim};
   }
 }
 
