@@ -1704,8 +1704,9 @@ struct Builder {
         gemm(g2, tmp);
       }
       h.check_launch();
-      free_tmp(tmp);
+      free_tmp_async(tmp, b0 / batch);
     }
+    h.sync();
   }
 
   // ------------------------------------------------------------------
