@@ -59,9 +59,10 @@ def parse():
                          "FP64 matrix cores and pivoted Cholesky; householder: skinny QR)")
     ap.add_argument("--no-householder-build", action="store_true",
                     help="skip the comparison build with Householder total weights")
-    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
-                    help="time the block-row pipeline shapes at build and keep the fastest (1) or use "
-                         "the default shape (0)")
+    ap.add_argument("--autotune", type=int, default=0, choices=[0, 1],
+                    help="timed FP64 steps: time the block-row pipeline shapes at build and keep the "
+                         "fastest (1) or use the default shape (0; at n = 131072 the tuner keeps it, "
+                         "after 0.23 s of timing).  The batching form always autotunes.")
     ap.add_argument("--batch", type=int, default=64, metavar="COUNT",
                     help="problems of the batching form (the recipe's 64; 0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -502,7 +503,8 @@ def learned_form(args, w, V, T, X, Y64, dh2, torch, results, st_exact, build_exa
 def batch_form(args, dh2, torch, count):
     """The batching form: count problems of the seeded recipe (sphere, cube and
     ellipsoid surfaces, n ~ U[2k, 32k], kappa ~ U[4, 24], m 4, leaf 32, tol
-    1e-5), FP32 form, 64 complex64 right-hand sides each.  Builds one by one;
+    1e-5), FP32 form, 64 complex64 right-hand sides each, block-row pipeline
+    shapes autotuned per problem.  Builds one by one;
     all products then run as one graph launch (dh2_batch_run), timed against
     the same products issued one handle after another, and checked bit for
     bit against them."""
@@ -511,15 +513,18 @@ def batch_form(args, dh2, torch, count):
     hs, X, Ye, Yb = [], [], [], []
     bytes_total = 0.0
     tb = 0.0
+    shapes, tune_ms = {}, 0.0
     for i, w in enumerate(ws):
         V, T = synth.make_mesh(w)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
-                       max_nrhs=nrhs, weights=WEIGHTS)
+                       max_nrhs=nrhs, weights=WEIGHTS, autotune=1)
         torch.cuda.synchronize()
         tb += time.perf_counter() - t0
         st = h.stats()
+        shapes[tuple(st["mv_variant"])] = shapes.get(tuple(st["mv_variant"]), 0) + 1
+        tune_ms += st["ms_autotune"]
         bytes_total += st["matvec_bytes"] + nrhs * st["matvec_bytes_per_rhs"]
         hs.append(h)
         X.append(torch.from_numpy(synth.complex_gaussian(len(T), nrhs, seed=100 + i).astype(np.complex64))
@@ -534,7 +539,7 @@ def batch_form(args, dh2, torch, count):
         probs.append((V, T, w.kappa, w.order, w.eta, w.leaf, w.tol))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hm = dh2.build_many(probs, precision=dh2.FP32, max_nrhs=nrhs, threads=8, weights=WEIGHTS)
+    hm = dh2.build_many(probs, precision=dh2.FP32, max_nrhs=nrhs, threads=8, weights=WEIGHTS, autotune=1)
     torch.cuda.synchronize()
     tbm = time.perf_counter() - t0
     same_build = True
@@ -579,6 +584,8 @@ def batch_form(args, dh2, torch, count):
                     % (count, sum(w.n for w in ws), nrhs),
         "build_s_total": round(tb, 2), "build_s_side_by_side": round(tbm, 2),
         "side_by_side_builds_equal": same_build,
+        "autotune": {"shapes_near_coupling_le16_gt16": {"%d,%d,%d,%d" % k: v for k, v in sorted(shapes.items())},
+                     "tune_ms_total": round(tune_ms, 1)},
         "graph_ms": round(t_bat, 3), "one_after_another_ms": round(t_seq, 3),
         "speedup": round(t_seq / t_bat, 3), "value": round(bytes_total / (t_bat * 1e-3) / 1e9, 1), "unit": "GB/s",
         "bytes_per_batch": bytes_total, "bitwise_equal_to_single_products": same,

@@ -2029,7 +2029,7 @@ void run_matvec_t(dh2_problem* h, const dh2_problem::MvView& v, const void* X, v
 
 // Autotuner of the block-row products.  Each shape is timed inside whole
 // products (the near-field and coupling launches see the caches and clocks
-// they see in use), with the shapes interleaved over four sweeps, the first
+// they see in use), with the shapes interleaved over three sweeps, the first
 // discarded; per phase and right-hand-side class the shape with the shortest
 // best time is kept (the default unless another beats it by 3 %).
 // Right-hand sides are zero (the timing does not depend on the values).
@@ -2052,7 +2052,7 @@ void tune_block_rows_t(dh2_problem& h) {
     }
     const int nrhs = cls == 0 ? std::min(h.max_nrhs, 16) : h.max_nrhs;
     std::vector<float> best(2 * nv, 1e30f);
-    for (int sweep = 0; sweep < 4; ++sweep)
+    for (int sweep = 0; sweep < 3; ++sweep)
       for (int var = 0; var < nv; ++var) {
         h.mv_var[2 * cls] = h.mv_var[2 * cls + 1] = var;
         run_matvec_t<R>(&h, h.mv_own, Xb, Yb, nrhs, ev, st);
