@@ -15,8 +15,8 @@ computes one by one is compared directly:
 and properties that hold at any size:
   - linearity of the matvec (1e-12);
   - the FP32 form within 1e-4 of the FP64 form over the full n x nrhs result.
-The handles are built as bench.py builds them (Gram form of the total
-weights, pipeline-shape autotuner); at n = 131072 the Householder form of
+The handles are built as bench.py builds its timed steps (Gram form of the
+total weights, default pipeline shape); at n = 131072 the Householder form of
 the same build is checked against it as well (the same ranks, products
 within 1e-9: rounding of the Gram sums and of the pivoted Cholesky).
 """
@@ -89,9 +89,9 @@ def test_full_size(name):
     st, tri = o.st, o.tri
     leaves = [t for t in range(len(st.first)) if st.is_leaf(t)]
     pick = [leaves[i] for i in sorted(np.random.default_rng(2).choice(len(leaves), size=3, replace=False).tolist())]
-    say("[gpu] dh2_build FP64 %s (Gram weights, autotuned)" % name)
+    say("[gpu] dh2_build FP64 %s (Gram weights)" % name)
     h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 2),
-                   weights=dh2.WEIGHTS_GRAM, autotune=1)
+                   weights=dh2.WEIGHTS_GRAM)
     try:
         s = h.stats()
         assert s["weights_gram"] == 1
@@ -147,7 +147,7 @@ def test_full_size(name):
     if nrhs >= 4:
         say("[gpu] dh2_build FP32 %s" % name)
         h32 = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, precision=dh2.FP32,
-                         max_nrhs=nrhs, weights=dh2.WEIGHTS_GRAM, autotune=1)
+                         max_nrhs=nrhs, weights=dh2.WEIGHTS_GRAM)
         try:
             Y32 = _matvec(h32, X, np.complex64)
             err32 = rel(Y32, Y)
