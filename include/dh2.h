@@ -100,7 +100,13 @@ typedef enum { DH2_RANKS_EXACT = 0, DH2_RANKS_LEARNED = 1 } dh2_rank_mode;
  *   pivoting, Zhat = R with R^H R = the Gram matrix.  Zhat^H Zhat, which is all
  *   the truncation uses, is the same up to rounding; rounding now acts on the
  *   squares of the singular values, so this form is taken only for tol >= 1e-7
- *   (smaller tolerances use HOUSEHOLDER; dh2_stats.weights_gram says which ran). */
+ *   (smaller tolerances use HOUSEHOLDER; dh2_stats.weights_gram says which ran).
+ *   The blocks' share of the Gram matrices is formed together with the block
+ *   weights, in two passes over the admissible blocks (column-slot order, then
+ *   row-slot order; dh2_stats.ms_block_weights covers both), the inherited rows
+ *   and the factorisation in a top-down pass (ms_total_weights).  The workspace
+ *   must hold one block: 4 k^2 complex doubles and k doubles (DH2_ERR_OOM
+ *   otherwise). */
 typedef enum { DH2_WEIGHTS_HOUSEHOLDER = 0, DH2_WEIGHTS_GRAM = 1 } dh2_weights_mode;
 
 /* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then
@@ -121,8 +127,10 @@ typedef struct {
   int32_t autotune;   /* pipeline shape of the matrix-core block-row products (near field
                          and coupling phase): 0 = the default shape; 1 = time every shape
                          on this handle's own data at the end of the build and keep the
-                         fastest per phase and right-hand-side class (nrhs <= 16, > 16);
-                         2 + v = use shape v everywhere (0 <= v < 4, a test hook) */
+                         fastest per phase and right-hand-side class (nrhs <= 16, > 16),
+                         another shape replacing the default only when more than 3 %
+                         faster; 2 + v = use shape v everywhere (0 <= v < 4, a test hook).
+                         Every shape gives the same results bit for bit. */
   int32_t weights;    /* dh2_weights_mode, default DH2_WEIGHTS_HOUSEHOLDER */
 } dh2_options;
 
