@@ -77,8 +77,8 @@ def test_matvec_rhs_counts(name):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_pipeline_shapes_and_autotune(precision):
     """Every pipeline shape of the block-row products (forced through the
-    autotune hook) gives the product of the default shape, for one ragged and
-    one two-tile right-hand-side count; an autotuned handle records the shapes
+    autotune hook) gives the product of the default shape bit for bit, for one
+    ragged and one two-tile right-hand-side count; an autotuned handle records the shapes
     it picked, each a valid one, and its product matches the oracle."""
     import torch
     from paper_1809_04384_amd import dh2
@@ -88,10 +88,8 @@ def test_pipeline_shapes_and_autotune(precision):
     V, T = synth.make_mesh(w)
     prec = dh2.FP64 if precision == "fp64" else dh2.FP32
     ctype = torch.complex128 if precision == "fp64" else torch.complex64
-    # against the oracle: the bounds of the FP64 and FP32 forms; between
-    # shapes: rounding of the product alone
+    # against the oracle: the bounds of the FP64 and FP32 forms
     tol = 1e-10 if precision == "fp64" else 1e-4
-    tol_shape = 1e-12 if precision == "fp64" else 1e-5
     first = {}
     ref = {}
     for nrhs in (1, 20):
@@ -121,7 +119,9 @@ def test_pipeline_shapes_and_autotune(precision):
                     err = rel(Y[r], Yo[r])
                     assert err <= tol, (mode, nrhs, r, err)
                 if nrhs in first:
-                    assert rel(Y, first[nrhs]) <= tol_shape, (mode, nrhs, rel(Y, first[nrhs]))
+                    # the shapes change the pipelining, not the order of the
+                    # accumulation: the same bits (builds are deterministic)
+                    assert np.array_equal(Y, first[nrhs]), (mode, nrhs, rel(Y, first[nrhs]))
                 else:
                     first[nrhs] = Y
         finally:
