@@ -274,7 +274,9 @@ typedef struct {
       ms_total_weights, ms_truncation, ms_projection, ms_total;
   double gemm_flops;        /* real flops of the build's complex matrix products, 8 M N K each
                                (4 N (N + 1) K for a Hermitian N x N product of which only the
-                               upper triangle is formed) */
+                               upper triangle is formed; with a basis weight R_tc as a factor,
+                               whose row i is zero left of column i, only the products outside
+                               those zeros) */
   int64_t gemm_launches;    /* kernel launches of those products */
   double qr_flops;          /* real flops of the Householder QR steps of the recompression:
                                folding M rows into an n x n triangular factor counts 8 M n^2,
@@ -300,6 +302,10 @@ typedef struct {
   int32_t mv_variant[4];
   double ms_autotune;
   int32_t weights_gram;     /* 1 when the total weights were factored in the Gram form */
+  /* The part of coupling_regeneration evaluated inside the products that use
+   * S_b (FP64 handles: the rows R S_b and R S_b^H of the Gram form with the
+   * Frobenius norm, and the projection's C_tc S_b), so never stored. */
+  double coupling_in_products;
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);

@@ -315,7 +315,8 @@ struct Builder {
   ChebTab ct;
   std::vector<SlotInfo> si;
   std::vector<int32_t> rR;                 // rows of R per slot
-  C64* R_d = nullptr;                      // per slot k x k
+  C64* R_d = nullptr;                      // per slot k x k: the compacted R of an unpivoted
+                                           // Householder QR, zero left of its diagonal (GemmDesc.tri)
   C64* Zr_d = nullptr;                     // per slot k x k (row pass)
   C64* Zc_d = nullptr;                     // per slot k x k (column pass)
   std::vector<int32_t> rZr, rZc;
@@ -359,6 +360,20 @@ struct Builder {
   // workgroup is started for a tile outside its product.
   // Batched complex products, grouped by tile counts.  force64: on the FP64
   // kernel whatever the handle's precision.
+  // Flops of one product: 8 per complex multiply-add; a Hermitian product
+  // (upper) counts its upper triangle, a trapezoidal operand (tri) the
+  // products outside its zeros: sum over the rows i (columns n) of K - i
+  // (K - n).  At most one tri bit is set per descriptor.
+  static double gemm_desc_flops(const GemmDesc& g) {
+    if (g.upper) return 4.0 * g.N * (g.N + 1.0) * g.K;
+    auto trap = [](double rows, double K) {     // sum over i < min(rows, K) of K - i
+      const double r = std::min(rows, K);
+      return r * K - r * (r - 1.0) / 2.0;
+    };
+    if (g.tri & 1) return 8.0 * g.N * trap(g.M, g.K);
+    if (g.tri & 2) return 8.0 * g.M * trap(g.N, g.K);
+    return 8.0 * g.M * g.N * g.K;
+  }
   void gemm(const std::vector<GemmDesc>& gd, std::vector<void*>& tmp, bool force64 = false) {
     if (gd.empty()) return;
     auto key = [](const GemmDesc& g) {
@@ -370,8 +385,7 @@ struct Builder {
       if (g.M > 0 && g.N > 0) v.push_back(g);
     if (v.empty()) return;
     std::stable_sort(v.begin(), v.end(), [&](const GemmDesc& a, const GemmDesc& b) { return key(a) < key(b); });
-    for (const GemmDesc& g : v)
-      h.stats.gemm_flops += g.upper ? 4.0 * g.N * (g.N + 1.0) * g.K : 8.0 * g.M * g.N * g.K;
+    for (const GemmDesc& g : v) h.stats.gemm_flops += gemm_desc_flops(g);
     const GemmDesc* d = upload_tmp(v, tmp);
     size_t i0 = 0;
     while (i0 < v.size()) {
@@ -410,6 +424,7 @@ struct Builder {
     }
   }
   int64_t n_coupling_gen = 0;   // S_b generated during the build
+  int64_t n_coupling_fused = 0; // of which inside products (k_gemm_coupling, never stored)
   void free_tmp(std::vector<void*>& tmp) {
     h.sync();
     for (void* x : tmp) h.release(x);
@@ -537,7 +552,7 @@ struct Builder {
               used += (size_t)std::max(r, 1) * k * sizeof(C64);
               if (r > 0) {
                 GemmDesc g{};
-                g.A = Rp(cq); g.lda = k; g.M = r; g.K = k;
+                g.A = Rp(cq); g.lda = k; g.M = r; g.K = k; g.tri = 1;
                 g.B = Ep(q, i); g.ldb = k; g.N = k;
                 g.C = dst; g.ldc = r;
                 g.alpha_re = 1.0;
@@ -577,6 +592,44 @@ struct Builder {
                             dst, h.stream);
     h.check_launch();
   }
+  // Products with S_b evaluated inside them (k_gemm_coupling): FP64 handles;
+  // the FP32 and BF16x3 forms keep their own product kernels on stored S_b.
+  bool fuse_couplings() const { return h.precision == DH2_FP64; }
+  CoupGemmDesc coup_desc(int64_t b, const C64* A, int lda, int M, int conj, int tri, C64* C, int ldc,
+                         double alpha) {
+    const AdmBlock& ab = p.adm[b];
+    CoupGemmDesc c{};
+    c.A = A; c.lda = lda; c.M = M;
+    c.t = (int32_t)ab.t; c.s = (int32_t)ab.s; c.dir = gdir(ab.t, ab.c);
+    c.conj = conj; c.tri = tri;
+    c.C = C; c.ldc = ldc;
+    c.alpha = alpha;
+    return c;
+  }
+  // Grouped by row count: products with M <= 32 and <= 64 get the kernel
+  // with 32- and 64-row chunks, the rest 128-row chunks.
+  void gemm_coupling(const std::vector<CoupGemmDesc>& cd, std::vector<void*>& tmp) {
+    if (cd.empty()) return;
+    std::vector<CoupGemmDesc> grp[3];
+    for (const CoupGemmDesc& c : cd) {
+      if (c.M <= 0) continue;
+      GemmDesc g{};
+      g.M = c.M; g.N = k; g.K = k; g.tri = c.tri;
+      h.stats.gemm_flops += gemm_desc_flops(g);
+      const int gi = c.M <= 32 ? 0 : (c.M <= 64 ? 1 : 2);
+      const int64_t chunks = gi < 2 ? 1 : (c.M + 127) / 128;   // S_b is evaluated once per chunk
+      n_coupling_gen += chunks;
+      n_coupling_fused += chunks;
+      grp[gi].push_back(c);
+    }
+    for (int gi = 0; gi < 3; ++gi) {
+      if (grp[gi].empty()) continue;
+      h.stats.gemm_launches += (int64_t)((grp[gi].size() + 65534) / 65535);
+      launch_gemm_coupling(upload_tmp(grp[gi], tmp), (int64_t)grp[gi].size(), 1 << gi, ct, p.kappa, h.box_d,
+                           h.dirs_d, h.stream);
+    }
+    h.check_launch();
+  }
 
   // ------------------------------------------------------------------
   // block weights omega_b = |R_tc S_b R_sc^*|_F, or its spectral norm
@@ -603,14 +656,14 @@ struct Builder {
         const int rt = rR[qt], rs = rR[qs];
         const size_t i = (size_t)(b - b0);
         GemmDesc g{};
-        g.A = Rp(qt); g.lda = k; g.M = rt; g.K = k;
+        g.A = Rp(qt); g.lda = k; g.M = rt; g.K = k; g.tri = 1;
         g.B = S + i * k * k; g.ldb = k; g.N = k;
         g.C = T1 + i * k * k; g.ldc = std::max(rt, 1);
         g.alpha_re = 1.0;
         g1.push_back(g);
         GemmDesc g2d{};
         g2d.A = T1 + i * k * k; g2d.lda = std::max(rt, 1); g2d.M = rt; g2d.K = k;
-        g2d.B = Rp(qs); g2d.ldb = k; g2d.N = rs; g2d.opB = 2;
+        g2d.B = Rp(qs); g2d.ldb = k; g2d.N = rs; g2d.opB = 2; g2d.tri = 2;
         g2d.C = T2 + i * k * k; g2d.ldc = std::max(rt, 1);
         g2d.alpha_re = 1.0;
         g2.push_back(g2d);
@@ -738,9 +791,11 @@ struct Builder {
   // temporaries that k_gram_sum then adds.  col: column side (R_tc S_b,
   // addresses written into colpiece / colld per block), else row side
   // (R_sc S_b^H / omega_b).  scale_later: the rows get their omega_b^-1 by a
-  // separate pass once omega_b is known (rw, ss).
+  // separate pass once omega_b is known (rw, ss).  S: the batch's stored
+  // couplings, or nullptr to form them inside the products (cpieces).
   struct GramRows {
     std::vector<GemmDesc> pieces, gram;
+    std::vector<CoupGemmDesc> cpieces;     // the pieces with S_b formed inside (S == nullptr)
     std::vector<GramSumTask> sums;
     std::vector<const void*> srcs;
     std::vector<RowWeightTask> rw;
@@ -785,12 +840,17 @@ struct Builder {
           const int64_t other = col ? p.slot_of(ab.t, ab.c) : p.slot_of(ab.s, ab.c);
           const int r = rR[other];
           if (r <= 0 || (!col && !(h.omega[b] > 0.0))) continue;
-          GemmDesc d{};
-          d.A = Rp(other); d.lda = k; d.M = r; d.K = k;
-          d.B = S + (size_t)g * kk; d.ldb = k; d.N = k; d.opB = col ? 0 : 2;
-          d.C = base + roff; d.ldc = (int32_t)rows;
-          d.alpha_re = col ? 1.0 : 1.0 / h.omega[b];
-          out.pieces.push_back(d);
+          const double alpha = col ? 1.0 : 1.0 / h.omega[b];
+          if (S) {
+            GemmDesc d{};
+            d.A = Rp(other); d.lda = k; d.M = r; d.K = k; d.tri = 1;
+            d.B = S + (size_t)g * kk; d.ldb = k; d.N = k; d.opB = col ? 0 : 2;
+            d.C = base + roff; d.ldc = (int32_t)rows;
+            d.alpha_re = alpha;
+            out.pieces.push_back(d);
+          } else {
+            out.cpieces.push_back(coup_desc(b, Rp(other), k, r, col ? 0 : 1, 1, base + roff, (int32_t)rows, alpha));
+          }
           if (colpiece) {
             (*colpiece)[g] = base + roff;
             (*colld)[g] = (int32_t)rows;
@@ -860,22 +920,25 @@ struct Builder {
     // pass 1, blocks in column-slot order.  Per block: S_b, scratch of the
     // spectral norm, R_tc S_b R_sc^H, the rows R_tc S_b (at most k x k) and
     // their k scale factors.
+    // The spectral norm needs S_b itself (and S, T1 as scratch); the Frobenius
+    // norm needs only the rows R_tc S_b, formed with S_b inside the product.
     {
-      const size_t per = 4 * kk * sizeof(C64) + (size_t)k * sizeof(double);
+      const bool fused = fuse_couplings() && h.norm_mode == 0;
+      const size_t per = (fused ? 2 : 4) * kk * sizeof(C64) + (size_t)k * sizeof(double);
       if (per > ws_bytes) throw Fail{DH2_ERR_OOM, "workspace too small for one block of the Gram weights"};
       const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
       for (int64_t b0 = 0; b0 < nb; b0 += batch) {
         const int64_t b1 = std::min(nb, b0 + batch);
         const size_t nbat = (size_t)(b1 - b0);
         std::vector<int64_t> blocks(p.col_blk.begin() + b0, p.col_blk.begin() + b1);
-        C64* S = (C64*)ws;
-        C64* T1 = S + nbat * kk;
-        C64* T2 = T1 + nbat * kk;
+        C64* S = fused ? nullptr : (C64*)ws;
+        C64* T1 = fused ? nullptr : S + nbat * kk;
+        C64* T2 = fused ? (C64*)ws : T1 + nbat * kk;
         C64* P = T2 + nbat * kk;
         double* Wt = (double*)(P + nbat * kk);
         std::vector<void*> tmp;
         ++h.stats.batches_block_weights;
-        gen_couplings(blocks, S, tmp);
+        if (!fused) gen_couplings(blocks, S, tmp);
         std::vector<C64*> colpiece(nbat, nullptr);
         std::vector<int32_t> colld(nbat, 0);
         GramRows gr = stack_rows(true, blocks, S, P, Wt, true, &colpiece, &colld, tmp);
@@ -887,7 +950,7 @@ struct Builder {
           if (colpiece[i]) {
             GemmDesc d{};
             d.A = colpiece[i]; d.lda = colld[i]; d.M = rt; d.K = k;
-            d.B = Rp(p.slot_of(a.s, a.c)); d.ldb = k; d.N = rs; d.opB = 2;
+            d.B = Rp(p.slot_of(a.s, a.c)); d.ldb = k; d.N = rs; d.opB = 2; d.tri = 2;
             d.C = T2 + i * kk; d.ldc = std::max(rt, 1);
             d.alpha_re = 1.0;
             g2.push_back(d);
@@ -895,6 +958,7 @@ struct Builder {
           fd.push_back({T2 + i * kk, colpiece[i] ? rt : 0, rs, std::max(rt, 1), 0, blocks[i]});
         }
         gemm(gr.pieces, tmp);
+        gemm_coupling(gr.cpieces, tmp);
         gemm(g2, tmp);
         if (h.norm_mode == 0)
           launch_frob<double>(upload_tmp(fd, tmp), (int64_t)fd.size(), om_d, h.stream);
@@ -913,18 +977,20 @@ struct Builder {
     }
     // pass 2, blocks in row-slot order: S_b and the rows R_sc S_b^H / omega_b
     {
-      const size_t per = 2 * kk * sizeof(C64);
+      const bool fused = fuse_couplings();
+      const size_t per = (fused ? 1 : 2) * kk * sizeof(C64);
       const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
       for (int64_t b0 = 0; b0 < nb; b0 += batch) {
         const int64_t b1 = std::min(nb, b0 + batch);
         const size_t nbat = (size_t)(b1 - b0);
         std::vector<int64_t> blocks(p.row_blk.begin() + b0, p.row_blk.begin() + b1);
-        C64* S = (C64*)ws;
-        C64* P = S + nbat * kk;
+        C64* S = fused ? nullptr : (C64*)ws;
+        C64* P = fused ? (C64*)ws : S + nbat * kk;
         std::vector<void*> tmp;
-        gen_couplings(blocks, S, tmp);
+        if (!fused) gen_couplings(blocks, S, tmp);
         GramRows gr = stack_rows(false, blocks, S, P, nullptr, false, nullptr, nullptr, tmp);
         gemm(gr.pieces, tmp);
+        gemm_coupling(gr.cpieces, tmp);
         add_grams(gr, tmp);
         h.check_launch();
         free_tmp_async(tmp, b0 / batch);
@@ -1135,7 +1201,7 @@ struct Builder {
             if (s.blockid >= 0) {
               const AdmBlock& ab = p.adm[s.blockid];
               const int64_t other = row ? p.slot_of(ab.s, ab.c) : p.slot_of(ab.t, ab.c);
-              g.A = Rp(other); g.lda = k;
+              g.A = Rp(other); g.lda = k; g.tri = 1;
               g.B = Sbuf + sidx * k * k; g.ldb = k; g.opB = row ? 2 : 0;
               g.alpha_re = 1.0 / h.omega[s.blockid];
               ++sidx;
@@ -1668,30 +1734,37 @@ struct Builder {
     }
     h.St_d = h.alloc<C64>((size_t)std::max<int64_t>(tot, 1));
     h.St_total = tot;
-    const size_t per = (size_t)2 * k * k * sizeof(C64);
+    // C_tc S_b with S_b formed inside the product (FP64), else stored first
+    const bool fused = fuse_couplings();
+    const size_t per = (size_t)(fused ? 1 : 2) * k * k * sizeof(C64);
     const int64_t batch = std::max<int64_t>(1, (int64_t)(ws_bytes / per));
     for (int64_t b0 = 0; b0 < nb; b0 += batch) {
       const int64_t b1 = std::min(nb, b0 + batch);
       std::vector<int64_t> blocks;
       for (int64_t b = b0; b < b1; ++b) blocks.push_back(b);
-      C64* S = (C64*)ws;
-      C64* T = S + (size_t)(b1 - b0) * k * k;
+      C64* S = fused ? nullptr : (C64*)ws;
+      C64* T = fused ? (C64*)ws : S + (size_t)(b1 - b0) * k * k;
       std::vector<void*> tmp;
       ++h.stats.batches_projection;
-      gen_couplings(blocks, S, tmp);
+      if (!fused) gen_couplings(blocks, S, tmp);
       std::vector<GemmDesc> g1, g2;
+      std::vector<CoupGemmDesc> c1;
       for (int64_t b = b0; b < b1; ++b) {
         const AdmBlock& a = p.adm[b];
         const int64_t qt = p.slot_of(a.t, a.c), qs = p.slot_of(a.s, a.c);
         const int kt = h.rank_row[qt], ks = h.rank_col[qs];
         if (kt == 0 || ks == 0) continue;
         const size_t i = (size_t)(b - b0);
-        GemmDesc g{};
-        g.A = Cr_ptr[qt]; g.lda = kt; g.M = kt; g.K = k;
-        g.B = S + i * k * k; g.ldb = k; g.N = k;
-        g.C = T + i * k * k; g.ldc = kt;
-        g.alpha_re = 1.0;
-        g1.push_back(g);
+        if (fused) {
+          c1.push_back(coup_desc(b, Cr_ptr[qt], kt, kt, 0, 0, T + i * k * k, kt, 1.0));
+        } else {
+          GemmDesc g{};
+          g.A = Cr_ptr[qt]; g.lda = kt; g.M = kt; g.K = k;
+          g.B = S + i * k * k; g.ldb = k; g.N = k;
+          g.C = T + i * k * k; g.ldc = kt;
+          g.alpha_re = 1.0;
+          g1.push_back(g);
+        }
         GemmDesc gg{};
         gg.A = T + i * k * k; gg.lda = kt; gg.M = kt; gg.K = k;
         gg.B = Cc_ptr[qs]; gg.ldb = ks; gg.N = ks; gg.opB = 2;
@@ -1699,8 +1772,9 @@ struct Builder {
         gg.alpha_re = 1.0;
         g2.push_back(gg);
       }
-      if (!g1.empty()) {
+      if (!g2.empty()) {
         gemm(g1, tmp);
+        gemm_coupling(c1, tmp);
         gemm(g2, tmp);
       }
       h.check_launch();
@@ -2228,6 +2302,7 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   h.sync();
   h.stats.ms_projection = now_ms() - t0;
   h.stats.coupling_regeneration = p.adm.empty() ? 0.0 : (double)bd.n_coupling_gen / (double)p.adm.size();
+  h.stats.coupling_in_products = p.adm.empty() ? 0.0 : (double)bd.n_coupling_fused / (double)p.adm.size();
   // release build-only buffers
   h.R_d = bd.R_d;
   h.Zr_d = bd.Zr_d;

@@ -224,6 +224,25 @@ __global__ void __launch_bounds__(256) k_transfer(const TransDesc* __restrict__ 
   }
 }
 
+// One entry of a coupling matrix S_b (defined below, before k_coupling) at the
+// interpolation points x_t of the row cluster and x_s of the column cluster.
+// Shared by k_coupling (S_b stored) and k_gemm_coupling (S_b formed inside a
+// product), so the two give the same bits.
+__device__ __forceinline__ z64 coupling_entry(double xt, double yt, double zt, double xs, double ys, double zs,
+                                              const double (&c)[3], double kappa) {
+  const double f0 = 0.25 / M_PI;
+  const double dx = xt - xs;
+  const double dy = yt - ys;
+  const double dz = zt - zs;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir = rsqrt_r(r2);
+  const double r = r2 * ir;
+  double sn, cs;
+  sincos_fast(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
+  const double f = f0 * ir;
+  return z64{f * cs, f * sn};
+}
+
 // ---------------------------------------------------------------------------
 // Coupling matrices (Section 2): S_b[nu,mu] = g_c(xi_{t,nu}, xi_{s,mu}),
 // g_c(x,y) = exp(i kappa (|x-y| - <x-y,c>)) / (4 pi |x-y|).  One workgroup per
@@ -256,7 +275,6 @@ __global__ void __launch_bounds__(256) k_coupling(const CoupDesc* __restrict__ d
   }
   __syncthreads();
   cpx<R>* o = out + (int64_t)blockIdx.x * k * k;
-  const double f0 = 0.25 / M_PI;
   // thread = row nu (its point in registers), the column points are read from
   // LDS (the same for every lane of an iteration); writes are coalesced
   const int ng = blockDim.x / 128;
@@ -265,16 +283,8 @@ __global__ void __launch_bounds__(256) k_coupling(const CoupDesc* __restrict__ d
     if (nu >= k) continue;
     const double xt = pt[0][nu % m], yt = pt[1][(nu / m) % m], zt = pt[2][nu / (m * m)];
     for (int mu = threadIdx.x >> 7; mu < k; mu += ng) {
-      const double dx = xt - qs[0][mu];
-      const double dy = yt - qs[1][mu];
-      const double dz = zt - qs[2][mu];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const double ir = rsqrt_r(r2);
-      const double r = r2 * ir;
-      double sn, cs;
-      sincos_fast(kappa * (r - (dx * c[0] + dy * c[1] + dz * c[2])), &sn, &cs);
-      const double f = f0 * ir;
-      o[nu + (int64_t)mu * k] = cpx<R>{(R)(f * cs), (R)(f * sn)};
+      const z64 v = coupling_entry(xt, yt, zt, qs[0][mu], qs[1][mu], qs[2][mu], c, kappa);
+      o[nu + (int64_t)mu * k] = cpx<R>{(R)v.x, (R)v.y};
     }
   }
 }
@@ -382,8 +392,11 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
       else Bs[e / 32][e % 32] = vb[h];
     }
   };
-  load_slice(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  // first slice: 0, or past the known zeros of a trapezoidal operand (m0 and
+  // n0 are multiples of the slice depth)
+  const int kb = max((d.tri & 1) ? m0 : 0, (d.tri & 2) ? n0 : 0);
+  load_slice(kb);
+  for (int k0 = kb; k0 < d.K; k0 += 16) {
     store_slice();
     __syncthreads();
     if (k0 + 16 < d.K) load_slice(k0 + 16);
@@ -406,6 +419,154 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
       const cpx<S> v = al * cpx<S>{(S)cre[e], (S)cim[e]};
       cpx<S>& dst = C[gi + (int64_t)gj * d.ldc];
       dst = d.accumulate ? dst + v : v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Products with a coupling matrix that is never stored: C = alpha A S_b or
+// C = alpha A S_b^H (A: M x k, column-major), the entries of S_b evaluated in
+// the product's B slices (coupling_entry, the bits k_coupling stores).  The
+// recompression takes S_b only through such products in its Frobenius-norm
+// passes (R_tc S_b, R_sc S_b^H / omega_b) and in the projection (C_tc S_b),
+// so the k^2 coupling of a block need not go through HBM.  A workgroup owns 32
+// columns of C and all of its rows, in chunks of 32 MT rows: every entry of
+// S_b is evaluated once per chunk, the 16 x 32 B slice of the next step while
+// the matrix cores multiply the current one.  Each wave holds MT 16 x 16
+// sub-tiles; per sub-tile the accumulation order is that of k_gemm (same
+// slices, same MFMA sequence), so with coupling_entry's values the result
+// equals k_gemm on a stored S_b bit for bit.  Slices that lie in the known
+// zeros of a trapezoidal A (tri bit 0) are skipped per sub-tile.  MT = 1, 2, 4
+// is chosen per product by its row count (fewer accumulators and loads, more
+// waves in flight to hide the evaluation's latency when M is small).
+template <int MT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT == 4 ? 2 : 3)))
+k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, const double* __restrict__ box,
+                const double* __restrict__ dirs) {
+  typedef GMfma<double>::acc_t acc_t;
+  constexpr int RC = 32 * MT;                 // rows per chunk
+  constexpr int NL = RC * 16 / 256;           // A entries per thread and slice
+  const CoupGemmDesc d = dd[blockIdx.y];
+  const int m = ct.m;
+  const int k = m * m * m;
+  const int n0 = blockIdx.x * 32;
+  if (n0 >= k || d.M <= 0) return;
+  const z64* A = (const z64*)d.A;
+  z64* C = (z64*)d.C;
+  __shared__ double pt[3][kMaxOrder], ps[3][kMaxOrder];
+  __shared__ z64 As[16][RC + 1];
+  __shared__ z64 Bs[16][33];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int sn = (wave & 1) * 16;             // sub-tile column
+  const int sm0 = (wave >> 1) * 16;           // sub-tile rows sm0 + 32 u, u < MT
+  if (tid < 3 * m) {
+    const int a = tid / m, j = tid % m;
+    const double* bt = box + 6 * d.t;
+    const double* bs = box + 6 * d.s;
+    pt[a][j] = axis_point(ct, bt[a], bt[a + 3], j);
+    ps[a][j] = axis_point(ct, bs[a], bs[a + 3], j);
+  }
+  __syncthreads();
+  const double c[3] = {dirs[3 * d.dir], dirs[3 * d.dir + 1], dirs[3 * d.dir + 2]};
+  // B slice entries of this thread: row kk of the slice, columns jb and jb + 16.
+  // op(S)[j][n] is S_b[j][n] (the K index a point of t, the column one of s)
+  // or conj(S_b[n][j]) (the K index a point of s, the column one of t).
+  const int kk = tid & 15, jb = tid >> 4;
+  const bool cj = d.conj != 0;
+  double nx[2], ny[2], nz[2];
+  bool nok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = min(n0 + jb + 16 * h, k - 1);
+    const int i0 = n % m, i1 = (n / m) % m, i2 = n / (m * m);
+    nok[h] = n0 + jb + 16 * h < k;
+    nx[h] = cj ? pt[0][i0] : ps[0][i0];
+    ny[h] = cj ? pt[1][i1] : ps[1][i1];
+    nz[h] = cj ? pt[2][i2] : ps[2][i2];
+  }
+  // A slice entries of this thread: row ia (the same in every slice), slice
+  // rows ka0 + 256 / RC u
+  const int ia = tid & (RC - 1), ka0 = tid / RC;
+  const z64 al{d.alpha, 0.0};
+  for (int mc = 0; mc < d.M; mc += RC) {
+    const int rows = min(RC, d.M - mc);
+    // wave-uniform: a wave whose A rows all lie past M loads nothing
+    const bool wload = ((wave * 64) & (RC - 1)) < rows;
+    acc_t cre[MT], cim[MT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cre[u][e] = cim[u][e] = 0.0;
+    z64 va[NL], vb[2];
+    auto load_slice = [&](int k0) __attribute__((always_inline)) {
+      const int j = k0 + kk;
+      const bool kok = j < k;
+      const int jc = min(j, k - 1);
+      const int i0 = jc % m, i1 = (jc / m) % m, i2 = jc / (m * m);
+      const double kx = cj ? ps[0][i0] : pt[0][i0];
+      const double ky = cj ? ps[1][i1] : pt[1][i1];
+      const double kz = cj ? ps[2][i2] : pt[2][i2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // x_t is the K point (S_b) or the column point (S_b^H)
+        const double xt = cj ? nx[h] : kx, yt = cj ? ny[h] : ky, zt = cj ? nz[h] : kz;
+        const double xs = cj ? kx : nx[h], ys = cj ? ky : ny[h], zs = cj ? kz : nz[h];
+        z64 v = coupling_entry(xt, yt, zt, xs, ys, zs, c, kappa);
+        if (cj) v.y = -v.y;
+        vb[h] = (kok && nok[h]) ? v : z64{0.0, 0.0};
+      }
+      // unmasked loads from a clamped (valid) address, then a select
+      if (wload) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+          const int ka = k0 + ka0 + (256 / RC) * u;
+          typedef double v2 __attribute__((ext_vector_type(2)));
+          const v2 w = *(const __attribute__((address_space(1))) v2*)(A + mc + min(ia, rows - 1) +
+                                                                      (int64_t)min(ka, k - 1) * d.lda);
+          const bool ok = ia < rows && ka < k;
+          va[u] = z64{ok ? w.x : 0.0, ok ? w.y : 0.0};
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) va[u] = z64{0.0, 0.0};
+      }
+    };
+    load_slice(0);
+    for (int k0 = 0; k0 < k; k0 += 16) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) As[ka0 + (256 / RC) * u][ia] = va[u];
+      Bs[kk][jb] = vb[0];
+      Bs[kk][jb + 16] = vb[1];
+      __syncthreads();
+      if (k0 + 16 < k) load_slice(k0 + 16);
+#pragma unroll
+      for (int u = 0; u < MT; ++u) {
+        const int ms = sm0 + 32 * u;
+        // wave-uniform: rows past M, or a slice wholly left of a trapezoidal A's diagonal
+        if (ms < rows && !((d.tri & 1) && k0 + 16 <= mc + ms)) {
+#pragma unroll
+          for (int ks = 0; ks < 16; ks += 4) {
+            const z64 a = As[ks + lk][ms + li];
+            const z64 b = Bs[ks + lk][sn + li];
+            cre[u] = GMfma<double>::mac(a.x, b.x, cre[u]);
+            cre[u] = GMfma<double>::mac(-a.y, b.y, cre[u]);
+            cim[u] = GMfma<double>::mac(a.x, b.y, cim[u]);
+            cim[u] = GMfma<double>::mac(a.y, b.x, cim[u]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+      const int ms = sm0 + 32 * u;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = ms + GMfma<double>::row(lane, e), gj = n0 + sn + li;
+        if (gi < rows && gj < k) C[mc + gi + (int64_t)gj * d.ldc] = al * z64{cre[u][e], cim[u][e]};
+      }
     }
   }
 }
@@ -499,8 +660,9 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const GemmDesc* __restrict_
       split_bf16(vb[h].y, Bs[2][j][kb], Bs[3][j][kb]);
     }
   };
-  load_slice(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  const int kb = max((d.tri & 1) ? m0 : 0, (d.tri & 2) ? n0 : 0);
+  load_slice(kb);
+  for (int k0 = kb; k0 < d.K; k0 += 16) {
     store_slice();
     __syncthreads();
     if (k0 + 16 < d.K) load_slice(k0 + 16);
@@ -1434,6 +1596,22 @@ void launch_coupling(const CoupDesc* d, int64_t nb, const ChebTab& ct, double ka
 }
 template void launch_coupling<double>(const CoupDesc*, int64_t, const ChebTab&, double,
                                       const double*, const double*, void*, hipStream_t);
+
+void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct, double kappa,
+                          const double* box, const double* dirs, hipStream_t st) {
+  const int k = ct.m * ct.m * ct.m;
+  const int ntn = (k + 31) / 32;
+  for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
+    const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
+    const dim3 g((unsigned)ntn, (unsigned)cnt);
+    if (mt == 1)
+      hipLaunchKernelGGL(k_gemm_coupling<1>, g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+    else if (mt == 2)
+      hipLaunchKernelGGL(k_gemm_coupling<2>, g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+    else
+      hipLaunchKernelGGL(k_gemm_coupling<4>, g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+  }
+}
 
 template <typename R>
 void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st) {

@@ -51,6 +51,11 @@ struct GemmDesc {
   int32_t accumulate;
   int32_t upper;      // FP64 kernel only: skip the 32 x 32 tiles of C below its diagonal
                       // (a Hermitian product whose upper triangle is all that is read)
+  int32_t tri;        // zeros known in an operand (upper trapezoidal R factors of a QR):
+                      // bit 0: op(A)[i][j] = 0 for j < i; bit 1: op(B)[j][n] = 0 for j < n.
+                      // A tile then starts its K loop at its first row (bit 0) or column
+                      // (bit 1); the products it skips are exact zeros, so C is unchanged.
+  int32_t pad_;
   double alpha_re, alpha_im;
 };
 
@@ -180,6 +185,24 @@ void launch_transfer(const TransDesc* d, int64_t nb, const ChebTab& ct, double k
 template <typename R>
 void launch_coupling(const CoupDesc* d, int64_t nb, const ChebTab& ct, double kappa,
                      const double* box, const double* dirs, void* out, hipStream_t st);
+
+// C = alpha A S_b (conj 0) or alpha A S_b^H (conj 1) with S_b of block
+// (t, s, dir) evaluated inside the product (k_gemm_coupling); A is M x k,
+// column-major; C is M x k.  FP64.  mt: rows per chunk / 32 (1, 2 or 4); the
+// caller groups the products by M (M <= 32 mt, or any M for mt = 4).
+struct CoupGemmDesc {
+  const void* A;
+  void* C;
+  int32_t M, lda, ldc;
+  int32_t t, s;
+  int32_t conj;
+  int32_t tri;        // bit 0: A[i][j] = 0 for j < i (as GemmDesc.tri)
+  int32_t pad_;
+  int64_t dir;
+  double alpha;
+};
+void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct, double kappa,
+                          const double* box, const double* dirs, hipStream_t st);
 template <typename R>
 void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st);
 // The same products on FP64 data with split-BF16x3 MFMA products and FP32 accumulation

@@ -72,7 +72,7 @@ class Stats(ctypes.Structure):
                 ("coupling_regeneration", ctypes.c_double), ("sketch_slots", ctypes.c_int64),
                 ("sketch_fallbacks", ctypes.c_int64), ("ms_rank_predict", ctypes.c_double),
                 ("mv_variant", ctypes.c_int32 * 4), ("ms_autotune", ctypes.c_double),
-                ("weights_gram", ctypes.c_int32)]
+                ("weights_gram", ctypes.c_int32), ("coupling_in_products", ctypes.c_double)]
 
 
 class PlanSizes(ctypes.Structure):

@@ -223,3 +223,32 @@ def test_gram_weights_edge_cases():
         assert err <= 1e-9
     finally:
         h.free()
+
+
+def test_couplings_formed_inside_products():
+    """Where a phase needs a coupling S_b only through a product with it, FP64
+    builds evaluate S_b inside that product (k_gemm_coupling) and never store
+    it: both Gram passes with the Frobenius norm (R_tc S_b, R_sc S_b^H /
+    omega_b) and the projection (C_tc S_b).  The spectral norm needs S_b
+    itself in the first pass, the Householder form stores it for its block and
+    total weights, and the FP32 form keeps its FP32 product kernel; the
+    products of every form are checked against the oracle by the tests above.
+    Counts per admissible block, k = 64 (one 128-row chunk per product)."""
+    from paper_1809_04384_amd import dh2
+    cases = [
+        ("gram, frobenius, fp64", dict(weights=dh2.WEIGHTS_GRAM), 3.0, 3.0),
+        ("gram, spectral, fp64", dict(weights=dh2.WEIGHTS_GRAM, norm=dh2.NORM_SPECTRAL), 3.0, 2.0),
+        ("householder, fp64", dict(weights=dh2.WEIGHTS_HOUSEHOLDER), 4.0, 1.0),
+        ("gram, fp32", dict(weights=dh2.WEIGHTS_GRAM, precision=dh2.FP32), 3.0, 0.0),
+    ]
+    for label, kw, gen, inside in cases:
+        h, _ = build_handle("sphere2k", **kw)
+        try:
+            st = h.stats()
+            say("[gpu] sphere2k %s: S_b generated %.2f x per block, %.2f x inside products"
+                % (label, st["coupling_regeneration"], st["coupling_in_products"]))
+            assert st["n_adm"] > 0
+            assert st["coupling_regeneration"] == gen, label
+            assert st["coupling_in_products"] == inside, label
+        finally:
+            h.free()
