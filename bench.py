@@ -791,8 +791,9 @@ def main():
                      "build": {"bound": "fp64", "achieved": round(build_tflops, 2), "unit": "TFLOP/s",
                                "peak": FP64_PEAK_TFLOPS, "frac": round(build_tflops / FP64_PEAK_TFLOPS, 4),
                                "flops": st["gemm_flops"] + st["qr_flops"],
-                               "note": "complex products (8 MNK) and Householder QR steps (8 M n^2) of "
-                                       "the recompression over the whole build time"}},
+                               "note": "complex products (8 MNK, only the products outside the zeros "
+                                       "of a trapezoidal basis weight) and Householder QR steps (8 M n^2) "
+                                       "of the recompression over the whole build time"}},
         "rel_err": errs,
         "cpu_baseline": base,
         "fp32_form": fp32,

@@ -438,14 +438,20 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
 // equals k_gemm on a stored S_b bit for bit.  Slices that lie in the known
 // zeros of a trapezoidal A (tri bit 0) are skipped per sub-tile.  MT = 1, 2, 4
 // is chosen per product by its row count (fewer accumulators and loads, more
-// waves in flight to hide the evaluation's latency when M is small).
-template <int MT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT == 4 ? 2 : 3)))
+// waves in flight to hide the evaluation's latency when M is small); NW waves
+// per workgroup hold 4 MT / NW sub-tiles each, registers sized for WPE waves
+// per SIMD (128-row chunks: eight waves of two sub-tiles, four per SIMD).
+template <int MT, int NW, int WPE>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, const double* __restrict__ box,
                 const double* __restrict__ dirs) {
   typedef GMfma<double>::acc_t acc_t;
+  constexpr int NT = 64 * NW;                 // threads
   constexpr int RC = 32 * MT;                 // rows per chunk
-  constexpr int NL = RC * 16 / 256;           // A entries per thread and slice
+  constexpr int NL = RC * 16 / NT;            // A entries per thread and slice
+  constexpr int NB = 512 / NT;                // B entries per thread and slice
+  constexpr int SPW = 4 * MT / NW;            // 16 x 16 sub-tiles per wave
+  static_assert(SPW >= 1 && NL >= 1 && NB >= 1, "shape");
   const CoupGemmDesc d = dd[blockIdx.y];
   const int m = ct.m;
   const int k = m * m * m;
@@ -460,7 +466,7 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int sn = (wave & 1) * 16;             // sub-tile column
-  const int sm0 = (wave >> 1) * 16;           // sub-tile rows sm0 + 32 u, u < MT
+  const int sm0 = (wave >> 1) * 16;           // sub-tile rows sm0 + 8 NW u, u < SPW
   if (tid < 3 * m) {
     const int a = tid / m, j = tid % m;
     const double* bt = box + 6 * d.t;
@@ -470,36 +476,36 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
   }
   __syncthreads();
   const double c[3] = {dirs[3 * d.dir], dirs[3 * d.dir + 1], dirs[3 * d.dir + 2]};
-  // B slice entries of this thread: row kk of the slice, columns jb and jb + 16.
+  // B slice entries of this thread: row kk of the slice, columns jb + NT / 16 h, h < NB.
   // op(S)[j][n] is S_b[j][n] (the K index a point of t, the column one of s)
   // or conj(S_b[n][j]) (the K index a point of s, the column one of t).
   const int kk = tid & 15, jb = tid >> 4;
   const bool cj = d.conj != 0;
-  double nx[2], ny[2], nz[2];
-  bool nok[2];
+  double nx[NB], ny[NB], nz[NB];
+  bool nok[NB];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int n = min(n0 + jb + 16 * h, k - 1);
+  for (int h = 0; h < NB; ++h) {
+    const int n = min(n0 + jb + (NT / 16) * h, k - 1);
     const int i0 = n % m, i1 = (n / m) % m, i2 = n / (m * m);
-    nok[h] = n0 + jb + 16 * h < k;
+    nok[h] = n0 + jb + (NT / 16) * h < k;
     nx[h] = cj ? pt[0][i0] : ps[0][i0];
     ny[h] = cj ? pt[1][i1] : ps[1][i1];
     nz[h] = cj ? pt[2][i2] : ps[2][i2];
   }
   // A slice entries of this thread: row ia (the same in every slice), slice
-  // rows ka0 + 256 / RC u
+  // rows ka0 + NT / RC u
   const int ia = tid & (RC - 1), ka0 = tid / RC;
   const z64 al{d.alpha, 0.0};
   for (int mc = 0; mc < d.M; mc += RC) {
     const int rows = min(RC, d.M - mc);
     // wave-uniform: a wave whose A rows all lie past M loads nothing
     const bool wload = ((wave * 64) & (RC - 1)) < rows;
-    acc_t cre[MT], cim[MT];
+    acc_t cre[SPW], cim[SPW];
 #pragma unroll
-    for (int u = 0; u < MT; ++u)
+    for (int u = 0; u < SPW; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) cre[u][e] = cim[u][e] = 0.0;
-    z64 va[NL], vb[2];
+    z64 va[NL], vb[NB];
     auto load_slice = [&](int k0) __attribute__((always_inline)) {
       const int j = k0 + kk;
       const bool kok = j < k;
@@ -509,7 +515,7 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
       const double ky = cj ? ps[1][i1] : pt[1][i1];
       const double kz = cj ? ps[2][i2] : pt[2][i2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < NB; ++h) {
         // x_t is the K point (S_b) or the column point (S_b^H)
         const double xt = cj ? nx[h] : kx, yt = cj ? ny[h] : ky, zt = cj ? nz[h] : kz;
         const double xs = cj ? kx : nx[h], ys = cj ? ky : ny[h], zs = cj ? kz : nz[h];
@@ -521,7 +527,7 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
       if (wload) {
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
-          const int ka = k0 + ka0 + (256 / RC) * u;
+          const int ka = k0 + ka0 + (NT / RC) * u;
           typedef double v2 __attribute__((ext_vector_type(2)));
           const v2 w = *(const __attribute__((address_space(1))) v2*)(A + mc + min(ia, rows - 1) +
                                                                       (int64_t)min(ka, k - 1) * d.lda);
@@ -536,14 +542,14 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
     load_slice(0);
     for (int k0 = 0; k0 < k; k0 += 16) {
 #pragma unroll
-      for (int u = 0; u < NL; ++u) As[ka0 + (256 / RC) * u][ia] = va[u];
-      Bs[kk][jb] = vb[0];
-      Bs[kk][jb + 16] = vb[1];
+      for (int u = 0; u < NL; ++u) As[ka0 + (NT / RC) * u][ia] = va[u];
+#pragma unroll
+      for (int h = 0; h < NB; ++h) Bs[kk][jb + (NT / 16) * h] = vb[h];
       __syncthreads();
       if (k0 + 16 < k) load_slice(k0 + 16);
 #pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const int ms = sm0 + 32 * u;
+      for (int u = 0; u < SPW; ++u) {
+        const int ms = sm0 + 8 * NW * u;
         // wave-uniform: rows past M, or a slice wholly left of a trapezoidal A's diagonal
         if (ms < rows && !((d.tri & 1) && k0 + 16 <= mc + ms)) {
 #pragma unroll
@@ -560,8 +566,8 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
       __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < MT; ++u) {
-      const int ms = sm0 + 32 * u;
+    for (int u = 0; u < SPW; ++u) {
+      const int ms = sm0 + 8 * NW * u;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gi = ms + GMfma<double>::row(lane, e), gj = n0 + sn + li;
@@ -1605,11 +1611,11 @@ void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const C
     const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
     const dim3 g((unsigned)ntn, (unsigned)cnt);
     if (mt == 1)
-      hipLaunchKernelGGL(k_gemm_coupling<1>, g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<1, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
     else if (mt == 2)
-      hipLaunchKernelGGL(k_gemm_coupling<2>, g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<2, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
     else
-      hipLaunchKernelGGL(k_gemm_coupling<4>, g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<4, 8, 4>), g, dim3(512), 0, st, d + i0, ct, kappa, box, dirs);
   }
 }
 
