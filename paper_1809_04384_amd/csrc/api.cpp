@@ -16,7 +16,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -2218,17 +2217,33 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
     }
     h.stats.near_entries = off;
     // The Galerkin matrix is symmetric: of the pair (t, s), (s, t) only the
-    // block with t < s is evaluated, its mirror is its transpose.
-    std::map<std::pair<int64_t, int64_t>, int64_t> where;
-    for (size_t b = 0; b < p.near.size(); ++b) where[{p.near[b].t, p.near[b].s}] = (int64_t)b;
+    // block with t < s is evaluated, its mirror is its transpose.  Mirrors are
+    // found through the blocks grouped by row cluster, each group sorted by
+    // column cluster (a binary search per block).
+    const int64_t nnear = (int64_t)p.near.size();
+    std::vector<int64_t> rptr(nc + 1, 0), rblk(nnear);
+    for (int64_t b = 0; b < nnear; ++b) ++rptr[p.near[b].t + 1];
+    for (int64_t t = 0; t < nc; ++t) rptr[t + 1] += rptr[t];
+    {
+      std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
+      for (int64_t b = 0; b < nnear; ++b) rblk[fill[p.near[b].t]++] = b;
+      for (int64_t t = 0; t < nc; ++t)
+        std::sort(rblk.begin() + rptr[t], rblk.begin() + rptr[t + 1],
+                  [&](int64_t a, int64_t c) { return p.near[a].s < p.near[c].s || (p.near[a].s == p.near[c].s && a < c); });
+    }
+    auto find_block = [&](int64_t t, int64_t sc) -> int64_t {   // first block (t, sc), or -1
+      auto lo = std::lower_bound(rblk.begin() + rptr[t], rblk.begin() + rptr[t + 1], sc,
+                                 [&](int64_t a, int64_t v) { return p.near[a].s < v; });
+      return (lo != rblk.begin() + rptr[t + 1] && p.near[*lo].s == sc) ? *lo : -1;
+    };
     std::vector<NearDesc> eval;
     std::vector<std::pair<int64_t, int64_t>> mirrors;      // (mirror block, evaluated block)
-    for (size_t b = 0; b < p.near.size(); ++b) {
+    for (int64_t b = 0; b < nnear; ++b) {
       const int64_t t = p.near[b].t, sc = p.near[b].s;
       if (t > sc) {
-        auto it = where.find({sc, t});
-        if (it != where.end()) {
-          mirrors.push_back({(int64_t)b, it->second});
+        const int64_t m = find_block(sc, t);
+        if (m >= 0) {
+          mirrors.push_back({b, m});
           continue;
         }
       }
