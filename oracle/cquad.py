@@ -5,6 +5,7 @@ import math
 import numpy as np
 
 from . import build_oracle
+from . import ses
 from .quadrature import laplace_self_integral
 
 _lib = None
@@ -56,3 +57,25 @@ def near_block(tri, rows, cols, kappa):
 def far_block(tri, rows, cols, kappa):
     """Reference Galerkin block with the Q7 x Q7 product rule (i != j)."""
     return pair_sums(rows, cols, tri["x7"], tri["w7"], kappa)
+
+
+def near_block_paper(tri, rows, cols, kappa):
+    """Near-field Galerkin block with the paper's quadrature (Section 5):
+    Duffy-Gauss of order 3 on both triangles (x9, w9) for pairs that share no
+    vertex, Sauter-Erichsen-Schwab of order 5 for pairs that share a vertex,
+    an edge, or are identical.  The touching rules are not symmetric in the
+    two triangles, so a pair is always integrated with the triangle of lower
+    index first: the matrix stays exactly symmetric."""
+    out = pair_sums(rows, cols, tri["x9"], tri["w9"], kappa)
+    V, T, vt = tri["V"], tri["T"], tri["vert_tris"]
+    pos = {int(j): c for c, j in enumerate(cols)}
+    for r, i in enumerate(np.asarray(rows)):
+        cand = set()
+        for v in T[int(i)]:
+            cand.update(vt[int(v)])
+        for j in sorted(cand):
+            c = pos.get(j)
+            if c is not None:
+                lo, hi = min(int(i), j), max(int(i), j)
+                out[r, c] = ses.ses_pair(V, T[lo], T[hi], kappa)
+    return out

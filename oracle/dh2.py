@@ -45,7 +45,7 @@ class OracleDH2:
     (cluster, direction index) / block index, for inspection by the tests."""
 
     def __init__(self, V, T, kappa, order, eta, leaf, tol, eta1=10.0, norm="fro",
-                 recompress=True, interp_only=False, lazy=False):
+                 recompress=True, interp_only=False, lazy=False, quadrature="default"):
         V = np.asarray(V, dtype=np.float64)
         T = np.asarray(T, dtype=np.int64)
         self.kappa = float(kappa)
@@ -53,6 +53,13 @@ class OracleDH2:
         self.k = self.m ** 3
         self.tol = float(tol)
         self.norm = norm
+        # "default": Q16 near rule with the closed-form self term, Q7 far rule;
+        # "paper": Section 5's rules (Sauter-Erichsen-Schwab of order 5 for
+        # touching pairs, Duffy-Gauss of order 3 for all others and the bases)
+        if quadrature not in ("default", "paper"):
+            raise ValueError("quadrature must be 'default' or 'paper'")
+        self.quadrature = quadrature
+        self._xf, self._wf = ("x9", "w9") if quadrature == "paper" else ("x7", "w7")
         t_start = time.perf_counter()
         self.st = build_structure(V, T, kappa, eta, leaf, eta1)
         self.tri = triangle_data(V, T)
@@ -127,24 +134,37 @@ class OracleDH2:
         return sorted(pairs, key=lambda p: ((-lv[p[0]]) if descending else lv[p[0]], p[0], p[1]))
 
     # ------------------------------------------------------------------ near field
+    def near_block(self, rows, cols):
+        """Near-field Galerkin entries of the rows x cols triangles with this
+        oracle's quadrature."""
+        if self.quadrature == "paper":
+            return cquad.near_block_paper(self.tri, rows, cols, self.kappa)
+        return cquad.near_block(self.tri, rows, cols, self.kappa)
+
+    def far_block(self, rows, cols):
+        """Reference entries of admissible blocks: the far rule on both triangles."""
+        return cquad.pair_sums(rows, cols, self.tri[self._xf], self.tri[self._wf], self.kappa)
+
     def _near_field(self):
         st = self.st
         self.N = []
         for (t, s) in st.near:
-            self.N.append(cquad.near_block(self.tri, st.idx(t), st.idx(s), self.kappa))
+            self.N.append(self.near_block(st.idx(t), st.idx(s)))
 
     # ------------------------------------------------------------------ interpolation
     def leaf_basis(self, t, c):
-        """V_tc for a leaf t: Q7 quadrature of the modulated Lagrange polynomials."""
+        """V_tc for a leaf t: the far rule (Q7, or the paper's 9-point rule) applied
+        to the modulated Lagrange polynomials."""
         st = self.st
         idx = st.idx(t)
-        x = self.tri["x7"][idx]               # [#t, 7, 3]
-        w = self.tri["w7"][idx]               # [#t, 7]
+        x = self.tri[self._xf][idx]           # [#t, nq, 3]
+        w = self.tri[self._wf][idx]           # [#t, nq]
+        nq = x.shape[1]
         cvec = self.dir(t, c)
         flat = x.reshape(-1, 3)
-        L = box_lagrange(flat, st.lo[t], st.hi[t], self.m)          # [#t*7, k]
-        phase = np.exp(1j * self.kappa * (flat @ cvec))             # [#t*7]
-        vals = (L * phase[:, None]).reshape(len(idx), 7, self.k)
+        L = box_lagrange(flat, st.lo[t], st.hi[t], self.m)          # [#t*nq, k]
+        phase = np.exp(1j * self.kappa * (flat @ cvec))             # [#t*nq]
+        vals = (L * phase[:, None]).reshape(len(idx), nq, self.k)
         return np.einsum("iq,iqk->ik", w, vals)
 
     def transfer(self, t1, c):
@@ -444,7 +464,7 @@ class OracleDH2:
                     Y += Vt @ (self.coupling(b) @ fwd(s, c))
                 for i in self._near_of.get(a, []):
                     _, s = st.near[i]
-                    Y += cquad.near_block(self.tri, st.idx(t), st.idx(s), self.kappa) @ X[st.idx(s)]
+                    Y += self.near_block(st.idx(t), st.idx(s)) @ X[st.idx(s)]
             rows.append(st.idx(t))
             out.append(Y)
         return np.concatenate(rows), np.vstack(out)
@@ -474,11 +494,12 @@ class OracleDH2:
 
     def dense_galerkin(self):
         """Reference Galerkin matrix: near rule on inadmissible leaves (self term
-        on the diagonal), Q7 x Q7 on admissible leaves."""
+        on the diagonal, or the paper's touching-pair rules), far rule x far rule
+        on admissible leaves."""
         st = self.st
         G = np.zeros((self.n, self.n), dtype=np.complex128)
         for (t, s, c) in st.adm:
-            G[np.ix_(st.idx(t), st.idx(s))] = cquad.far_block(self.tri, st.idx(t), st.idx(s), self.kappa)
+            G[np.ix_(st.idx(t), st.idx(s))] = self.far_block(st.idx(t), st.idx(s))
         for i, (t, s) in enumerate(st.near):
             G[np.ix_(st.idx(t), st.idx(s))] = self.N[i]
         return G
@@ -492,13 +513,13 @@ class OracleDH2:
         for (t, s, c) in st.adm:
             sel = [int(i) for i in st.idx(t) if int(i) in where]
             if sel:
-                blk = cquad.far_block(self.tri, np.array(sel), st.idx(s), self.kappa)
+                blk = self.far_block(np.array(sel), st.idx(s))
                 for r, i in enumerate(sel):
                     out[where[i], st.idx(s)] = blk[r]
         for (t, s) in st.near:
             sel = [int(i) for i in st.idx(t) if int(i) in where]
             if sel:
-                blk = cquad.near_block(self.tri, np.array(sel), st.idx(s), self.kappa)
+                blk = self.near_block(np.array(sel), st.idx(s))
                 for r, i in enumerate(sel):
                     out[where[i], st.idx(s)] = blk[r]
         return out

@@ -69,11 +69,25 @@ def q16_rule():
     return np.array(lam), np.array(w)
 
 
+def q9_rule():
+    """3 x 3 Gauss-Legendre collapsed by the Duffy map (the paper's rule of order
+    3 for pairs of triangles that share no vertex, Section 5); weights sum to one."""
+    u, wu = gauss_legendre_01(3)
+    lam = []
+    w = []
+    for i in range(3):
+        for j in range(3):
+            lam.append((1.0 - u[i], u[i] * (1.0 - u[j]), u[i] * u[j]))
+            w.append(2.0 * wu[i] * wu[j] * u[i])
+    return np.array(lam), np.array(w)
+
+
 def triangle_data(V, T):
     """Per-triangle area, centroid, Q7 and Q16 physical points and weights.
 
     Returns dict with area [n], centroid [n,3], x7 [n,7,3], w7 [n,7],
-    x16 [n,16,3], w16 [n,16] and the vertex coordinates P [n,3,3].
+    x16 [n,16,3], w16 [n,16], x9 [n,9,3], w9 [n,9] (the paper's rule), the
+    vertex coordinates P [n,3,3], V, T and the triangles of every vertex.
     """
     P = V[T]                       # [n, 3 vertices, 3 coords]
     a, b, c = P[:, 0], P[:, 1], P[:, 2]
@@ -86,11 +100,19 @@ def triangle_data(V, T):
     centroid = ((a + b) + c) / 3.0
     l7, w7 = q7_rule()
     l16, w16 = q16_rule()
+    l9, w9 = q9_rule()
     x7 = np.einsum("qv,nvd->nqd", l7, P)
     x16 = np.einsum("qv,nvd->nqd", l16, P)
+    x9 = np.einsum("qv,nvd->nqd", l9, P)
+    vert_tris = {}
+    for i, tri in enumerate(np.asarray(T)):
+        for v in tri:
+            vert_tris.setdefault(int(v), []).append(i)
     return {"P": P, "area": area, "centroid": centroid,
             "x7": x7, "w7": area[:, None] * w7[None, :],
-            "x16": x16, "w16": area[:, None] * w16[None, :]}
+            "x16": x16, "w16": area[:, None] * w16[None, :],
+            "x9": x9, "w9": area[:, None] * w9[None, :],
+            "V": np.asarray(V, dtype=np.float64), "T": np.asarray(T), "vert_tris": vert_tris}
 
 
 def laplace_self_integral(p0, p1, p2):
