@@ -109,6 +109,21 @@ typedef enum { DH2_RANKS_EXACT = 0, DH2_RANKS_LEARNED = 1 } dh2_rank_mode;
  *   otherwise). */
 typedef enum { DH2_WEIGHTS_HOUSEHOLDER = 0, DH2_WEIGHTS_GRAM = 1 } dh2_weights_mode;
 
+/* Quadrature of the Galerkin entries (piecewise-constant basis on flat
+ * triangles).
+ * DH2_QUAD_DEFAULT: the near field by the 16-point Duffy-collapsed Gauss rule on
+ *   both triangles, its diagonal by singularity subtraction (closed-form Laplace
+ *   part plus the 16 x 16 rule on the bounded remainder); the leaf bases by the
+ *   7-point rule.
+ * DH2_QUAD_PAPER: the rules of Section 5: Sauter-Erichsen-Schwab quadrature of
+ *   order 5 (5^4 tensor Gauss points per region of the regularising
+ *   coordinates) for triangle pairs that share a vertex, an edge, or are
+ *   identical; Gauss quadrature with the Duffy transformation of order 3 (3 x 3
+ *   points per triangle) for every other near-field pair and for the leaf
+ *   bases.  A touching pair is integrated with the triangle of lower index (in
+ *   the caller's numbering) first, so the matrix stays exactly symmetric. */
+typedef enum { DH2_QUAD_DEFAULT = 0, DH2_QUAD_PAPER = 1 } dh2_quadrature;
+
 /* Optional settings.  Zero-initialise, set size = sizeof(dh2_options), then
  * override fields; zero fields take the defaults given here. */
 typedef struct {
@@ -132,6 +147,7 @@ typedef struct {
                          faster; 2 + v = use shape v everywhere (0 <= v < 4, a test hook).
                          Every shape gives the same results bit for bit. */
   int32_t weights;    /* dh2_weights_mode, default DH2_WEIGHTS_HOUSEHOLDER */
+  int32_t quadrature; /* dh2_quadrature, default DH2_QUAD_DEFAULT */
 } dh2_options;
 
 typedef struct dh2_problem* dh2_handle;
@@ -306,6 +322,9 @@ typedef struct {
    * S_b (FP64 handles: the rows R S_b and R S_b^H of the Gram form with the
    * Frobenius norm, and the projection's C_tc S_b), so never stored. */
   double coupling_in_products;
+  /* DH2_QUAD_PAPER: touching triangle pairs integrated by the Sauter-Erichsen-
+   * Schwab rules (pairs of mirrored near-field blocks are copied, not counted). */
+  int64_t touching_pairs;
 } dh2_stats;
 
 dh2_status dh2_get_stats(dh2_handle h, dh2_stats* s);

@@ -105,6 +105,17 @@ QuadTab make_quad() {
       q.b16[k][2] = u[i] * u[j];
       q.w16[k] = 2.0 * wu[i] * wu[j] * u[i];
     }
+  // the paper's rule of order 3: 3 x 3 Gauss-Legendre, Duffy-collapsed
+  double u3[3], wu3[3];
+  gauss_legendre01(3, u3, wu3);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const int k = 3 * i + j;
+      q.b9[k][0] = 1.0 - u3[i];
+      q.b9[k][1] = u3[i] * (1.0 - u3[j]);
+      q.b9[k][2] = u3[i] * u3[j];
+      q.w9[k] = 2.0 * wu3[i] * wu3[j] * u3[i];
+    }
   return q;
 }
 
@@ -139,6 +150,7 @@ struct dh2_problem {
   int sketch_rank = 0;     // fixed predicted rank of every slot (0 = the predictor's)
   int autotune = 0;        // dh2_options.autotune
   int weights_mode = 0;    // dh2_options.weights
+  int quadrature = 0;      // dh2_options.quadrature
   int mv_var[4] = {0, 0, 0, 0};  // block-row pipeline shape: near / coupling, nrhs <= 16 / > 16
   int device = 0;
   size_t ws_bytes = 0;
@@ -486,7 +498,7 @@ struct Builder {
       }
     h.V_d = h.alloc<C64>(voff);
     std::vector<void*> tmp;
-    launch_leaf_basis<double>(upload_tmp(ld, tmp), (int64_t)ld.size(), ct, p.kappa, x7, w7, h.box_d,
+    launch_leaf_basis<double>(upload_tmp(ld, tmp), (int64_t)ld.size(), ct, p.kappa, x7, w7, nq_far, h.box_d,
                               h.dirs_d, h.V_d, h.stream);
     h.check_launch();
     // transfers
@@ -510,8 +522,9 @@ struct Builder {
     free_tmp(tmp);
   }
 
-  const double* x7 = nullptr;
+  const double* x7 = nullptr;   // far rule: points and weights per triangle (nq_far each)
   const double* w7 = nullptr;
+  int nq_far = 7;
 
   // ------------------------------------------------------------------
   // basis weights, bottom-up (eq. (basis_weights_def))
@@ -2156,6 +2169,91 @@ void tune_block_rows(dh2_problem& h) {
   else tune_block_rows_t<double>(h);
 }
 
+// Touching triangle pairs of the near field, for the paper's quadrature
+// (Section 5): every ordered pair (i, j) of triangles that share a vertex (kind
+// 1), an edge (2) or are identical (3), with the element offset of entry
+// (pos(i), pos(j)) in the near-field storage.  Pairs in mirrored blocks are
+// left out (the transposition copies them from the evaluated block).  The
+// pair is integrated with the triangle of lower index in the caller's
+// numbering first, its vertices ordered with the shared part first (a shared
+// vertex as A, a shared edge as A -> B of both, the rest in the caller's order).
+// rptr / rblk: the near blocks grouped by row cluster.
+std::vector<TouchDesc> touching_pairs(const Plan& p, const dh2_geometry& g, const std::vector<int64_t>& near_off,
+                                      const std::vector<uint8_t>& mirrored, const std::vector<int64_t>& rptr,
+                                      const std::vector<int64_t>& rblk) {
+  const int64_t n = p.n, nc = (int64_t)p.cl.size(), nv = g.n_vertices;
+  const int32_t* T = g.triangles;
+  std::vector<int64_t> pos(n), leaf_of(n, -1);
+  for (int64_t q = 0; q < n; ++q) pos[p.perm[q]] = q;
+  for (int64_t c = 0; c < nc; ++c)
+    if (p.cl[c].leaf())
+      for (int64_t q = p.cl[c].first; q < p.cl[c].first + p.cl[c].size; ++q) leaf_of[q] = c;
+  // each row cluster's blocks by the first position of their column cluster
+  std::vector<int64_t> byfirst(rblk);
+  auto col_first = [&](int64_t b) { return p.cl[p.near[b].s].first; };
+  for (int64_t t = 0; t < nc; ++t)
+    std::sort(byfirst.begin() + rptr[t], byfirst.begin() + rptr[t + 1],
+              [&](int64_t a, int64_t b) { return col_first(a) < col_first(b); });
+  std::vector<int64_t> vptr(nv + 1, 0), vtri(3 * n);
+  for (int64_t i = 0; i < 3 * n; ++i) ++vptr[T[i] + 1];
+  for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+  {
+    std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) vtri[fill[T[3 * i + a]]++] = i;
+  }
+  std::vector<TouchDesc> out;
+  out.reserve((size_t)n * 16);
+  std::vector<std::pair<int64_t, int>> cand;
+  for (int64_t i = 0; i < n; ++i) {
+    cand.clear();
+    for (int a = 0; a < 3; ++a) {
+      const int32_t v = T[3 * i + a];
+      for (int64_t e = vptr[v]; e < vptr[v + 1]; ++e) {
+        const int64_t j = vtri[e];
+        bool found = false;
+        for (auto& c : cand)
+          if (c.first == j) { ++c.second; found = true; break; }
+        if (!found) cand.push_back({j, 1});
+      }
+    }
+    const int64_t pi = pos[i];
+    for (const auto& c : cand) {
+      const int64_t j = c.first, pj = pos[j];
+      int64_t b = -1;
+      for (int64_t a = leaf_of[pi]; a >= 0 && b < 0; a = p.cl[a].parent) {
+        const auto lo = byfirst.begin() + rptr[a], hi = byfirst.begin() + rptr[a + 1];
+        auto it = std::upper_bound(lo, hi, pj, [&](int64_t v, int64_t blk) { return v < col_first(blk); });
+        if (it == lo) continue;
+        const int64_t cand_b = *(it - 1);
+        const Cluster& sc = p.cl[p.near[cand_b].s];
+        if (pj < sc.first + sc.size) b = cand_b;
+      }
+      if (b < 0) throw Fail{DH2_ERR_GEOMETRY, "touching triangles outside the near field"};
+      if (mirrored[b]) continue;
+      const Cluster& tc = p.cl[p.near[b].t];
+      const Cluster& sc = p.cl[p.near[b].s];
+      TouchDesc d{};
+      d.off = near_off[b] + (pi - tc.first) + (pj - sc.first) * tc.size;
+      d.kind = c.second;
+      const int32_t* Ta = T + 3 * std::min(i, j);
+      const int32_t* Tb = T + 3 * std::max(i, j);
+      auto in_b = [&](int32_t v) { return v == Tb[0] || v == Tb[1] || v == Tb[2]; };
+      auto in_a = [&](int32_t v) { return v == Ta[0] || v == Ta[1] || v == Ta[2]; };
+      int na = 0, nb = 0;
+      for (int a = 0; a < 3; ++a)   // shared vertices first, in Ta's order
+        if (in_b(Ta[a])) d.va[na++] = d.vb[nb++] = Ta[a];
+      if (na != d.kind) throw Fail{DH2_ERR_GEOMETRY, "repeated vertex in a triangle"};
+      for (int a = 0; a < 3; ++a) {
+        if (!in_b(Ta[a])) d.va[na++] = Ta[a];
+        if (!in_a(Tb[a])) d.vb[nb++] = Tb[a];
+      }
+      out.push_back(d);
+    }
+  }
+  return out;
+}
+
 void build_all(dh2_problem& h, const dh2_geometry& g) {
   const double t_start = now_ms();
   Plan& p = h.plan;
@@ -2185,9 +2283,12 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   double* w7 = h.alloc<double>((size_t)n * 7);
   double* x16 = h.alloc<double>((size_t)n * 48);
   double* w16 = h.alloc<double>((size_t)n * 16);
+  double* x9 = h.alloc<double>((size_t)n * 27);
+  double* w9 = h.alloc<double>((size_t)n * 9);
   double* selfl = h.alloc<double>((size_t)n);
-  launch_tri_data(n, Vd, Td, h.perm_d, make_quad(), x7, w7, x16, w16, selfl, h.stream);
+  launch_tri_data(n, Vd, Td, h.perm_d, make_quad(), x7, w7, x16, w16, x9, w9, selfl, h.stream);
   h.check_launch();
+  const bool paper_quad = h.quadrature == DH2_QUAD_PAPER;
   std::vector<double> box(6 * nc);
   for (int64_t t = 0; t < nc; ++t)
     for (int d = 0; d < 3; ++d) {
@@ -2252,11 +2353,33 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
     const int es = h.precision != DH2_FP64 ? (int)sizeof(z32) : (int)sizeof(C64);
     h.near_d = h.alloc<char>((size_t)std::max<int64_t>(off, 1) * es);
     NearDesc* ndd = h.upload(eval);
+    const double* xq = paper_quad ? x9 : x16;
+    const double* wq = paper_quad ? w9 : w16;
+    const int nq = paper_quad ? 9 : 16;
     if (h.precision != DH2_FP64)
-      launch_near<float>(ndd, (int64_t)eval.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+      launch_near<float>(ndd, (int64_t)eval.size(), p.kappa, xq, wq, selfl, h.near_d, nq, h.stream);
     else
-      launch_near<double>(ndd, (int64_t)eval.size(), p.kappa, x16, w16, selfl, h.near_d, h.stream);
+      launch_near<double>(ndd, (int64_t)eval.size(), p.kappa, xq, wq, selfl, h.near_d, nq, h.stream);
     h.check_launch();
+    // the paper's quadrature: touching pairs of the evaluated blocks take the
+    // Sauter-Erichsen-Schwab rules (mirrors get them by the transposition below)
+    TouchDesc* tdd = nullptr;
+    if (paper_quad) {
+      std::vector<uint8_t> mirrored(nnear, 0);
+      for (const auto& mb : mirrors) mirrored[mb.first] = 1;
+      const std::vector<TouchDesc> td = touching_pairs(p, g, h.near_off, mirrored, rptr, rblk);
+      h.stats.touching_pairs = (int64_t)td.size();
+      if (!td.empty()) {
+        tdd = h.upload(td);
+        SesTab tab{};
+        gauss_legendre01(kSesOrder, tab.g, tab.gw);
+        if (h.precision != DH2_FP64)
+          launch_touch<float>(tdd, (int64_t)td.size(), Vd, tab, p.kappa, h.near_d, h.stream);
+        else
+          launch_touch<double>(tdd, (int64_t)td.size(), Vd, tab, p.kappa, h.near_d, h.stream);
+        h.check_launch();
+      }
+    }
     std::vector<CopyDesc> cp;
     cp.reserve(mirrors.size());
     for (const auto& mb : mirrors) {
@@ -2273,6 +2396,7 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
     h.sync();
     h.release(ndd);
     if (cpd) h.release(cpd);
+    if (tdd) h.release(tdd);
   }
   h.stats.ms_near = now_ms() - t0;
 
@@ -2282,8 +2406,9 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   bd.cnt_d = h.alloc<int32_t>((size_t)std::max<int64_t>(bd.ns, 1));
 
   t0 = now_ms();
-  bd.x7 = x7;
-  bd.w7 = w7;
+  bd.x7 = paper_quad ? x9 : x7;
+  bd.w7 = paper_quad ? w9 : w7;
+  bd.nq_far = paper_quad ? 9 : 7;
   bd.interpolation();
   h.sync();
   h.stats.ms_interp = now_ms() - t0;
@@ -2333,6 +2458,8 @@ void build_all(dh2_problem& h, const dh2_geometry& g) {
   h.release(w7);
   h.release(x16);
   h.release(w16);
+  h.release(x9);
+  h.release(w9);
   h.release(selfl);
   h.release(Vd);
   h.release(Td);
@@ -2446,6 +2573,10 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     g_err = "sketch_rank must be >= 0";
     return DH2_ERR_ARG;
   }
+  if (opt.quadrature != DH2_QUAD_DEFAULT && opt.quadrature != DH2_QUAD_PAPER) {
+    g_err = "quadrature must be DH2_QUAD_DEFAULT or DH2_QUAD_PAPER";
+    return DH2_ERR_ARG;
+  }
   if (opt.weights != DH2_WEIGHTS_HOUSEHOLDER && opt.weights != DH2_WEIGHTS_GRAM) {
     g_err = "unknown weights mode";
     return DH2_ERR_ARG;
@@ -2480,6 +2611,7 @@ dh2_status dh2_build_ex(const dh2_geometry* geometry, double kappa, int order, d
     h->sketch_rank = opt.sketch_rank;
     h->autotune = opt.autotune;
     h->weights_mode = opt.weights;
+    h->quadrature = opt.quadrature;
     h->plan.kappa = kappa;
     h->plan.order = order;
     h->plan.eta = eta;

@@ -16,13 +16,14 @@ namespace dh2 {
 // ---------------------------------------------------------------------------
 // Per-triangle data (Section 5: piecewise-constant basis on flat triangles).
 // Triangle at cluster position p is user triangle perm[p].  Outputs in
-// cluster order: 7-point and 16-point quadrature points / weights and the
+// cluster order: 7-, 16- and 9-point quadrature points / weights and the
 // closed-form Laplace self integral int_T int_T 1/|x-y| divided by 4 pi:
 //   (4 A^2 / 3) sum_e (1/l_e) log(L / (L - 2 l_e)),  L = perimeter.
 __global__ void k_tri_data(int64_t n, const double* __restrict__ V, const int32_t* __restrict__ T,
                            const int64_t* __restrict__ perm, QuadTab qt, double* __restrict__ x7,
                            double* __restrict__ w7, double* __restrict__ x16,
-                           double* __restrict__ w16, double* __restrict__ self_lap) {
+                           double* __restrict__ w16, double* __restrict__ x9, double* __restrict__ w9,
+                           double* __restrict__ self_lap) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int64_t u = perm[p];
@@ -49,6 +50,11 @@ __global__ void k_tri_data(int64_t n, const double* __restrict__ V, const int32_
           qt.b16[q][0] * P[0][d] + qt.b16[q][1] * P[1][d] + qt.b16[q][2] * P[2][d];
     w16[p * 16 + q] = area * qt.w16[q];
   }
+  for (int q = 0; q < 9; ++q) {
+    for (int d = 0; d < 3; ++d)
+      x9[(p * 9 + q) * 3 + d] = qt.b9[q][0] * P[0][d] + qt.b9[q][1] * P[1][d] + qt.b9[q][2] * P[2][d];
+    w9[p * 9 + q] = area * qt.w9[q];
+  }
   double l[3];
   for (int e = 0; e < 3; ++e) {
     const int a = (e + 1) % 3, b = (e + 2) % 3;
@@ -67,32 +73,34 @@ __global__ void k_tri_data(int64_t n, const double* __restrict__ V, const int32_
 //   i != j: sum_{p,q<16} w_i,p w_j,q g(x_i,p, y_j,q),  g = exp(i kappa r) / (4 pi r)
 //   i == j: Laplace closed form + sum w w rho(r), rho(r) = (exp(i kappa r) - 1) / r,
 //           rho(0) = i kappa (singularity subtraction).
-// One workgroup per block, one thread per entry; the 16-point data of the row
+// One workgroup per block, one thread per entry; the quadrature data of the row
 // triangles is read through the caches, that of the column triangles from LDS.
-// Output column-major, leading dimension #t.
-template <typename R>
+// Output column-major, leading dimension #t.  NQ = 16: the rules above; NQ =
+// 9: the paper's rule of order 3 on both triangles for every pair of distinct
+// triangles, the diagonal left 0 (touching pairs take k_touch afterwards).
+template <typename R, int NQ>
 __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ blocks, double kappa,
-                                              const double* __restrict__ x16,
-                                              const double* __restrict__ w16,
+                                              const double* __restrict__ xq,
+                                              const double* __restrict__ wq,
                                               const double* __restrict__ self_lap,
                                               cpx<R>* __restrict__ out) {
   const NearDesc d = blocks[blockIdx.x];
   const R kap = (R)kappa;
   const R inv4pi = (R)(0.25 / M_PI);
-  // the 16 points and weights of up to 64 column triangles, staged in LDS per
+  // the NQ points and weights of up to 64 column triangles, staged in LDS per
   // chunk of columns: every evaluation reads them from there (the lanes of a
   // wave mostly share one column, so the reads are broadcasts)
-  __shared__ double cp[64 * 16][4];
+  __shared__ double cp[64 * NQ][4];
   for (int c0 = 0; c0 < d.nc; c0 += 64) {
     const int cn = min(64, d.nc - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < cn * 16; e += blockDim.x) {
-      const int64_t gj = d.col0 + c0 + e / 16;
-      const int q = e % 16;
-      cp[e][0] = x16[gj * 48 + 3 * q];
-      cp[e][1] = x16[gj * 48 + 3 * q + 1];
-      cp[e][2] = x16[gj * 48 + 3 * q + 2];
-      cp[e][3] = w16[gj * 16 + q];
+    for (int e = threadIdx.x; e < cn * NQ; e += blockDim.x) {
+      const int64_t gj = d.col0 + c0 + e / NQ;
+      const int q = e % NQ;
+      cp[e][0] = xq[gj * 3 * NQ + 3 * q];
+      cp[e][1] = xq[gj * 3 * NQ + 3 * q + 1];
+      cp[e][2] = xq[gj * 3 * NQ + 3 * q + 2];
+      cp[e][3] = wq[gj * NQ + q];
     }
     __syncthreads();
     const int64_t total = (int64_t)d.nr * cn;
@@ -100,15 +108,15 @@ __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ block
       const int i = (int)(e % d.nr);
       const int jj = (int)(e / d.nr);
       const int64_t gi = d.row0 + i, gj = d.col0 + c0 + jj;
-      const double* xi = x16 + gi * 48;
-      const double* wi = w16 + gi * 16;
-      const double(*pj)[4] = cp + jj * 16;
+      const double* xi = xq + gi * 3 * NQ;
+      const double* wi = wq + gi * NQ;
+      const double(*pj)[4] = cp + jj * NQ;
       R sre = 0, sim = 0;
       if (gi != gj) {
-        for (int p = 0; p < 16; ++p) {
+        for (int p = 0; p < NQ; ++p) {
           const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
           R accr = 0, acci = 0;
-          for (int q = 0; q < 16; ++q) {
+          for (int q = 0; q < NQ; ++q) {
             const R dx = (R)(ax - pj[q][0]), dy = (R)(ay - pj[q][1]), dz = (R)(az - pj[q][2]);
             const R r2 = dx * dx + dy * dy + dz * dz;
             const R ir = rsqrt_r(r2);
@@ -124,10 +132,10 @@ __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ block
         }
         sre *= inv4pi;
         sim *= inv4pi;
-      } else {
-        for (int p = 0; p < 16; ++p) {
+      } else if (NQ == 16) {
+        for (int p = 0; p < NQ; ++p) {
           const double ax = xi[3 * p], ay = xi[3 * p + 1], az = xi[3 * p + 2];
-          for (int q = 0; q < 16; ++q) {
+          for (int q = 0; q < NQ; ++q) {
             const R w = (R)(wi[p] * pj[q][3]);
             const R dx = (R)(ax - pj[q][0]), dy = (R)(ay - pj[q][1]), dz = (R)(az - pj[q][2]);
             const R r = sqrt_r(dx * dx + dy * dy + dz * dz);
@@ -151,12 +159,109 @@ __global__ void __launch_bounds__(256) k_near(const NearDesc* __restrict__ block
 }
 
 // ---------------------------------------------------------------------------
-// Leaf bases (Section 2): V_tc[i,nu] = sum_{q<7} w_q exp(i kappa <x_q,c>) L_{t,nu}(x_q)
-// for the triangles i of leaf t.  Output #t x k, column-major.
+// Touching pairs with the paper's quadrature (Section 5): Sauter-Erichsen-
+// Schwab rules of order 5 for triangles that share a vertex (kind 1), an edge
+// (2) or are identical (3).  With the reference triangle {0 <= s2 <= s1 <= 1}
+// and chi(s) = A + s1 (B - A) + s2 (C - B) for the ordered vertices of each
+// triangle (the shared part first), the entry is
+//   (4 |Ta| |Tb| / (4 pi)) sum over the regions and the 5^4 tensor Gauss
+//   points (xi, e1, e2, e3) of w * J * exp(i kappa r) / r,  r = |chi_a(s) - chi_b(t)|,
+// where each region maps the cube onto part of the pair of reference
+// triangles with Jacobian J, which vanishes where x = y (identical: six
+// regions, J = xi^3 e1^2 e2; common edge: five, J = xi^3 e1^2 for the first
+// and xi^3 e1^2 e2 for the others; common vertex: two, J = xi^3 e2).  One
+// workgroup per pair; the entry overwrites the near-field value of the pair.
+template <typename R>
+__global__ void __launch_bounds__(256) k_touch(const TouchDesc* __restrict__ dd, const double* __restrict__ V,
+                                               SesTab tab, double kappa, cpx<R>* __restrict__ out) {
+  const TouchDesc d = dd[blockIdx.x];
+  double A[3], U[3], W[3], A2[3], U2[3], W2[3];
+  for (int k = 0; k < 3; ++k) {
+    const double a = V[3 * (int64_t)d.va[0] + k], b = V[3 * (int64_t)d.va[1] + k], c = V[3 * (int64_t)d.va[2] + k];
+    A[k] = a;
+    U[k] = b - a;
+    W[k] = c - b;
+    const double a2 = V[3 * (int64_t)d.vb[0] + k], b2 = V[3 * (int64_t)d.vb[1] + k],
+                 c2 = V[3 * (int64_t)d.vb[2] + k];
+    A2[k] = a2;
+    U2[k] = b2 - a2;
+    W2[k] = c2 - b2;
+  }
+  constexpr int NP = kSesOrder * kSesOrder * kSesOrder * kSesOrder;
+  const int nreg = d.kind == 3 ? 6 : (d.kind == 2 ? 5 : 2);
+  double sre = 0.0, sim = 0.0;
+  for (int e = threadIdx.x; e < nreg * NP; e += blockDim.x) {
+    const int reg = e / NP, q = e % NP;
+    const int i0 = q % kSesOrder, i1 = (q / kSesOrder) % kSesOrder, i2 = (q / (kSesOrder * kSesOrder)) % kSesOrder,
+              i3 = q / (kSesOrder * kSesOrder * kSesOrder);
+    const double xi = tab.g[i0], e1 = tab.g[i1], e2 = tab.g[i2], e3 = tab.g[i3];
+    double w = tab.gw[i0] * tab.gw[i1] * tab.gw[i2] * tab.gw[i3];
+    double s1, s2, t1, t2;
+    if (d.kind == 3) {
+      w *= xi * xi * xi * e1 * e1 * e2;
+      switch (reg) {
+        case 0: s1 = xi; s2 = xi * (1 - e1 + e1 * e2); t1 = xi * (1 - e1 * e2 * e3); t2 = xi * (1 - e1); break;
+        case 1: s1 = xi * (1 - e1 * e2 * e3); s2 = xi * (1 - e1); t1 = xi; t2 = xi * (1 - e1 + e1 * e2); break;
+        case 2: s1 = xi; s2 = xi * e1 * (1 - e2 + e2 * e3); t1 = xi * (1 - e1 * e2); t2 = xi * e1 * (1 - e2); break;
+        case 3: s1 = xi * (1 - e1 * e2); s2 = xi * e1 * (1 - e2); t1 = xi; t2 = xi * e1 * (1 - e2 + e2 * e3); break;
+        case 4: s1 = xi * (1 - e1 * e2 * e3); s2 = xi * e1 * (1 - e2 * e3); t1 = xi; t2 = xi * e1 * (1 - e2); break;
+        default: s1 = xi; s2 = xi * e1 * (1 - e2); t1 = xi * (1 - e1 * e2 * e3); t2 = xi * e1 * (1 - e2 * e3); break;
+      }
+    } else if (d.kind == 2) {
+      w *= xi * xi * xi * e1 * e1 * (reg == 0 ? 1.0 : e2);
+      switch (reg) {
+        case 0: s1 = xi; s2 = xi * e1 * e3; t1 = xi * (1 - e1 * e2); t2 = xi * e1 * (1 - e2); break;
+        case 1: s1 = xi; s2 = xi * e1; t1 = xi * (1 - e1 * e2 * e3); t2 = xi * e1 * e2 * (1 - e3); break;
+        case 2: s1 = xi * (1 - e1 * e2); s2 = xi * e1 * (1 - e2); t1 = xi; t2 = xi * e1 * e2 * e3; break;
+        case 3: s1 = xi * (1 - e1 * e2 * e3); s2 = xi * e1 * e2 * (1 - e3); t1 = xi; t2 = xi * e1; break;
+        default: s1 = xi * (1 - e1 * e2 * e3); s2 = xi * e1 * (1 - e2 * e3); t1 = xi; t2 = xi * e1 * e2; break;
+      }
+    } else {
+      w *= xi * xi * xi * e2;
+      if (reg == 0) { s1 = xi; s2 = xi * e1; t1 = xi * e2; t2 = xi * e2 * e3; }
+      else { s1 = xi * e2; s2 = xi * e2 * e3; t1 = xi; t2 = xi * e1; }
+    }
+    double r2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double dx = (A[k] + s1 * U[k] + s2 * W[k]) - (A2[k] + t1 * U2[k] + t2 * W2[k]);
+      r2 += dx * dx;
+    }
+    const double ir = rsqrt_r(r2);
+    double sn, cs;
+    sincos_fast(kappa * (r2 * ir), &sn, &cs);
+    sre += w * ir * cs;
+    sim += w * ir * sn;
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = sre;
+  red[1][threadIdx.x] = sim;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    auto cross2 = [](const double* u, const double* v) {
+      const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+      return sqrt(cx * cx + cy * cy + cz * cz);
+    };
+    // 4 |Ta| |Tb| / (4 pi) = |2 Ta| |2 Tb| / (4 pi)
+    const double scale = cross2(U, W) * cross2(U2, W2) * (0.25 / M_PI);
+    out[d.off] = cpx<R>{(R)(red[0][0] * scale), (R)(red[1][0] * scale)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf bases (Section 2): V_tc[i,nu] = sum_{q<nq} w_q exp(i kappa <x_q,c>) L_{t,nu}(x_q)
+// for the triangles i of leaf t, with the far rule (7 points, or the paper's 9).
+// Output #t x k, column-major.
 template <typename R>
 __global__ void __launch_bounds__(256) k_leaf_basis(const LeafDesc* __restrict__ dd, ChebTab ct,
-                                                    double kappa, const double* __restrict__ x7,
-                                                    const double* __restrict__ w7,
+                                                    double kappa, const double* __restrict__ xf,
+                                                    const double* __restrict__ wf, int nq,
                                                     const double* __restrict__ box,
                                                     const double* __restrict__ dirs,
                                                     cpx<R>* __restrict__ out) {
@@ -173,8 +278,8 @@ __global__ void __launch_bounds__(256) k_leaf_basis(const LeafDesc* __restrict__
     const int jx = nu % m, jy = (nu / m) % m, jz = nu / (m * m);
     const int64_t g = d.row0 + i;
     double sre = 0, sim = 0;
-    for (int q = 0; q < 7; ++q) {
-      const double* x = x7 + (g * 7 + q) * 3;
+    for (int q = 0; q < nq; ++q) {
+      const double* x = xf + (g * nq + q) * 3;
       double Lx[kMaxOrder], Ly[kMaxOrder], Lz[kMaxOrder];
       lagrange<double>(ct, to_ref(x[0], lo[0], hi[0]), Lx);
       lagrange<double>(ct, to_ref(x[1], lo[1], hi[1]), Ly);
@@ -182,7 +287,7 @@ __global__ void __launch_bounds__(256) k_leaf_basis(const LeafDesc* __restrict__
       const double L = Lx[jx] * Ly[jy] * Lz[jz];
       double sn, cs;
       sincos_fast(kappa * (x[0] * c[0] + x[1] * c[1] + x[2] * c[2]), &sn, &cs);
-      const double f = w7[g * 7 + q] * L;
+      const double f = wf[g * nq + q] * L;
       sre += f * cs;
       sim += f * sn;
     }
@@ -1552,36 +1657,54 @@ __global__ void __launch_bounds__(256) k_narrow_list(const NarrowDesc* __restric
 // launch wrappers
 void launch_tri_data(int64_t n, const double* V, const int32_t* T, const int64_t* perm,
                      const QuadTab& qt, double* x7, double* w7, double* x16, double* w16,
-                     double* self_lap, hipStream_t st) {
+                     double* x9, double* w9, double* self_lap, hipStream_t st) {
   hipLaunchKernelGGL(k_tri_data, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, V, T,
-                     perm, qt, x7, w7, x16, w16, self_lap);
+                     perm, qt, x7, w7, x16, w16, x9, w9, self_lap);
 }
 
 template <typename R>
-void launch_near(const NearDesc* d, int64_t nb, double kappa, const double* x16, const double* w16,
-                 const double* self_lap, void* out, hipStream_t st) {
+void launch_near(const NearDesc* d, int64_t nb, double kappa, const double* xq, const double* wq,
+                 const double* self_lap, void* out, int nq, hipStream_t st) {
   for (int64_t b0 = 0; b0 < nb; b0 += 1 << 30) {
     const int64_t cnt = std::min<int64_t>(nb - b0, 1 << 30);
-    hipLaunchKernelGGL(k_near<R>, dim3((unsigned)cnt), dim3(256), 0, st, d + b0, kappa, x16, w16,
-                       self_lap, (cpx<R>*)out);
+    if (nq == 9)
+      hipLaunchKernelGGL((k_near<R, 9>), dim3((unsigned)cnt), dim3(256), 0, st, d + b0, kappa, xq, wq,
+                         self_lap, (cpx<R>*)out);
+    else
+      hipLaunchKernelGGL((k_near<R, 16>), dim3((unsigned)cnt), dim3(256), 0, st, d + b0, kappa, xq, wq,
+                         self_lap, (cpx<R>*)out);
   }
 }
 template void launch_near<double>(const NearDesc*, int64_t, double, const double*, const double*,
-                                  const double*, void*, hipStream_t);
+                                  const double*, void*, int, hipStream_t);
 template void launch_near<float>(const NearDesc*, int64_t, double, const double*, const double*,
-                                 const double*, void*, hipStream_t);
+                                 const double*, void*, int, hipStream_t);
 
 template <typename R>
 void launch_leaf_basis(const LeafDesc* d, int64_t nb, const ChebTab& ct, double kappa,
-                       const double* x7, const double* w7, const double* box, const double* dirs,
+                       const double* xf, const double* wf, int nq, const double* box, const double* dirs,
                        void* out, hipStream_t st) {
   if (nb > 0)
-    hipLaunchKernelGGL(k_leaf_basis<R>, dim3((unsigned)nb), dim3(256), 0, st, d, ct, kappa, x7, w7,
+    hipLaunchKernelGGL(k_leaf_basis<R>, dim3((unsigned)nb), dim3(256), 0, st, d, ct, kappa, xf, wf, nq,
                        box, dirs, (cpx<R>*)out);
 }
 template void launch_leaf_basis<double>(const LeafDesc*, int64_t, const ChebTab&, double,
-                                        const double*, const double*, const double*,
+                                        const double*, const double*, int, const double*,
                                         const double*, void*, hipStream_t);
+
+template <typename R>
+void launch_touch(const TouchDesc* d, int64_t nt, const double* V, const SesTab& tab, double kappa,
+                  void* out, hipStream_t st) {
+  for (int64_t b0 = 0; b0 < nt; b0 += 1 << 30) {
+    const int64_t cnt = std::min<int64_t>(nt - b0, 1 << 30);
+    hipLaunchKernelGGL(k_touch<R>, dim3((unsigned)cnt), dim3(256), 0, st, d + b0, V, tab, kappa,
+                       (cpx<R>*)out);
+  }
+}
+template void launch_touch<double>(const TouchDesc*, int64_t, const double*, const SesTab&, double, void*,
+                                   hipStream_t);
+template void launch_touch<float>(const TouchDesc*, int64_t, const double*, const SesTab&, double, void*,
+                                  hipStream_t);
 
 template <typename R>
 void launch_transfer(const TransDesc* d, int64_t nb, const ChebTab& ct, double kappa,

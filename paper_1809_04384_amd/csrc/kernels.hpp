@@ -15,6 +15,25 @@ struct QuadTab {
   double w7[7];
   double b16[16][3];
   double w16[16];
+  double b9[9][3];    // the paper's rule of order 3 (Duffy-collapsed 3 x 3 Gauss)
+  double w9[9];
+};
+
+// Sauter-Erichsen-Schwab rules of the paper's quadrature: the Gauss-Legendre
+// rule on [0, 1] used in each of the four cube coordinates.
+constexpr int kSesOrder = 5;
+struct SesTab {
+  double g[kSesOrder], gw[kSesOrder];
+};
+
+// One touching triangle pair (Section 5): the entry at element offset off of
+// the near-field storage; vertex indices of the two triangles in the order
+// that puts the shared part first (a shared vertex as A, a shared edge as
+// A -> B of both); kind 1 common vertex, 2 common edge, 3 identical.
+struct TouchDesc {
+  int64_t off;
+  int32_t va[3], vb[3];
+  int32_t kind, pad;
 };
 
 struct NearDesc {     // inadmissible leaf t x s
@@ -171,13 +190,21 @@ struct CopyDesc {
 
 void launch_tri_data(int64_t n, const double* V, const int32_t* T, const int64_t* perm,
                      const QuadTab& qt, double* x7, double* w7, double* x16, double* w16,
-                     double* self_lap, hipStream_t st);
+                     double* x9, double* w9, double* self_lap, hipStream_t st);
+// nq = 16: Q16 x Q16 and the closed-form self term; nq = 9: the paper's 9 x 9
+// rule for every pair of distinct triangles (touching pairs are overwritten by
+// launch_touch, the diagonal is left 0 for it)
 template <typename R>
-void launch_near(const NearDesc* d, int64_t nb, double kappa, const double* x16, const double* w16,
-                 const double* self_lap, void* out, hipStream_t st);
+void launch_near(const NearDesc* d, int64_t nb, double kappa, const double* xq, const double* wq,
+                 const double* self_lap, void* out, int nq, hipStream_t st);
+// Sauter-Erichsen-Schwab entries of touching pairs, written over the near field
+template <typename R>
+void launch_touch(const TouchDesc* d, int64_t nt, const double* V, const SesTab& tab, double kappa,
+                  void* out, hipStream_t st);
+// far rule of nq points per triangle (7, or the paper's 9)
 template <typename R>
 void launch_leaf_basis(const LeafDesc* d, int64_t nb, const ChebTab& ct, double kappa,
-                       const double* x7, const double* w7, const double* box, const double* dirs,
+                       const double* xf, const double* wf, int nq, const double* box, const double* dirs,
                        void* out, hipStream_t st);
 template <typename R>
 void launch_transfer(const TransDesc* d, int64_t nb, const ChebTab& ct, double kappa,

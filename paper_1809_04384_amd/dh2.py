@@ -18,6 +18,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_GEOMETRY", 3: "ERR_OOM", 4: "ERR_DEVICE
 FP64, FP32, BF16X3 = 0, 1, 2
 RANKS_EXACT, RANKS_LEARNED = 0, 1
 WEIGHTS_HOUSEHOLDER, WEIGHTS_GRAM = 0, 1
+QUAD_DEFAULT, QUAD_PAPER = 0, 1
 NORM_FROBENIUS, NORM_SPECTRAL = 0, 1
 INSPECT = {"near": 1, "leaf_basis": 2, "transfer": 3, "rank_row": 4, "rank_col": 5,
            "sigma_row": 6, "sigma_col": 7, "omega": 8, "basis_weight": 9,
@@ -46,7 +47,7 @@ class Options(ctypes.Structure):
                 ("max_nrhs", ctypes.c_int32), ("norm", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace_gb", ctypes.c_double),
                 ("rank_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("weights", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("weights", ctypes.c_int32), ("quadrature", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -72,7 +73,8 @@ class Stats(ctypes.Structure):
                 ("coupling_regeneration", ctypes.c_double), ("sketch_slots", ctypes.c_int64),
                 ("sketch_fallbacks", ctypes.c_int64), ("ms_rank_predict", ctypes.c_double),
                 ("mv_variant", ctypes.c_int32 * 4), ("ms_autotune", ctypes.c_double),
-                ("weights_gram", ctypes.c_int32), ("coupling_in_products", ctypes.c_double)]
+                ("weights_gram", ctypes.c_int32), ("coupling_in_products", ctypes.c_double),
+                ("touching_pairs", ctypes.c_int64)]
 
 
 class PlanSizes(ctypes.Structure):
@@ -185,7 +187,7 @@ class Handle:
 
     def __init__(self, V, T, kappa, order, eta, leafsize, tol, eta1=10.0, precision=FP64,
                  max_nrhs=16, stream=None, workspace_gb=0.0, norm=NORM_FROBENIUS, rank_mode=RANKS_EXACT,
-                 sketch_rank=0, autotune=0, weights=0):
+                 sketch_rank=0, autotune=0, weights=0, quadrature=QUAD_DEFAULT):
         lib = load()
         g, keep = _geometry(V, T)
         opt = Options()
@@ -200,6 +202,7 @@ class Handle:
         opt.sketch_rank = sketch_rank
         opt.autotune = autotune
         opt.weights = weights
+        opt.quadrature = quadrature
         self.precision = precision
         self.max_nrhs = max_nrhs
         self.n = int(np.asarray(T).shape[0])

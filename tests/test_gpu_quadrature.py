@@ -1,0 +1,142 @@
+"""GPU parity of the paper's quadrature (dh2_options.quadrature = PAPER,
+Section 5: Sauter-Erichsen-Schwab rules of order 5 for touching triangle
+pairs, Duffy-Gauss of order 3 for all other pairs and the leaf bases) against
+the FP64 oracle built with the same rules (oracle/ses.py, pinned in
+tests/test_oracle_ses.py).
+
+Bounds: near-field entries and leaf bases are the same finite sums in a
+different order (1e-12 of the block's largest entry: the touching rules add
+up to 3750 terms); the matvec of the whole compressed matrix within 1e-10,
+as for the default rules."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.dh2 import OracleDH2
+from oracle import ses
+from tests.gpu_common import say, build_handle, rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["dir512", "sphere2k", "cube768"]
+_oracles = {}
+
+
+def paper_oracle(name):
+    if name not in _oracles:
+        w = synth.WORKLOADS[name]
+        V, T = synth.make_mesh(w)
+        _oracles[name] = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1,
+                                   quadrature="paper")
+    return _oracles[name]
+
+
+def _touching_count(o):
+    """Touching ordered pairs in the evaluated near-field blocks (the library
+    copies the mirrored blocks instead): every pair inside a block with t <= s
+    or without a mirror."""
+    st = o.st
+    T = o.tri["T"]
+    where = {(t, s) for (t, s) in st.near}
+    cnt = 0
+    for (t, s) in st.near:
+        if t > s and (s, t) in where:
+            continue
+        rows, cols = st.idx(t), set(int(j) for j in st.idx(s))
+        for i in rows:
+            cand = set()
+            for v in T[int(i)]:
+                cand.update(o.tri["vert_tris"][int(v)])
+            cnt += len(cand & cols)
+    return cnt
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_paper_quadrature_matches_oracle(name):
+    import torch
+    from paper_1809_04384_amd import dh2
+    o = paper_oracle(name)
+    h, slots = build_handle(name, quadrature=dh2.QUAD_PAPER)
+    try:
+        st = h.stats()
+        say("[gpu] %s paper quadrature: %d touching pairs" % (name, st["touching_pairs"]))
+        assert st["touching_pairs"] == _touching_count(o)
+        nb = len(o.st.near)
+        for b in range(nb):
+            N = h.inspect("near", b)
+            ref = o.N[b]
+            assert np.max(np.abs(N - ref)) <= 1e-12 * np.max(np.abs(ref)), b
+        for q, (t, c, flags) in enumerate(slots.tolist()):
+            if o.st.is_leaf(t) and q % 5 == 0:
+                V = h.inspect("leaf_basis", q)
+                ref = o.Vleaf[(t, c)]
+                assert np.max(np.abs(V - ref)) <= 1e-13 * max(np.max(np.abs(ref)), 1e-300)
+        X = synth.complex_gaussian(o.n, 3, seed=11)
+        Xd = torch.from_numpy(X).to("cuda:0")
+        Yd = torch.empty_like(Xd)
+        h.matvec(Xd, Yd)
+        torch.cuda.synchronize()
+        err = rel(Yd.cpu().numpy(), o.matvec(X.T).T)
+        say("[gpu] %s paper quadrature matvec rel err vs oracle %.3e" % (name, err))
+        assert err <= 1e-10
+    finally:
+        h.free()
+
+
+def test_paper_quadrature_fp32_and_gram():
+    """FP32 near field (the touching rules evaluated in FP64, stored in
+    complex64) and the Gram form on top of the paper's rules."""
+    import torch
+    from paper_1809_04384_amd import dh2
+    name = "sphere2k"
+    o = paper_oracle(name)
+    X = synth.complex_gaussian(o.n, 2, seed=12)
+    Yo = o.matvec(X.T).T
+    for kw, tol in ((dict(precision=dh2.FP32), 1e-4), (dict(weights=dh2.WEIGHTS_GRAM), 1e-9)):
+        h, _ = build_handle(name, quadrature=dh2.QUAD_PAPER, **kw)
+        try:
+            dt = torch.complex64 if kw.get("precision") == dh2.FP32 else torch.complex128
+            Xd = torch.from_numpy(X).to(dt).to("cuda:0")
+            Yd = torch.empty_like(Xd)
+            h.matvec(Xd, Yd)
+            torch.cuda.synchronize()
+            err = rel(Yd.cpu().numpy().astype(np.complex128), Yo)
+            say("[gpu] %s paper quadrature %s: rel err vs oracle %.3e" % (name, kw, err))
+            assert err <= tol
+        finally:
+            h.free()
+
+
+def test_paper_quadrature_touching_entries_against_direct_rule():
+    """The library's entries of a few touching pairs against the oracle's
+    Sauter-Erichsen-Schwab sum for exactly that pair (lower index first), so
+    a wrong vertex order or region shows up directly."""
+    from paper_1809_04384_amd import dh2
+    name = "dir512"
+    w = synth.WORKLOADS[name]
+    V, T = synth.make_mesh(w)
+    o = paper_oracle(name)
+    h, _ = build_handle(name, quadrature=dh2.QUAD_PAPER)
+    try:
+        st = o.st
+        seen = {1: 0, 2: 0, 3: 0}
+        for b, (t, s) in enumerate(st.near):
+            N = h.inspect("near", b)
+            rows, cols = st.idx(t), st.idx(s)
+            for r, i in enumerate(rows):
+                for c, j in enumerate(cols):
+                    kind = ses.touching_order(T[i], T[j])[0]
+                    if kind and seen[kind] < 6:
+                        lo, hi = min(i, j), max(i, j)
+                        ref = ses.ses_pair(V, T[lo], T[hi], w.kappa)
+                        assert abs(N[r, c] - ref) <= 1e-12 * abs(ref), (kind, i, j)
+                        seen[kind] += 1
+        assert min(seen.values()) >= 1
+    finally:
+        h.free()
+
+
+def test_paper_quadrature_option_checks():
+    from paper_1809_04384_amd import dh2
+    with pytest.raises(dh2.Dh2Error):
+        build_handle("dir512", quadrature=7)
