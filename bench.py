@@ -52,6 +52,8 @@ def parse():
                          "spectral control)")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the split-BF16x3 form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank form")
+    ap.add_argument("--no-paper-quadrature", action="store_true",
+                    help="skip the build with the paper's quadrature (Sauter-Erichsen-Schwab / Duffy-Gauss)")
     ap.add_argument("--learned-cube", default="cube28k_m6",
                     help="cube workload of the learned-rank family (cube7k_m6, cube28k_m6, cube110k_m6)")
     ap.add_argument("--weights", default="gram", choices=["gram", "householder"],
@@ -310,6 +312,66 @@ def householder_build(w, V, T, Xd, Y64, dh2, torch, results):
     return {"build_s": round(tb, 3), "total_weights_ms": round(st["ms_total_weights"], 1),
             "qr_flops": st["qr_flops"], "rel_diff_vs_timed": diff,
             "rank_mean_row": round(st["rank_mean_row"], 3), "rank_mean_col": round(st["rank_mean_col"], 3)}
+
+
+def paper_quadrature_form(args, w, V, T, X, Xd, Y64, dh2, torch):
+    """The timed build with the paper's quadrature (Section 5: Sauter-Erichsen-
+    Schwab order 5 for touching pairs, Duffy-Gauss order 3 otherwise; the timed
+    steps use the 16-point near rule with the closed-form self term): build
+    time and phases, touching pairs, matvec time, the relative difference of its
+    product from the timed one (the two quadratures), and its errors against
+    the interpolated and the Galerkin matrix of the same quadrature on the
+    sampled rows (oracle with quadrature="paper")."""
+    from oracle.dh2 import OracleDH2
+    nrhs = Xd.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=max(nrhs, 1),
+                   weights=WEIGHTS, quadrature=dh2.QUAD_PAPER)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    st = h.stats()
+    Yd = torch.empty_like(Xd)
+    h.matvec(Xd, Yd)
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.matvec(Xd, Yd)
+    e1.record()
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / reps
+    Y = Yd.cpu().numpy()
+    diff = float(torch.linalg.norm(Yd - Y64) / torch.linalg.norm(Y64))
+    h.free()
+    out = {"build_s": round(tb, 3),
+           "build_phases_ms": {k[3:]: round(st[k], 1) for k in ("ms_near", "ms_interp", "ms_block_weights",
+                                                                "ms_total_weights", "ms_truncation",
+                                                                "ms_projection", "ms_total")},
+           "touching_pairs": st["touching_pairs"], "matvec_ms": round(mv_ms, 3),
+           "rank_mean_row": round(st["rank_mean_row"], 3),
+           "rel_diff_vs_timed_quadrature": diff}
+    log("paper quadrature: build %.2f s (near field %.0f ms, %d touching pairs), matvec %.3f ms, "
+        "product vs timed quadrature %.3e" % (tb, st["ms_near"], st["touching_pairs"], mv_ms, diff))
+    if args.err_sample_leaves > 0:
+        t0 = time.perf_counter()
+        o = OracleDH2(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, lazy=True, quadrature="paper")
+        ost = o.st
+        leaves = [t for t in range(len(ost.first)) if ost.is_leaf(t)]
+        rng = np.random.default_rng(2)
+        pick = [leaves[i] for i in sorted(rng.choice(len(leaves), size=args.err_sample_leaves,
+                                                     replace=False).tolist())]
+        rows, Yi = o.interp_rows(pick, X.T)
+        Yg = o.galerkin_rows(rows) @ X.T
+        Yr = Y[:, rows].T
+        out["rel_err"] = {"sample": "the same %d leaf row clusters as rel_err (%d rows), oracle with the "
+                                    "paper's quadrature, %.1f s" % (len(pick), len(rows), time.perf_counter() - t0),
+                          "vs_interp": float(np.linalg.norm(Yr - Yi) / np.linalg.norm(Yi)),
+                          "vs_galerkin": float(np.linalg.norm(Yr - Yg) / np.linalg.norm(Yg)),
+                          "interp_vs_galerkin": float(np.linalg.norm(Yi - Yg) / np.linalg.norm(Yg))}
+        log("paper quadrature errors on sampled rows: %s" % json.dumps(out["rel_err"]))
+    return out
 
 
 def fp32_form(args, w, V, T, X, Y64, dh2, torch, results, precision=None):
@@ -701,6 +763,9 @@ def main():
     hh = None
     if not args.no_householder_build and args.weights == "gram":
         hh = householder_build(w, V, T, Xd, Y64, dh2, torch, results)
+    paperq = None
+    if not args.no_paper_quadrature:
+        paperq = paper_quadrature_form(args, w, V, T, X, Xd, Y64, dh2, torch)
     fp32 = None
     if not args.no_fp32:
         fp32 = fp32_form(args, w, V, T, X, Y64, dh2, torch, results)
@@ -799,6 +864,7 @@ def main():
         "fp32_form": fp32,
         "bf16x3_form": bf,
         "spectral_form": spec,
+        "paper_quadrature_form": paperq,
         "paper_table3_131k": paper_cfg,
         "batch_form": batch,
         "learned_form": learned,
