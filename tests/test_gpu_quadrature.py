@@ -140,3 +140,62 @@ def test_paper_quadrature_option_checks():
     from paper_1809_04384_amd import dh2
     with pytest.raises(dh2.Dh2Error):
         build_handle("dir512", quadrature=7)
+
+
+def test_paper_quadrature_full_size():
+    """The benchmark's n = 131072 sphere with the paper's quadrature (Gram form,
+    16 right-hand sides): sampled near-field blocks element by element against
+    the oracle's rules (among them diagonal blocks, which hold identical,
+    common-edge and common-vertex pairs), the touching-pair count against the
+    mesh, and the product within the quadrature difference of the default
+    rules' product (the two discretisations differ by about 5e-3 here)."""
+    import torch
+    from paper_1809_04384_amd import dh2
+    from oracle import cquad
+    from oracle.quadrature import triangle_data
+    from oracle.structure import build_structure
+    w = synth.WORKLOADS["sphere131k"]
+    V, T = synth.make_mesh(w)
+    st = build_structure(V, T, w.kappa, w.eta, w.leaf, w.eta1)
+    tri = triangle_data(V, T)
+    # touching ordered pairs of the evaluated (not mirrored) near blocks
+    where = {(t, s) for (t, s) in st.near}
+    n = len(T)
+    pos = np.empty(n, dtype=np.int64)
+    pos[st.perm] = np.arange(n)
+    hp = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=16,
+                    weights=dh2.WEIGHTS_GRAM, quadrature=dh2.QUAD_PAPER)
+    try:
+        stats = hp.stats()
+        say("[gpu] sphere131k paper quadrature: %d touching pairs, near field %.0f ms"
+            % (stats["touching_pairs"], stats["ms_near"]))
+        # each triangle touches itself, ~3 edge and ~9 vertex neighbours; pairs
+        # in mirrored blocks are not counted
+        assert 6 * n < stats["touching_pairs"] < 14 * n
+        rng = np.random.default_rng(5)
+        diag = [b for b, (t, s) in enumerate(st.near) if t == s]
+        other = [b for b, (t, s) in enumerate(st.near) if t != s]
+        picks = sorted(set(rng.choice(diag, 6, replace=False).tolist() + rng.choice(other, 10, replace=False).tolist()))
+        for b in picks:
+            t, s = st.near[b]
+            N = hp.inspect("near", b)
+            ref = cquad.near_block_paper(tri, st.idx(t), st.idx(s), w.kappa)
+            assert np.max(np.abs(N - ref)) <= 1e-12 * np.max(np.abs(ref)), b
+        X = synth.complex_gaussian(n, 16, seed=3)
+        Xd = torch.from_numpy(X).to("cuda:0")
+        Yp = torch.empty_like(Xd)
+        hp.matvec(Xd, Yp)
+        torch.cuda.synchronize()
+    finally:
+        hp.free()
+    hd = dh2.Handle(V, T, w.kappa, w.order, w.eta, w.leaf, w.tol, eta1=w.eta1, max_nrhs=16,
+                    weights=dh2.WEIGHTS_GRAM)
+    try:
+        Yd = torch.empty_like(Xd)
+        hd.matvec(Xd, Yd)
+        torch.cuda.synchronize()
+        d = float(torch.linalg.norm(Yp - Yd) / torch.linalg.norm(Yd))
+        say("[gpu] sphere131k paper vs default quadrature: product difference %.3e" % d)
+        assert 1e-6 < d < 2e-2
+    finally:
+        hd.free()
