@@ -546,11 +546,14 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, i
 // waves in flight to hide the evaluation's latency when M is small); NW waves
 // per workgroup hold 4 MT / NW sub-tiles each, registers sized for WPE waves
 // per SIMD (128-row chunks: eight waves of two sub-tiles, four per SIMD).
-template <int MT, int NW, int WPE>
+// RM: the matrix-core type; RM = float is the FP32 form's product (operands
+// rounded to FP32 as they are staged, f32 MFMA, FP32 accumulation, FP64
+// result), the bits of k_gemm<double, float> on a stored S_b.
+template <typename RM, int MT, int NW, int WPE>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, const double* __restrict__ box,
                 const double* __restrict__ dirs) {
-  typedef GMfma<double>::acc_t acc_t;
+  typedef typename GMfma<RM>::acc_t acc_t;
   constexpr int NT = 64 * NW;                 // threads
   constexpr int RC = 32 * MT;                 // rows per chunk
   constexpr int NL = RC * 16 / NT;            // A entries per thread and slice
@@ -565,8 +568,8 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
   const z64* A = (const z64*)d.A;
   z64* C = (z64*)d.C;
   __shared__ double pt[3][kMaxOrder], ps[3][kMaxOrder];
-  __shared__ z64 As[16][RC + 1];
-  __shared__ z64 Bs[16][33];
+  __shared__ cpx<RM> As[16][RC + 1];
+  __shared__ cpx<RM> Bs[16][33];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -609,7 +612,7 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
 #pragma unroll
     for (int u = 0; u < SPW; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) cre[u][e] = cim[u][e] = 0.0;
+      for (int e = 0; e < 4; ++e) cre[u][e] = cim[u][e] = RM(0);
     z64 va[NL], vb[NB];
     auto load_slice = [&](int k0) __attribute__((always_inline)) {
       const int j = k0 + kk;
@@ -647,9 +650,9 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
     load_slice(0);
     for (int k0 = 0; k0 < k; k0 += 16) {
 #pragma unroll
-      for (int u = 0; u < NL; ++u) As[ka0 + (NT / RC) * u][ia] = va[u];
+      for (int u = 0; u < NL; ++u) As[ka0 + (NT / RC) * u][ia] = cpx<RM>{(RM)va[u].x, (RM)va[u].y};
 #pragma unroll
-      for (int h = 0; h < NB; ++h) Bs[kk][jb + (NT / 16) * h] = vb[h];
+      for (int h = 0; h < NB; ++h) Bs[kk][jb + (NT / 16) * h] = cpx<RM>{(RM)vb[h].x, (RM)vb[h].y};
       __syncthreads();
       if (k0 + 16 < k) load_slice(k0 + 16);
 #pragma unroll
@@ -659,12 +662,12 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
         if (ms < rows && !((d.tri & 1) && k0 + 16 <= mc + ms)) {
 #pragma unroll
           for (int ks = 0; ks < 16; ks += 4) {
-            const z64 a = As[ks + lk][ms + li];
-            const z64 b = Bs[ks + lk][sn + li];
-            cre[u] = GMfma<double>::mac(a.x, b.x, cre[u]);
-            cre[u] = GMfma<double>::mac(-a.y, b.y, cre[u]);
-            cim[u] = GMfma<double>::mac(a.x, b.y, cim[u]);
-            cim[u] = GMfma<double>::mac(a.y, b.x, cim[u]);
+            const cpx<RM> a = As[ks + lk][ms + li];
+            const cpx<RM> b = Bs[ks + lk][sn + li];
+            cre[u] = GMfma<RM>::mac(a.x, b.x, cre[u]);
+            cre[u] = GMfma<RM>::mac(-a.y, b.y, cre[u]);
+            cim[u] = GMfma<RM>::mac(a.x, b.y, cim[u]);
+            cim[u] = GMfma<RM>::mac(a.y, b.x, cim[u]);
           }
         }
       }
@@ -675,8 +678,8 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
       const int ms = sm0 + 8 * NW * u;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gi = ms + GMfma<double>::row(lane, e), gj = n0 + sn + li;
-        if (gi < rows && gj < k) C[mc + gi + (int64_t)gj * d.ldc] = al * z64{cre[u][e], cim[u][e]};
+        const int gi = ms + GMfma<RM>::row(lane, e), gj = n0 + sn + li;
+        if (gi < rows && gj < k) C[mc + gi + (int64_t)gj * d.ldc] = al * z64{(double)cre[u][e], (double)cim[u][e]};
       }
     }
   }
@@ -1726,20 +1729,26 @@ void launch_coupling(const CoupDesc* d, int64_t nb, const ChebTab& ct, double ka
 template void launch_coupling<double>(const CoupDesc*, int64_t, const ChebTab&, double,
                                       const double*, const double*, void*, hipStream_t);
 
-void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct, double kappa,
-                          const double* box, const double* dirs, hipStream_t st) {
+template <typename RM>
+static void launch_gemm_coupling_t(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct,
+                                   double kappa, const double* box, const double* dirs, hipStream_t st) {
   const int k = ct.m * ct.m * ct.m;
   const int ntn = (k + 31) / 32;
   for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
     const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
     const dim3 g((unsigned)ntn, (unsigned)cnt);
     if (mt == 1)
-      hipLaunchKernelGGL((k_gemm_coupling<1, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<RM, 1, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
     else if (mt == 2)
-      hipLaunchKernelGGL((k_gemm_coupling<2, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<RM, 2, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
     else
-      hipLaunchKernelGGL((k_gemm_coupling<4, 8, 4>), g, dim3(512), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<RM, 4, 8, 4>), g, dim3(512), 0, st, d + i0, ct, kappa, box, dirs);
   }
+}
+void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct, double kappa,
+                          const double* box, const double* dirs, bool f32, hipStream_t st) {
+  if (f32) launch_gemm_coupling_t<float>(d, nitems, mt, ct, kappa, box, dirs, st);
+  else launch_gemm_coupling_t<double>(d, nitems, mt, ct, kappa, box, dirs, st);
 }
 
 template <typename R>
