@@ -604,10 +604,9 @@ struct Builder {
                             dst, h.stream);
     h.check_launch();
   }
-  // Products with S_b evaluated inside them (k_gemm_coupling): FP64 handles
-  // and the FP32 form (FP32 matrix cores, as its other products); the BF16x3
-  // form keeps its split product kernel on stored S_b.
-  bool fuse_couplings() const { return h.precision == DH2_FP64 || h.precision == DH2_FP32; }
+  // Products with S_b evaluated inside them (k_gemm_coupling), in each form's
+  // own product arithmetic (FP64, FP32 or split-BF16x3 matrix cores).
+  bool fuse_couplings() const { return true; }
   CoupGemmDesc coup_desc(int64_t b, const C64* A, int lda, int M, int conj, int tri, C64* C, int ldc,
                          double alpha) {
     const AdmBlock& ab = p.adm[b];
@@ -639,7 +638,7 @@ struct Builder {
       if (grp[gi].empty()) continue;
       h.stats.gemm_launches += (int64_t)((grp[gi].size() + 65534) / 65535);
       launch_gemm_coupling(upload_tmp(grp[gi], tmp), (int64_t)grp[gi].size(), 1 << gi, ct, p.kappa, h.box_d,
-                           h.dirs_d, h.precision == DH2_FP32, h.stream);
+                           h.dirs_d, h.precision == DH2_FP32 ? 1 : (h.precision == DH2_BF16X3 ? 2 : 0), h.stream);
     }
     h.check_launch();
   }

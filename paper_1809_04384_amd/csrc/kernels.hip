@@ -813,6 +813,156 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const GemmDesc* __restrict_
   }
 }
 
+// The split-BF16x3 form of k_gemm_coupling: the same chunks, slices and
+// evaluation of S_b, the operands split into bf16 hi and lo parts as they are
+// staged (the split of k_gemm_bf16x3, so the bits of k_gemm_bf16x3 on a stored
+// S_b), twelve 16x16x16 bf16 MFMAs per sub-tile and slice.
+template <int MT, int NW, int WPE>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_gemm_coupling_bf16x3(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa,
+                       const double* __restrict__ box, const double* __restrict__ dirs) {
+  constexpr int NT = 64 * NW;
+  constexpr int RC = 32 * MT;
+  constexpr int NL = RC * 16 / NT;
+  constexpr int NB = 512 / NT;
+  constexpr int SPW = 4 * MT / NW;
+  static_assert(SPW >= 1 && NL >= 1 && NB >= 1, "shape");
+  const CoupGemmDesc d = dd[blockIdx.y];
+  const int m = ct.m;
+  const int k = m * m * m;
+  const int n0 = blockIdx.x * 32;
+  if (n0 >= k || d.M <= 0) return;
+  const z64* A = (const z64*)d.A;
+  z64* C = (z64*)d.C;
+  __shared__ double pt[3][kMaxOrder], ps[3][kMaxOrder];
+  // [part][row of A | column of op(S)][k]; parts Re hi, Re lo, Im hi, Im lo
+  __shared__ __align__(16) unsigned short As[4][RC][20];
+  __shared__ __align__(16) unsigned short Bs[4][32][20];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int sn = (wave & 1) * 16;
+  const int sm0 = (wave >> 1) * 16;
+  if (tid < 3 * m) {
+    const int a = tid / m, j = tid % m;
+    const double* bt = box + 6 * d.t;
+    const double* bs = box + 6 * d.s;
+    pt[a][j] = axis_point(ct, bt[a], bt[a + 3], j);
+    ps[a][j] = axis_point(ct, bs[a], bs[a + 3], j);
+  }
+  __syncthreads();
+  const double c[3] = {dirs[3 * d.dir], dirs[3 * d.dir + 1], dirs[3 * d.dir + 2]};
+  const int kk = tid & 15, jb = tid >> 4;
+  const bool cj = d.conj != 0;
+  double nx[NB], ny[NB], nz[NB];
+  bool nok[NB];
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    const int n = min(n0 + jb + (NT / 16) * h, k - 1);
+    const int i0 = n % m, i1 = (n / m) % m, i2 = n / (m * m);
+    nok[h] = n0 + jb + (NT / 16) * h < k;
+    nx[h] = cj ? pt[0][i0] : ps[0][i0];
+    ny[h] = cj ? pt[1][i1] : ps[1][i1];
+    nz[h] = cj ? pt[2][i2] : ps[2][i2];
+  }
+  const int ia = tid & (RC - 1), ka0 = tid / RC;
+  const z64 al{d.alpha, 0.0};
+  for (int mc = 0; mc < d.M; mc += RC) {
+    const int rows = min(RC, d.M - mc);
+    const bool wload = ((wave * 64) & (RC - 1)) < rows;
+    gm_f32x4 rr[SPW], ii[SPW], ri[SPW], ir[SPW];
+#pragma unroll
+    for (int u = 0; u < SPW; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rr[u][e] = ii[u][e] = ri[u][e] = ir[u][e] = 0.f;
+    z64 va[NL], vb[NB];
+    auto load_slice = [&](int k0) __attribute__((always_inline)) {
+      const int j = k0 + kk;
+      const bool kok = j < k;
+      const int jc = min(j, k - 1);
+      const int i0 = jc % m, i1 = (jc / m) % m, i2 = jc / (m * m);
+      const double kx = cj ? ps[0][i0] : pt[0][i0];
+      const double ky = cj ? ps[1][i1] : pt[1][i1];
+      const double kz = cj ? ps[2][i2] : pt[2][i2];
+#pragma unroll
+      for (int h = 0; h < NB; ++h) {
+        const double xt = cj ? nx[h] : kx, yt = cj ? ny[h] : ky, zt = cj ? nz[h] : kz;
+        const double xs = cj ? kx : nx[h], ys = cj ? ky : ny[h], zs = cj ? kz : nz[h];
+        z64 v = coupling_entry(xt, yt, zt, xs, ys, zs, c, kappa);
+        if (cj) v.y = -v.y;
+        vb[h] = (kok && nok[h]) ? v : z64{0.0, 0.0};
+      }
+      if (wload) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+          const int ka = k0 + ka0 + (NT / RC) * u;
+          typedef double v2 __attribute__((ext_vector_type(2)));
+          const v2 w = *(const __attribute__((address_space(1))) v2*)(A + mc + min(ia, rows - 1) +
+                                                                      (int64_t)min(ka, k - 1) * d.lda);
+          const bool ok = ia < rows && ka < k;
+          va[u] = z64{ok ? w.x : 0.0, ok ? w.y : 0.0};
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) va[u] = z64{0.0, 0.0};
+      }
+    };
+    load_slice(0);
+    for (int k0 = 0; k0 < k; k0 += 16) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int ka = ka0 + (NT / RC) * u;
+        split_bf16(va[u].x, As[0][ia][ka], As[1][ia][ka]);
+        split_bf16(va[u].y, As[2][ia][ka], As[3][ia][ka]);
+      }
+#pragma unroll
+      for (int h = 0; h < NB; ++h) {
+        const int jj = jb + (NT / 16) * h;
+        split_bf16(vb[h].x, Bs[0][jj][kk], Bs[1][jj][kk]);
+        split_bf16(vb[h].y, Bs[2][jj][kk], Bs[3][jj][kk]);
+      }
+      __syncthreads();
+      if (k0 + 16 < k) load_slice(k0 + 16);
+      gm_bf16x4 b[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) b[p] = *(const gm_bf16x4*)&Bs[p][sn + li][4 * lk];
+#pragma unroll
+      for (int u = 0; u < SPW; ++u) {
+        const int ms = sm0 + 8 * NW * u;
+        if (ms < rows && !((d.tri & 1) && k0 + 16 <= mc + ms)) {
+          gm_bf16x4 a[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) a[p] = *(const gm_bf16x4*)&As[p][ms + li][4 * lk];
+          rr[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[1], rr[u], 0, 0, 0);
+          rr[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[0], rr[u], 0, 0, 0);
+          rr[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], rr[u], 0, 0, 0);
+          ii[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[3], ii[u], 0, 0, 0);
+          ii[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[3], b[2], ii[u], 0, 0, 0);
+          ii[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[2], ii[u], 0, 0, 0);
+          ri[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[3], ri[u], 0, 0, 0);
+          ri[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[2], ri[u], 0, 0, 0);
+          ri[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[2], ri[u], 0, 0, 0);
+          ir[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[1], ir[u], 0, 0, 0);
+          ir[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[3], b[0], ir[u], 0, 0, 0);
+          ir[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[0], ir[u], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) {
+      const int ms = sm0 + 8 * NW * u;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = ms + 4 * lk + e, gj = n0 + sn + li;
+        if (gi < rows && gj < k)
+          C[mc + gi + (int64_t)gj * d.ldc] =
+              al * z64{(double)rr[u][e] - (double)ii[u][e], (double)ri[u][e] + (double)ir[u][e]};
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Householder fold (FP64): R <- R factor of [R; P_1; P_2; ...] for an n x n
 // upper triangular R (column-major, leading dimension ldr) and pieces P
@@ -1746,9 +1896,27 @@ static void launch_gemm_coupling_t(const CoupGemmDesc* d, int64_t nitems, int mt
   }
 }
 void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct, double kappa,
-                          const double* box, const double* dirs, bool f32, hipStream_t st) {
-  if (f32) launch_gemm_coupling_t<float>(d, nitems, mt, ct, kappa, box, dirs, st);
-  else launch_gemm_coupling_t<double>(d, nitems, mt, ct, kappa, box, dirs, st);
+                          const double* box, const double* dirs, int form, hipStream_t st) {
+  if (form == 1) {
+    launch_gemm_coupling_t<float>(d, nitems, mt, ct, kappa, box, dirs, st);
+    return;
+  }
+  if (form == 0) {
+    launch_gemm_coupling_t<double>(d, nitems, mt, ct, kappa, box, dirs, st);
+    return;
+  }
+  const int k = ct.m * ct.m * ct.m;
+  const int ntn = (k + 31) / 32;
+  for (int64_t i0 = 0; i0 < nitems; i0 += 65535) {
+    const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
+    const dim3 g((unsigned)ntn, (unsigned)cnt);
+    if (mt == 1)
+      hipLaunchKernelGGL((k_gemm_coupling_bf16x3<1, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+    else if (mt == 2)
+      hipLaunchKernelGGL((k_gemm_coupling_bf16x3<2, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+    else
+      hipLaunchKernelGGL((k_gemm_coupling_bf16x3<4, 8, 4>), g, dim3(512), 0, st, d + i0, ct, kappa, box, dirs);
+  }
 }
 
 template <typename R>

@@ -215,8 +215,9 @@ void launch_coupling(const CoupDesc* d, int64_t nb, const ChebTab& ct, double ka
 
 // C = alpha A S_b (conj 0) or alpha A S_b^H (conj 1) with S_b of block
 // (t, s, dir) evaluated inside the product (k_gemm_coupling); A is M x k,
-// column-major; C is M x k, FP64 data; f32: the products on the FP32 matrix
-// cores (the FP32 form).  mt: rows per chunk / 32 (1, 2 or 4); the
+// column-major; C is M x k, FP64 data; form: the products on the FP64 (0) or
+// FP32 (1) matrix cores or in the split-BF16x3 form (2), as the handle's other
+// products.  mt: rows per chunk / 32 (1, 2 or 4); the
 // caller groups the products by M (M <= 32 mt, or any M for mt = 4).
 struct CoupGemmDesc {
   const void* A;
@@ -230,7 +231,7 @@ struct CoupGemmDesc {
   double alpha;
 };
 void launch_gemm_coupling(const CoupGemmDesc* d, int64_t nitems, int mt, const ChebTab& ct, double kappa,
-                          const double* box, const double* dirs, bool f32, hipStream_t st);
+                          const double* box, const double* dirs, int form, hipStream_t st);
 template <typename R>
 void launch_gemm(const GemmDesc* d, int64_t nitems, int maxM, int maxN, hipStream_t st);
 // The same products on FP64 data with split-BF16x3 MFMA products and FP32 accumulation

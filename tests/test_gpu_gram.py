@@ -231,9 +231,9 @@ def test_couplings_formed_inside_products():
     it: both Gram passes with the Frobenius norm (R_tc S_b, R_sc S_b^H /
     omega_b) and the projection (C_tc S_b).  The spectral norm needs S_b
     itself in the first pass, the Householder form stores it for its block and
-    total weights, and the split-BF16x3 form keeps its own product kernel; the
-    products of every form are checked against the oracle by the tests above.
-    The FP32 form does the same on the FP32 matrix cores.
+    total weights; the products of every form are checked against the oracle
+    by the tests above.  The FP32 and split-BF16x3 forms do the same in their
+    own product arithmetic.
     Counts per admissible block, k = 64 (one 128-row chunk per product)."""
     from paper_1809_04384_amd import dh2
     cases = [
@@ -241,7 +241,7 @@ def test_couplings_formed_inside_products():
         ("gram, spectral, fp64", dict(weights=dh2.WEIGHTS_GRAM, norm=dh2.NORM_SPECTRAL), 3.0, 2.0),
         ("householder, fp64", dict(weights=dh2.WEIGHTS_HOUSEHOLDER), 4.0, 1.0),
         ("gram, fp32", dict(weights=dh2.WEIGHTS_GRAM, precision=dh2.FP32), 3.0, 3.0),
-        ("gram, bf16x3", dict(weights=dh2.WEIGHTS_GRAM, precision=dh2.BF16X3), 3.0, 0.0),
+        ("gram, bf16x3", dict(weights=dh2.WEIGHTS_GRAM, precision=dh2.BF16X3), 3.0, 3.0),
     ]
     for label, kw, gen, inside in cases:
         h, _ = build_handle("sphere2k", **kw)
