@@ -431,11 +431,26 @@ struct GMfma<float> {
 // S: storage type of A, B and C; R: the matrix-core type of the products
 // (S = double, R = float: FP64 data multiplied on the FP32 matrix cores with
 // FP32 accumulation).
+// XCD-aware order of a 2-d grid: workgroup b of the linear order runs on XCD
+// b % 8, so the logical index is remapped to give each XCD a contiguous range
+// of the logical order (the tiles of one product run on one XCD and share its
+// L2).  Returns (x, y) of the logical workgroup.
+__device__ __forceinline__ void xcd_remap(int& x, int& y) {
+  const unsigned gx = gridDim.x, total = gx * gridDim.y;
+  const unsigned b = blockIdx.x + gx * blockIdx.y;
+  const unsigned q = total / 8, r = total % 8, xcd = b % 8;
+  const unsigned l = xcd * q + min(xcd, r) + b / 8;
+  x = (int)(l % gx);
+  y = (int)(l / gx);
+}
+
 template <typename S, typename R>
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ dd, int ntm) {
   typedef typename GMfma<R>::acc_t acc_t;
-  const GemmDesc d = dd[blockIdx.y];
-  const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
+  int bx, by;
+  xcd_remap(bx, by);
+  const GemmDesc d = dd[by];
+  const int tm = bx % ntm, tn = bx / ntm;
   const int m0 = tm * 32, n0 = tn * 32;
   if (m0 >= d.M || n0 >= d.N) return;
   if (d.upper && m0 >= n0 + 32) return;
@@ -560,10 +575,12 @@ k_gemm_coupling(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double kappa, c
   constexpr int NB = 512 / NT;                // B entries per thread and slice
   constexpr int SPW = 4 * MT / NW;            // 16 x 16 sub-tiles per wave
   static_assert(SPW >= 1 && NL >= 1 && NB >= 1, "shape");
-  const CoupGemmDesc d = dd[blockIdx.y];
+  int bx, by;
+  xcd_remap(bx, by);
+  const CoupGemmDesc d = dd[by];
   const int m = ct.m;
   const int k = m * m * m;
-  const int n0 = blockIdx.x * 32;
+  const int n0 = bx * 32;
   if (n0 >= k || d.M <= 0) return;
   const z64* A = (const z64*)d.A;
   z64* C = (z64*)d.C;
@@ -708,8 +725,10 @@ __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigne
 }
 
 __global__ void __launch_bounds__(256) k_gemm_bf16x3(const GemmDesc* __restrict__ dd, int ntm) {
-  const GemmDesc d = dd[blockIdx.y];
-  const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
+  int bx, by;
+  xcd_remap(bx, by);
+  const GemmDesc d = dd[by];
+  const int tm = bx % ntm, tn = bx / ntm;
   const int m0 = tm * 32, n0 = tn * 32;
   if (m0 >= d.M || n0 >= d.N) return;
   const z64* A = (const z64*)d.A;
@@ -827,10 +846,12 @@ k_gemm_coupling_bf16x3(const CoupGemmDesc* __restrict__ dd, ChebTab ct, double k
   constexpr int NB = 512 / NT;
   constexpr int SPW = 4 * MT / NW;
   static_assert(SPW >= 1 && NL >= 1 && NB >= 1, "shape");
-  const CoupGemmDesc d = dd[blockIdx.y];
+  int bx, by;
+  xcd_remap(bx, by);
+  const CoupGemmDesc d = dd[by];
   const int m = ct.m;
   const int k = m * m * m;
-  const int n0 = blockIdx.x * 32;
+  const int n0 = bx * 32;
   if (n0 >= k || d.M <= 0) return;
   const z64* A = (const z64*)d.A;
   z64* C = (z64*)d.C;
