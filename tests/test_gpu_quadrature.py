@@ -199,3 +199,37 @@ def test_paper_quadrature_full_size():
         assert 1e-6 < d < 2e-2
     finally:
         hd.free()
+
+
+def test_paper_quadrature_tiny_meshes():
+    """Edge cases: one triangle (only the identical pair), two triangles sharing
+    an edge, two sharing a vertex, and two apart, each a single leaf (one
+    near block holding every pair); kappa 0 and 5.  The near block against the
+    oracle's rules, 1e-12."""
+    from paper_1809_04384_amd import dh2
+    from oracle import cquad
+    from oracle.quadrature import triangle_data
+    V = np.array([[0, 0, 0], [1, 0, 0], [0.4, 0.9, 0], [1.3, 0.8, 0.2], [-0.9, -0.2, 0.3],
+                  [-0.5, -1.0, 0.1], [3.0, 3.0, 1.0], [3.8, 3.1, 1.0], [3.3, 3.9, 1.2]], dtype=float)
+    meshes = {"single": [[0, 1, 2]], "edge": [[0, 1, 2], [1, 3, 2]], "vertex": [[0, 1, 2], [0, 4, 5]],
+              "apart": [[0, 1, 2], [6, 7, 8]]}
+    for label, T in meshes.items():
+        T = np.array(T)
+        used = np.unique(T)
+        Vm, Tm = V[used], np.searchsorted(used, T)
+        tri = triangle_data(Vm, Tm)
+        idx = np.arange(len(Tm))
+        for kappa in (0.0, 5.0):
+            h = dh2.Handle(Vm, Tm, kappa, 3, 1.0, 64, 1e-6, eta1=10.0, quadrature=dh2.QUAD_PAPER)
+            try:
+                st = h.stats()
+                assert st["n_near"] == 1 and st["n_adm"] == 0, label
+                N = h.inspect("near", 0)
+                ref = cquad.near_block_paper(tri, idx, idx, kappa)
+                # the library's near block is in cluster order; with one leaf of
+                # up to two triangles compare as a set of entries per pair
+                perm = dh2.Plan(Vm, Tm, kappa, 3, 1.0, 64, 10.0).export()["perm"]
+                refp = ref[np.ix_(perm, perm)]
+                assert np.max(np.abs(N - refp)) <= 1e-12 * np.max(np.abs(refp)), (label, kappa)
+            finally:
+                h.free()
