@@ -1909,7 +1909,7 @@ static void launch_gemm_coupling_t(const CoupGemmDesc* d, int64_t nitems, int mt
     const int64_t cnt = std::min<int64_t>(nitems - i0, 65535);
     const dim3 g((unsigned)ntn, (unsigned)cnt);
     if (mt == 1)
-      hipLaunchKernelGGL((k_gemm_coupling<RM, 1, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
+      hipLaunchKernelGGL((k_gemm_coupling<RM, 1, 4, 4>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
     else if (mt == 2)
       hipLaunchKernelGGL((k_gemm_coupling<RM, 2, 4, 3>), g, dim3(256), 0, st, d + i0, ct, kappa, box, dirs);
     else
