@@ -318,7 +318,7 @@ class Batch:
 
 
 def build_many(problems, precision=FP64, max_nrhs=16, eta1=10.0, norm=NORM_FROBENIUS, threads=0,
-               workspace_gb=0.0, weights=WEIGHTS_HOUSEHOLDER, autotune=0):
+               workspace_gb=0.0, weights=WEIGHTS_HOUSEHOLDER, autotune=0, quadrature=QUAD_DEFAULT):
     """Handles for many problems built side by side (dh2_build_many): problems is
     a list of (V, T, kappa, order, eta, leafsize, tol); every handle owns a
     stream of its own."""
@@ -346,6 +346,7 @@ def build_many(problems, precision=FP64, max_nrhs=16, eta1=10.0, norm=NORM_FROBE
     opt.weights = weights
     opt.autotune = autotune
     opt.norm = norm
+    opt.quadrature = quadrature
     out = (ctypes.c_void_p * cnt)()
     _check(lib.dh2_build_many(cnt, geoms, kap, order, eta, leaf, tol, ctypes.byref(opt), threads, out))
     hs = []
