@@ -430,8 +430,8 @@ struct GMfma<float> {
 //   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
 // S: storage type of A, B and C; R: the matrix-core type of the products
 // (S = double, R = float: FP64 data multiplied on the FP32 matrix cores with
-// FP32 accumulation).  Registers are sized for six waves per SIMD (the FP64
-// products: 1336 -> 1270 ms per build at n = 131072 against five).
+// FP32 accumulation).  Registers are sized for seven waves per SIMD (the
+// FP64 products per build at n = 131072: five 1336 ms, six 1270, seven 1245).
 // XCD-aware order of a 2-d grid: workgroup b of the linear order runs on XCD
 // b % 8, so the logical index is remapped to give each XCD a contiguous range
 // of the logical order (the tiles of one product run on one XCD and share its
@@ -446,7 +446,7 @@ __device__ __forceinline__ void xcd_remap(int& x, int& y) {
 }
 
 template <typename S, typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_gemm(const GemmDesc* __restrict__ dd, int ntm) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_gemm(const GemmDesc* __restrict__ dd, int ntm) {
   typedef typename GMfma<R>::acc_t acc_t;
   int bx, by;
   xcd_remap(bx, by);
